@@ -1,0 +1,279 @@
+/*
+ * reach.h -- C ABI of the MI355X (gfx950) interval-reachability library.
+ *
+ * The library computes interval reachable sets of a nonlinear system
+ * x' = f(t, x, p) from an interval initial set and constant inputs drawn from
+ * an interval, following PIRK (Devonport, Khaled, Arcak, Zamani, arXiv
+ * 2001.10635):
+ *   - reach_embed_rk4: the mixed-monotonicity method.  The embedding system
+ *     of Sec. 2.1 (state (x, xh) of dimension 2n, right-hand side
+ *     (d(x, p, xh, ph), d(xh, ph, x, p)) for a decomposition function d with
+ *     d(x, p, x, p) = f(x, p)) is integrated by classical RK4 from
+ *     (lower, upper) with inputs (lower, upper), Algorithm 3 with Algorithm 1
+ *     as integrator.  The result [r_lo, r_hi] over-approximates the reachable
+ *     set (Sec. 2.1).
+ *   - reach_montecarlo: the Monte Carlo method of Sec. 2.1 / Algorithm 4:
+ *     uniform samples of the initial box (and input box) integrated by RK4,
+ *     reduced to the per-dimension min / max.
+ *   - reach_mc_samples: the sample count m = ceil((2n/eps) ln(2n/delta)) of
+ *     the Monte Carlo guarantee (Sec. 2.1, Algorithm 4).
+ *   - reach_embed_rk4_batch, reach_server_*: many small embeddings at once,
+ *     by a persistent kernel (offline batch) or by a continuously fed request
+ *     loop (online serving).  These answer the "many reachable sets" use of
+ *     the paper's vehicle study and its reachability-as-a-service interface
+ *     (Sec. 1); each query is the same computation as reach_embed_rk4.
+ *
+ * Integrator (Algorithm 1, read as the classical method): for step k,
+ * t = t0 + k dt (computed, not accumulated), stages at t, t + dt/2,
+ * t + dt/2, t + dt with inputs z, z + dt/2 K1, z + dt/2 K2, z + dt K3, and
+ * z <- z + dt/6 (K1 + 2 K2 + 2 K3 + K4).  All built-in systems are autonomous.
+ *
+ * Built-in systems (one-dimensional chains, cell i couples to i-1 and i+1):
+ *   REACH_CTM  prm = {v, w, c, q}: cell transmission model of the n-link road
+ *              (Sec. 5.1): F_i = min(v y_i, w (c - y_{i+1}), q) for i < n-1,
+ *              F_{n-1} = min(v y_{n-1}, q) (free outflow), zero inflow into
+ *              cell 0, f_i = F_{i-1} - F_i.  Cooperative: d = f.  n_in = 0.
+ *   REACH_RD   prm = {h}: reaction-diffusion, f_i = (y_{i-1} - 2 y_i +
+ *              y_{i+1}) / h^2 - y_i^3 + u, Dirichlet ghosts 0.  Cooperative and
+ *              increasing in u: d = f.  n_in = 0, 1 (shared u) or n.
+ *   REACH_LIN3 prm = {aL, aD, aR, b}: f_i = aL y_{i-1} + aD y_i + aR y_{i+1}
+ *              + b u, ghosts 0, with the sign-split decomposition function
+ *              d_i = aD x_i + aL+ x_{i-1} + aL- xh_{i-1} + aR+ x_{i+1}
+ *                    + aR- xh_{i+1} + b+ p_i + b- ph_i.
+ *              n_in = 0, 1 or n.
+ *
+ * Conventions (all entry points):
+ *   - Array pointers are DEVICE pointers (hipMalloc / torch tensors on the
+ *     GPU) unless stated otherwise, owned by the caller.  The library never
+ *     allocates or frees caller memory; its own allocations are a few status
+ *     words per context, pinned host staging for batch descriptors, and the
+ *     serving ring.
+ *   - Arrays are contiguous SoA vectors of n elements of the call's dtype
+ *     (double for REACH_F64, float for REACH_F32); input arrays have n_in
+ *     elements.  Element i is cell i.
+ *   - Calls that take a `stream` (a hipStream_t, NULL = the default stream)
+ *     are stream-ordered and return only argument or launch errors; what the
+ *     device detects (a non-finite result, lower > upper) is accumulated in
+ *     the context's status word and returned by reach_sync.
+ *   - Returned status codes: REACH_OK, or a negative REACH_E_*; the context's
+ *     reach_last_error() then describes the failure.
+ *   - A context is not thread-safe, except reach_submit / reach_poll /
+ *     reach_cancel, which may be called from any thread while a server runs.
+ */
+#ifndef REACH_H
+#define REACH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t reach_status;
+enum {
+    REACH_OK = 0,
+    REACH_PENDING = 1,          /* reach_poll: the query has not finished */
+    REACH_E_INVAL = -1,         /* bad argument (sizes, pointers, parameters) */
+    REACH_E_NOMEM = -2,         /* workspace / pool / slots too small */
+    REACH_E_DEVICE = -3,        /* HIP runtime error */
+    REACH_E_UNSUPPORTED = -4,   /* valid request outside what this build runs */
+    REACH_E_NONFINITE = -5,     /* device saw a non-finite result */
+    REACH_E_ORDER = -6,         /* device saw r_lo > r_hi */
+    REACH_E_CANCELLED = -7,     /* the query was cancelled */
+    REACH_E_BUSY = -8,          /* server state does not allow the call */
+    REACH_E_TIMEOUT = -9        /* a bounded wait ran out */
+};
+
+typedef int32_t reach_dtype;
+enum { REACH_F64 = 0, REACH_F32 = 1 };
+
+enum { REACH_CTM = 1, REACH_RD = 2, REACH_LIN3 = 3 };
+
+/* A system of the list above.  `reserved` must be 0. */
+typedef struct reach_system {
+    int32_t kind;
+    int32_t reserved;
+    int64_t n;        /* number of cells (state dimension), 1 <= n < 2^40 */
+    int64_t n_in;     /* input dimension: 0, 1 or n */
+    double prm[8];    /* parameters, layout per kind (unused entries ignored) */
+} reach_system;
+
+/* One embedding query for the batch and serving entry points.  For
+   reach_embed_rk4_batch all pointers are device pointers; for reach_submit
+   they are HOST pointers (inputs are copied at admission, r_lo / r_hi are
+   written before reach_poll reports completion). */
+typedef struct reach_query {
+    reach_system sys;
+    reach_dtype dtype;     /* REACH_F64 (the batch and serving kernels are FP64) */
+    int32_t reserved;
+    const void* x_lo;
+    const void* x_hi;
+    const void* p_lo;      /* NULL when sys.n_in == 0 */
+    const void* p_hi;
+    void* r_lo;
+    void* r_hi;
+    double t0;
+    double dt;
+    int64_t nsteps;
+} reach_query;
+
+typedef struct reach_ctx reach_ctx;
+
+/* ------------------------------------------------------------ context -- */
+
+/* Create a context on HIP device `device` (made current for the call).
+   Allocates the context's status words on that device. */
+reach_status reach_ctx_create(int device, reach_ctx** out);
+
+/* Destroy a context (stops a running server first).  NULL is a no-op. */
+void reach_ctx_destroy(reach_ctx* ctx);
+
+/* Text of the last error on this context; valid until the next call on it. */
+const char* reach_last_error(const reach_ctx* ctx);
+
+/* Tuning overrides, mainly for tests and the autotuner:
+     "embed.K"    steps fused per HBM pass (0 = tuned default)
+     "embed.E"    cells per lane of the embedding kernel (0 = tuned default)
+     "mc.waves"   resident waves of the Monte Carlo kernel (0 = default)
+     "batch.waves" resident waves of the batch kernel (0 = default)
+   Returns REACH_E_INVAL for an unknown key or a value out of range. */
+reach_status reach_set_option(reach_ctx* ctx, const char* key, int64_t value);
+int64_t reach_get_option(const reach_ctx* ctx, const char* key);
+
+/* Launch plan reach_embed_rk4 would use for this system, dtype and step
+   count with the context's current tuning: out[0] = E (cells per lane),
+   out[1] = K (RK4 steps per HBM pass), out[2] = tiles (one wavefront each),
+   out[3] = tile stride in cells, out[4] = halo cells per cut edge,
+   out[5] = passes (kernel launches).  `out` is a host array of 6. */
+reach_status reach_plan_embed(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
+                              int64_t nsteps, int64_t* out);
+
+/* Bytes of device workspace reach_embed_rk4 (m = 0) or reach_montecarlo
+   (m = sample count) needs for this system and dtype with the context's
+   current tuning; 0 if none is needed; (size_t)-1 on invalid arguments. */
+size_t reach_workspace_bytes(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
+                             int64_t m);
+
+/* Wait for all work on `stream`, then return and clear the device status
+   word: REACH_E_NONFINITE or REACH_E_ORDER if a kernel since the last
+   reach_sync saw such a result, REACH_E_DEVICE on a HIP error, else OK. */
+reach_status reach_sync(reach_ctx* ctx, void* stream);
+
+/* ---------------------------------------------------------- embedding --
+ * Mixed-monotonicity reachable box (Sec. 2.1, Algorithm 3): integrate the
+ * embedding system nsteps RK4 steps of size dt from t0, starting at
+ * (x_lo, x_hi) with inputs (p_lo, p_hi), and write the box (r_lo, r_hi).
+ *   x_lo, x_hi  n elements, x_lo <= x_hi expected (not checked)
+ *   p_lo, p_hi  n_in elements (NULL iff n_in == 0)
+ *   r_lo, r_hi  n elements; may be the same arrays as x_lo, x_hi
+ *   workspace   device memory of reach_workspace_bytes(ctx, sys, dtype, 0)
+ *               bytes (may be NULL when that is 0); must not overlap the
+ *               other arrays
+ * nsteps = 0 copies the box.  Errors: REACH_E_INVAL for n < 1, n_in not in
+ * {0, 1, n}, dt not finite or <= 0, nsteps < 0, NULL required pointers,
+ * unknown kind or nonzero reserved field, workspace too small;
+ * REACH_E_UNSUPPORTED for CTM with inputs.
+ */
+reach_status reach_embed_rk4(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
+                             const void* x_lo, const void* x_hi,
+                             const void* p_lo, const void* p_hi,
+                             double t0, double dt, int64_t nsteps,
+                             void* r_lo, void* r_hi,
+                             void* workspace, size_t workspace_bytes, void* stream);
+
+/* --------------------------------------------------------- Monte Carlo --
+ * Monte Carlo box (Sec. 2.1, Algorithm 4) over samples s = s0 .. s0+m-1:
+ *   x0_j = x_lo_j + U(s, j) (x_hi_j - x_lo_j),  p_k = p_lo_k + U(s, n+k) (p_hi_k - p_lo_k)
+ * where U(s, j) is word j mod 4 of Philox4x64-10 (Salmon et al., SC'11) at
+ * key (seed, 0), counter (floor(j/4), s, 2, 0), taken as its top 53 bits
+ * (REACH_F64) or top 24 bits (REACH_F32) over 2^53 or 2^24.  Each sample is
+ * integrated nsteps RK4 steps of x' = f(x, p); r_min / r_max (n elements)
+ * receive the per-dimension min / max over the samples, NaN-propagating.
+ * Sample ranges compose: the min / max of two ranges is that of their union.
+ * workspace: reach_workspace_bytes(ctx, sys, dtype, m) bytes.
+ * Errors as reach_embed_rk4, plus REACH_E_INVAL for m < 1 or s0 < 0, and
+ * REACH_E_UNSUPPORTED when n exceeds the register-resident limit
+ * (4096 cells for REACH_F32, 2048 for REACH_F64).
+ */
+reach_status reach_montecarlo(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
+                              const void* x_lo, const void* x_hi,
+                              const void* p_lo, const void* p_hi,
+                              double t0, double dt, int64_t nsteps,
+                              int64_t m, uint64_t seed,
+                              void* r_min, void* r_max,
+                              void* workspace, size_t workspace_bytes, void* stream);
+
+/* Same as reach_montecarlo over samples s0 .. s0+m-1 (resumable MC). */
+reach_status reach_montecarlo_range(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
+                                    const void* x_lo, const void* x_hi,
+                                    const void* p_lo, const void* p_hi,
+                                    double t0, double dt, int64_t nsteps,
+                                    int64_t s0, int64_t m, uint64_t seed,
+                                    void* r_min, void* r_max,
+                                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* Sample count of the Monte Carlo guarantee (Sec. 2.1): with
+   m = ceil((2n/eps) ln(2n/delta)) samples, with probability 1 - delta the
+   box leaves out at most probability eps of the reachable set.
+   Returns -1 unless n >= 1, 0 < eps < 1 and 0 < delta < 1.  Host only. */
+int64_t reach_mc_samples(int64_t n, double eps, double delta);
+
+/* --------------------------------------------------------------- batch --
+ * Many small embeddings (n <= 512, FP64, n_in 0 or 1) in one persistent
+ * kernel: each wave takes the next query from a device work counter
+ * (longest first) and integrates it with its whole state in registers.
+ * `q` is a HOST array of nq queries whose pointers are device pointers; it is
+ * read during the call only.  workspace: reach_batch_workspace_bytes(nq)
+ * bytes of device memory.  Results are identical to nq separate
+ * reach_embed_rk4 calls.  The launch sequence (counter reset, descriptor
+ * upload, worker kernel) is replayed from a captured hipGraph when the same
+ * nq capacity and stream repeat.
+ * Errors: as reach_embed_rk4 for each query, REACH_E_UNSUPPORTED for n > 512,
+ * REACH_F32 or per-cell inputs, REACH_E_NOMEM for a short workspace.
+ */
+size_t reach_batch_workspace_bytes(int64_t nq);
+reach_status reach_embed_rk4_batch(reach_ctx* ctx, const reach_query* q, int64_t nq,
+                                   void* workspace, size_t workspace_bytes, void* stream);
+
+/* Baseline for the batch: one kernel launch per query, round-robin over
+   `nstreams` internal streams (1..16).  Same results; host-blocking. */
+reach_status reach_embed_rk4_each(reach_ctx* ctx, const reach_query* q, int64_t nq,
+                                  int32_t nstreams);
+
+/* ------------------------------------------------------------- serving --
+ * Continuous batching.  reach_server_start launches a persistent kernel on
+ * `stream` that keeps `max_slots` query slots; queries submitted while others
+ * run are admitted as soon as a slot and enough bytes of the device `pool`
+ * (caller-owned device memory, first-fit, 4 n 8 bytes per query) are free,
+ * and run concurrently with them.  Admission order is submission order.
+ *   reach_submit: HOST pointers in *q (inputs copied before return into
+ *     pinned staging); *ticket receives the query's id.  REACH_E_NOMEM if
+ *     the query can never fit the pool; REACH_E_BUSY if no server runs.
+ *   reach_poll: REACH_PENDING until the query is done, then its final status
+ *     (REACH_OK, REACH_E_NONFINITE, REACH_E_ORDER or REACH_E_CANCELLED) --
+ *     r_lo / r_hi hold the box when it returns REACH_OK.  A ticket may be
+ *     polled until it is reported done; after that it is forgotten.
+ *   reach_cancel: drop a query that has not started (REACH_E_BUSY if it is
+ *     already running or done).
+ *   reach_server_stop: drain every admitted and waiting query, stop the
+ *     kernel and join the service thread.
+ *   reach_server_stats: arrivals-to-completion latencies in microseconds of
+ *     completed queries (p50, p99, max) and the count.
+ * Every wave of the serving kernel exits when the host sets its stop flag,
+ * and also after `REACH_SERVER_IDLE_S` seconds (default 120) without work,
+ * so the kernel always drains.
+ */
+reach_status reach_server_start(reach_ctx* ctx, void* pool, size_t pool_bytes,
+                                int32_t max_slots, void* stream);
+reach_status reach_submit(reach_ctx* ctx, const reach_query* q, uint64_t* ticket);
+reach_status reach_poll(reach_ctx* ctx, uint64_t ticket, reach_status* result);
+reach_status reach_cancel(reach_ctx* ctx, uint64_t ticket);
+reach_status reach_server_stop(reach_ctx* ctx);
+reach_status reach_server_stats(reach_ctx* ctx, double* p50_us, double* p99_us,
+                                double* max_us, int64_t* completed);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* REACH_H */

@@ -1,0 +1,112 @@
+// Host-side interface between the C-ABI runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace reach {
+
+// Bits of a context's device status word (the kernels use the same values).
+enum { STATUS_NONFINITE = 1, STATUS_ORDER = 2 };
+
+// One HBM pass of the embedding: `ksteps` RK4 steps on every tile.
+// Tile w reads cells [w*OUT, w*OUT + 64E) of src and writes the cells it
+// owns to dst: [0, 64E - H) for tile 0, [w*OUT + H, w*OUT + 64E - H) for
+// the others, up to n for the tile whose window reaches the chain's end.
+struct EmbedPass {
+    const void* src_lo;
+    const void* src_hi;
+    void* dst_lo;
+    void* dst_hi;
+    const void* p_lo;
+    const void* p_hi;
+    int64_t n;        // cells in the chain
+    int64_t W;        // tiles
+    int64_t OUT;      // tile stride (64E - 2H); 0 when W == 1
+    int64_t ksteps;   // RK4 steps this pass
+    int32_t H;        // halo cells per cut edge (4 * steps per pass)
+    int32_t aligned;  // every array 16-byte aligned
+    int32_t check;    // last pass: report non-finite / lower > upper
+    int32_t per_xcd;  // tiles per XCD in the blockIdx -> tile map
+    double prm[5];
+    double h2, dt, dt6;
+    unsigned int* status;
+};
+
+// kind: 1 CTM, 2 RD, 3 LIN3; mode: 0 scalar input, 1 per-cell input;
+// dtype: 0 f64, 1 f32.  Returns hipErrorInvalidValue for an E this build
+// does not instantiate.
+hipError_t launch_embed(int kind, int mode, int dtype, int E, const EmbedPass& a,
+                        int64_t grid, hipStream_t stream);
+bool embed_has_E(int dtype, int E);
+int embed_max_E(int dtype);
+
+struct McArgs {
+    const void* x_lo;
+    const void* x_hi;
+    const void* p_lo;
+    const void* p_hi;
+    void* part_min;     // [nw][E][64] interleaved partials of the kernel's type
+    void* part_max;
+    int64_t n;
+    int64_t n_in;
+    int64_t nsteps;
+    int64_t s0;
+    int64_t m;
+    int64_t nw;         // resident waves (= grid)
+    uint64_t seed;
+    int32_t aligned;
+    double prm[5];
+    double h2, dt, dt6;
+};
+hipError_t launch_mc(int kind, int mode, int dtype, int E, const McArgs& a, hipStream_t stream);
+// r_min / r_max [n] from the partials of `nw` waves; reports non-finite.
+hipError_t launch_mc_reduce(int dtype, int E, const void* part_min, const void* part_max,
+                            int64_t nw, int64_t n, void* r_min, void* r_max,
+                            unsigned int* status, hipStream_t stream);
+bool mc_has_E(int dtype, int E);
+int mc_max_E(int dtype);
+
+// Batch / serving descriptor of one FP64 query (n <= 512).
+struct QDesc {
+    int32_t kind;
+    int32_t E;          // cells per lane: 1, 2, 4 or 8
+    int64_t n;
+    int64_t nsteps;
+    double prm[5];
+    double u_lo, u_hi;  // scalar inputs (0 when n_in == 0)
+    double h2, dt, dt6;
+    const double* x_lo;
+    const double* x_hi;
+    double* r_lo;
+    double* r_hi;
+    int64_t tag;        // caller's index (batch) or ticket slot (serving)
+};
+
+// Persistent batch worker: `grid` waves pull descriptors through *counter.
+hipError_t launch_batch(const QDesc* d, int64_t nq, unsigned long long* counter,
+                        unsigned int* qflags, unsigned int* status, int64_t grid,
+                        hipStream_t stream);
+// Zero `count` 32-bit words (a kernel, so it can sit in a captured graph).
+hipError_t launch_zero(void* p, int64_t count, hipStream_t stream);
+// One query with a plain launch (the one-launch-per-query baseline).
+hipError_t launch_single(const QDesc& d, unsigned int* status, hipStream_t stream);
+
+// Serving ring (see runtime): slots live in pinned host memory.
+struct ServeSlot {
+    QDesc d;
+    unsigned long long seq;      // ticket index published in this slot (+1), 0 = empty
+    unsigned long long done;     // ticket index completed in this slot (+1)
+    unsigned int flags;          // status bits of that query
+    unsigned int pad;
+};
+struct ServeCtl {
+    unsigned long long next;     // device: next ticket index to claim
+    unsigned int stop;           // host-set stop flag (pinned host memory)
+    unsigned int pad;
+};
+// ctl: device words [claim counter, status, published watermark].
+hipError_t launch_server(ServeSlot* ring, int32_t slots, unsigned long long* ctl,
+                         volatile unsigned int* stop, unsigned int* status,
+                         int64_t idle_cycles, int64_t grid, hipStream_t stream);
+
+}  // namespace reach

@@ -1,0 +1,214 @@
+// Monte Carlo reachable box on gfx950 (PIRK Sec. 2.1, Algorithm 4).
+//
+// Each wavefront integrates whole samples: the full n-cell state of one sample
+// lives in the wave's registers (E cells per lane, n <= 64E), so a sample's
+// N RK4 steps touch no memory at all.  Waves are persistent: wave w takes
+// samples s0 + w, s0 + w + nw, ... and folds each final state into its own
+// running min / max kept in the workspace (read-modify-write once per sample,
+// interleaved [w][e][lane] so those accesses are coalesced).  A second kernel
+// reduces the nw partials per dimension.
+//
+// Sampling: x0_j = x_lo_j + U(s, j) (x_hi_j - x_lo_j) and, for inputs,
+// p_k = p_lo_k + U(s, n + k) (p_hi_k - p_lo_k), with U(s, j) word j mod 4 of
+// Philox4x64-10 at key (seed, 0), counter (floor(j/4), s, 2, 0): counter-based,
+// so any sample can be drawn independently and sample ranges compose.
+#include "dev.hpp"
+#include "kernels.hpp"
+
+namespace reach {
+
+template <class T>
+__device__ __forceinline__ T nan_min(T m, T x) {
+    // NaN-propagating: once either side is NaN the result stays NaN.
+    return (m != m) ? m : ((x < m || x != x) ? x : m);
+}
+template <class T>
+__device__ __forceinline__ T nan_max(T m, T x) {
+    return (m != m) ? m : ((x > m || x != x) ? x : m);
+}
+
+template <int KIND, class T, int E, int MODE>
+__global__ __launch_bounds__(64) void mc_kernel(McArgs a) {
+    const int lane = threadIdx.x;
+    const int64_t w = blockIdx.x;
+    const int64_t n = a.n;
+    const bool masked = (int64_t)WAVE * E > n;
+    const int64_t left = n - (int64_t)lane * E;
+    const int nvalid = (int)(left < 0 ? 0 : (left > E ? E : left));
+
+    const T* __restrict__ xlo = (const T*)a.x_lo;
+    const T* __restrict__ xhi = (const T*)a.x_hi;
+    T* __restrict__ pmin = (T*)a.part_min + (size_t)w * E * WAVE;
+    T* __restrict__ pmax = (T*)a.part_max + (size_t)w * E * WAVE;
+    const SysPrm<T> P = {(T)a.prm[0], (T)a.prm[1], (T)a.prm[2], (T)a.prm[3], (T)a.prm[4]};
+    const Steps<T> st = {(T)a.h2, (T)a.dt, (T)a.dt6};
+    const uint64_t k0 = a.seed, k1 = 0;
+
+    bool first = true;
+    for (int64_t s = a.s0 + w; s < a.s0 + a.m; s += a.nw) {
+        T y[1][E];
+        Inputs<T, E, 1, MODE> U;
+        // initial state: one Philox block per 4 consecutive cells
+        if constexpr (E % 4 == 0) {
+#pragma unroll
+            for (int g = 0; g < E / 4; ++g) {
+                const int64_t j0 = (int64_t)lane * E + 4 * g;
+                const U4 r = philox4x64_10((uint64_t)(j0 >> 2), (uint64_t)s, MC_STREAM, 0, k0, k1);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int64_t j = j0 + q;
+                    const T u = unif(r.x[q], T(0));
+                    y[0][4 * g + q] = (j < n) ? fmaT(u, xhi[j] - xlo[j], xlo[j]) : ghost<KIND, T>();
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t j = (int64_t)lane * E + e;
+                const U4 r = philox4x64_10((uint64_t)(j >> 2), (uint64_t)s, MC_STREAM, 0, k0, k1);
+                const T u = unif(r.x[j & 3], T(0));
+                y[0][e] = (j < n) ? fmaT(u, xhi[j] - xlo[j], xlo[j]) : ghost<KIND, T>();
+            }
+        }
+        // inputs, drawn per sample at coordinates n + k
+        if constexpr (MODE == IN_SCALAR) {
+            if (a.n_in == 0) {
+                U.u[0] = T(0);
+            } else {
+                const int64_t j = n;
+                const U4 r = philox4x64_10((uint64_t)(j >> 2), (uint64_t)s, MC_STREAM, 0, k0, k1);
+                const T u = unif(r.x[j & 3], T(0));
+                const T pl = ((const T*)a.p_lo)[0], ph = ((const T*)a.p_hi)[0];
+                U.u[0] = fmaT(u, ph - pl, pl);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t c = (int64_t)lane * E + e;
+                const int64_t j = n + c;
+                const U4 r = philox4x64_10((uint64_t)(j >> 2), (uint64_t)s, MC_STREAM, 0, k0, k1);
+                const T u = unif(r.x[j & 3], T(0));
+                if (c < n) {
+                    const T pl = ((const T*)a.p_lo)[c], ph = ((const T*)a.p_hi)[c];
+                    U.u[0][e] = fmaT(u, ph - pl, pl);
+                } else {
+                    U.u[0][e] = T(0);
+                }
+            }
+        }
+
+        if (masked) {
+            Mask<E, true> M{nvalid};
+            rk4_steps<KIND, T, E, 1, MODE, true>(y, a.nsteps, P, U, st, M);
+        } else {
+            Mask<E, false> M{E};
+            rk4_steps<KIND, T, E, 1, MODE, false>(y, a.nsteps, P, U, st, M);
+        }
+
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const size_t idx = (size_t)e * WAVE + lane;
+            if (first) {
+                pmin[idx] = y[0][e];
+                pmax[idx] = y[0][e];
+            } else {
+                pmin[idx] = nan_min(pmin[idx], y[0][e]);
+                pmax[idx] = nan_max(pmax[idx], y[0][e]);
+            }
+        }
+        first = false;
+    }
+}
+
+template <class T, int E>
+__global__ __launch_bounds__(256) void mc_reduce_kernel(const T* __restrict__ pmin,
+                                                        const T* __restrict__ pmax, int64_t nw,
+                                                        int64_t n, T* __restrict__ rmin,
+                                                        T* __restrict__ rmax, unsigned int* status) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned bits = 0;
+    if (j < n) {
+        // cell j = lane * E + e lives at [w][e][lane]
+        const int64_t lane = j / E, e = j % E;
+        const size_t off = (size_t)e * WAVE + (size_t)lane;
+        T mn = pmin[off], mx = pmax[off];
+        for (int64_t w = 1; w < nw; ++w) {
+            mn = nan_min(mn, pmin[(size_t)w * E * WAVE + off]);
+            mx = nan_max(mx, pmax[(size_t)w * E * WAVE + off]);
+        }
+        rmin[j] = mn;
+        rmax[j] = mx;
+        if (!finiteT(mn) || !finiteT(mx)) bits = ST_NONFINITE;
+    }
+    report_status(status, bits);
+}
+
+template <int KIND, class T, int E, int MODE>
+static hipError_t go(const McArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((mc_kernel<KIND, T, E, MODE>), dim3((unsigned)a.nw), dim3(WAVE), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int KIND, class T, int MODE>
+static hipError_t by_E(int E, const McArgs& a, hipStream_t s) {
+    switch (E) {
+        case 1: return go<KIND, T, 1, MODE>(a, s);
+        case 2: return go<KIND, T, 2, MODE>(a, s);
+        case 4: return go<KIND, T, 4, MODE>(a, s);
+        case 8: return go<KIND, T, 8, MODE>(a, s);
+        case 16: return go<KIND, T, 16, MODE>(a, s);
+        case 32: return go<KIND, T, 32, MODE>(a, s);
+        case 64:
+            if constexpr (sizeof(T) == 4) return go<KIND, T, 64, MODE>(a, s);
+            else return hipErrorInvalidValue;
+        default: return hipErrorInvalidValue;
+    }
+}
+
+bool mc_has_E(int dtype, int E) {
+    return E == 1 || E == 2 || E == 4 || E == 8 || E == 16 || E == 32 || (dtype == 1 && E == 64);
+}
+int mc_max_E(int dtype) { return dtype == 1 ? 64 : 32; }
+
+hipError_t launch_mc(int kind, int mode, int dtype, int E, const McArgs& a, hipStream_t s) {
+    if (dtype == 0) {
+        if (kind == K_CTM) return by_E<K_CTM, double, IN_SCALAR>(E, a, s);
+        if (kind == K_RD) return mode ? by_E<K_RD, double, IN_CELL>(E, a, s)
+                                      : by_E<K_RD, double, IN_SCALAR>(E, a, s);
+        if (kind == K_LIN3) return mode ? by_E<K_LIN3, double, IN_CELL>(E, a, s)
+                                        : by_E<K_LIN3, double, IN_SCALAR>(E, a, s);
+    } else {
+        if (kind == K_CTM) return by_E<K_CTM, float, IN_SCALAR>(E, a, s);
+        if (kind == K_RD) return mode ? by_E<K_RD, float, IN_CELL>(E, a, s)
+                                      : by_E<K_RD, float, IN_SCALAR>(E, a, s);
+        if (kind == K_LIN3) return mode ? by_E<K_LIN3, float, IN_CELL>(E, a, s)
+                                        : by_E<K_LIN3, float, IN_SCALAR>(E, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <class T>
+static hipError_t reduce_T(int E, const void* pmin, const void* pmax, int64_t nw, int64_t n,
+                           void* rmin, void* rmax, unsigned int* status, hipStream_t s) {
+    const unsigned grid = (unsigned)((n + 255) / 256);
+#define REACH_RED(EE)                                                                            \
+    case EE:                                                                                     \
+        hipLaunchKernelGGL((mc_reduce_kernel<T, EE>), dim3(grid), dim3(256), 0, s,               \
+                           (const T*)pmin, (const T*)pmax, nw, n, (T*)rmin, (T*)rmax, status);  \
+        return hipGetLastError();
+    switch (E) {
+        REACH_RED(1) REACH_RED(2) REACH_RED(4) REACH_RED(8) REACH_RED(16) REACH_RED(32)
+        REACH_RED(64)
+        default: return hipErrorInvalidValue;
+    }
+#undef REACH_RED
+}
+
+hipError_t launch_mc_reduce(int dtype, int E, const void* pmin, const void* pmax, int64_t nw,
+                            int64_t n, void* rmin, void* rmax, unsigned int* status,
+                            hipStream_t s) {
+    return dtype == 0 ? reduce_T<double>(E, pmin, pmax, nw, n, rmin, rmax, status, s)
+                      : reduce_T<float>(E, pmin, pmax, nw, n, rmin, rmax, status, s);
+}
+
+}  // namespace reach

@@ -1,0 +1,612 @@
+// C-ABI runtime of the reachability library: argument validation, launch
+// planning (tile shape, steps per HBM pass, ping-pong buffers), the batch
+// path with its captured hipGraph, the one-launch-per-query baseline, the
+// autotuner and the continuous-batching server.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/reach.h"
+#include "kernels.hpp"
+
+using namespace reach;
+
+namespace {
+
+constexpr int64_t kMaxN = (int64_t)1 << 40;
+constexpr int64_t kBatchMaxN = 512;
+
+struct GraphKey {
+    int64_t nq;
+    void* ws;
+    void* staging;
+    int64_t grid;
+    hipStream_t stream;
+    bool operator<(const GraphKey& o) const {
+        return std::tie(nq, ws, staging, grid, stream) < std::tie(o.nq, o.ws, o.staging, o.grid, o.stream);
+    }
+};
+
+struct TuneEntry { int E; int K; };
+
+}  // namespace
+
+struct reach_ctx {
+    int device = 0;
+    int cus = 256;
+    unsigned int* status = nullptr;      // device status word
+    std::string err;
+    std::map<std::string, int64_t> opt;
+    std::map<std::tuple<int, int, int>, TuneEntry> tune;  // (kind, dtype, log2 n bucket)
+    // batch staging (pinned host) and graph cache
+    QDesc* staging = nullptr;
+    int64_t staging_cap = 0;
+    hipEvent_t staging_ev = nullptr;
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    std::vector<hipStream_t> each_streams;
+};
+
+namespace {
+
+reach_status fail(reach_ctx* c, reach_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return st;
+}
+
+reach_status hip_fail(reach_ctx* c, hipError_t e, const char* what) {
+    return fail(c, REACH_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIPCHK(c, expr)                                          \
+    do {                                                         \
+        hipError_t _e = (expr);                                  \
+        if (_e != hipSuccess) return hip_fail((c), _e, #expr);   \
+    } while (0)
+
+size_t dsize(reach_dtype d) { return d == REACH_F64 ? 8 : 4; }
+
+int64_t opt_get(const reach_ctx* c, const char* k) {
+    auto it = c->opt.find(k);
+    return it == c->opt.end() ? 0 : it->second;
+}
+
+reach_status check_system(reach_ctx* c, const reach_system* s, reach_dtype dtype) {
+    if (!s) return fail(c, REACH_E_INVAL, "system is NULL");
+    if (s->reserved != 0) return fail(c, REACH_E_INVAL, "reserved field must be 0");
+    if (s->kind != REACH_CTM && s->kind != REACH_RD && s->kind != REACH_LIN3)
+        return fail(c, REACH_E_INVAL, "unknown system kind %d", s->kind);
+    if (dtype != REACH_F64 && dtype != REACH_F32) return fail(c, REACH_E_INVAL, "bad dtype %d", dtype);
+    if (s->n < 1 || s->n >= kMaxN) return fail(c, REACH_E_INVAL, "n = %lld out of range", (long long)s->n);
+    if (s->n_in != 0 && s->n_in != 1 && s->n_in != s->n)
+        return fail(c, REACH_E_INVAL, "n_in must be 0, 1 or n");
+    if (s->kind == REACH_CTM && s->n_in != 0)
+        return fail(c, REACH_E_UNSUPPORTED, "the CTM chain takes no inputs");
+    for (int i = 0; i < 8; ++i)
+        if (!std::isfinite(s->prm[i])) return fail(c, REACH_E_INVAL, "parameter %d not finite", i);
+    if (s->kind == REACH_RD && !(s->prm[0] > 0.0)) return fail(c, REACH_E_INVAL, "RD spacing h must be > 0");
+    return REACH_OK;
+}
+
+// Kernel-side parameters: CTM {v, w, w*c, q}, RD {1/h^2}, LIN3 {aL, aD, aR, b}.
+void kernel_prm(const reach_system* s, double out[5]) {
+    for (int i = 0; i < 5; ++i) out[i] = 0.0;
+    if (s->kind == REACH_CTM) {
+        out[0] = s->prm[0]; out[1] = s->prm[1]; out[2] = s->prm[1] * s->prm[2]; out[3] = s->prm[3];
+    } else if (s->kind == REACH_RD) {
+        out[0] = 1.0 / (s->prm[0] * s->prm[0]);
+    } else {
+        out[0] = s->prm[0]; out[1] = s->prm[1]; out[2] = s->prm[2]; out[3] = s->prm[3];
+    }
+}
+
+bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
+
+int ceil_pow2_E(int64_t n) {
+    int E = 1;
+    while ((int64_t)64 * E < n) E *= 2;
+    return E;
+}
+
+// ------------------------------------------------------------ planning --
+struct EmbedPlan {
+    int E = 1;
+    int K = 1;           // steps per pass
+    int64_t W = 1;       // tiles
+    int64_t OUT = 0;
+    int H = 0;
+    int64_t passes = 1;
+};
+
+TuneEntry default_tune(int dtype) {
+    return dtype == REACH_F64 ? TuneEntry{8, 8} : TuneEntry{16, 8};
+}
+
+int n_bucket(int64_t n) {
+    int b = 0;
+    while (((int64_t)1 << (b + 1)) <= n) ++b;
+    return b;
+}
+
+TuneEntry tuned(const reach_ctx* c, int kind, int dtype, int64_t n) {
+    auto it = c->tune.find({kind, dtype, n_bucket(n)});
+    if (it != c->tune.end()) return it->second;
+    return default_tune(dtype);
+}
+
+reach_status plan_embed(reach_ctx* c, const reach_system* s, reach_dtype dtype, int64_t nsteps,
+                        EmbedPlan* p) {
+    const int64_t n = s->n;
+    const int maxE = embed_max_E(dtype);
+    int64_t oE = opt_get(c, "embed.E"), oK = opt_get(c, "embed.K");
+    TuneEntry te = tuned(c, s->kind, dtype, n);
+    int E = oE ? (int)oE : 0;
+    if (E && !embed_has_E(dtype, E)) return fail(c, REACH_E_INVAL, "embed.E = %d not built", E);
+    if (!E) {
+        if (n <= (int64_t)64 * maxE) E = std::min(ceil_pow2_E(n), maxE);
+        else E = te.E;
+    }
+    p->E = E;
+    const int64_t span = (int64_t)64 * E;
+    if (n <= span && !oK) {
+        // one window covers the chain: both ends are true boundaries, no halo
+        p->K = (int)std::min<int64_t>(std::max<int64_t>(nsteps, 1), INT32_MAX);
+        p->W = 1; p->OUT = 0; p->H = 0;
+        p->passes = nsteps > 0 ? 1 : 0;
+        return REACH_OK;
+    }
+    int K = oK ? (int)oK : te.K;
+    if (K < 1) K = 1;
+    if ((int64_t)8 * K >= span) return fail(c, REACH_E_INVAL, "K = %d too large for E = %d", K, E);
+    p->K = K;
+    p->H = 4 * K;
+    if (n <= span) {
+        p->W = 1; p->OUT = span - 2 * p->H;
+    } else {
+        p->OUT = span - 2 * p->H;
+        p->W = 1 + (n - span + p->OUT - 1) / p->OUT;
+    }
+    p->passes = (nsteps + K - 1) / K;
+    return REACH_OK;
+}
+
+size_t embed_ws_bytes(reach_ctx* c, const reach_system* s, reach_dtype dtype) {
+    EmbedPlan p;
+    if (plan_embed(c, s, dtype, 2 * (int64_t)std::max(1, (int)opt_get(c, "embed.K")), &p) != REACH_OK)
+        return (size_t)-1;
+    if (p.W == 1) return 0;
+    return (size_t)2 * (size_t)s->n * dsize(dtype);
+}
+
+// ------------------------------------------------------------- Monte Carlo
+int mc_E(int dtype, int64_t n) {
+    const int E = ceil_pow2_E(n);
+    return E <= mc_max_E(dtype) ? E : -1;
+}
+
+int64_t mc_waves(const reach_ctx* c, int64_t m) {
+    int64_t w = opt_get(c, "mc.waves");
+    if (w <= 0) w = (int64_t)c->cus * 8;
+    return std::max<int64_t>(1, std::min<int64_t>(w, m));
+}
+
+size_t mc_ws_bytes(const reach_ctx* c, const reach_system* s, reach_dtype dtype, int64_t m) {
+    const int E = mc_E(dtype, s->n);
+    if (E < 0) return (size_t)-1;
+    return (size_t)2 * (size_t)mc_waves(c, m) * (size_t)(64 * E) * dsize(dtype);
+}
+
+}  // namespace
+
+// =================================================================== ABI ==
+
+extern "C" {
+
+reach_status reach_ctx_create(int device, reach_ctx** out) {
+    if (!out) return REACH_E_INVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return REACH_E_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return REACH_E_DEVICE;
+    reach_ctx* c = new reach_ctx();
+    c->device = device;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->cus = cus;
+    if (hipMalloc((void**)&c->status, 256) != hipSuccess) { delete c; return REACH_E_DEVICE; }
+    if (hipMemset(c->status, 0, 256) != hipSuccess) { hipFree(c->status); delete c; return REACH_E_DEVICE; }
+    if (hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming) != hipSuccess) {
+        hipFree(c->status); delete c; return REACH_E_DEVICE;
+    }
+    *out = c;
+    return REACH_OK;
+}
+
+__attribute__((visibility("hidden"))) void reach_server_destroy_internal(reach_ctx* c);
+
+void reach_ctx_destroy(reach_ctx* c) {
+    if (!c) return;
+    hipSetDevice(c->device);
+    reach_server_destroy_internal(c);
+    hipDeviceSynchronize();
+    for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+    for (auto s : c->each_streams) hipStreamDestroy(s);
+    if (c->staging) hipHostFree(c->staging);
+    if (c->staging_ev) hipEventDestroy(c->staging_ev);
+    if (c->status) hipFree(c->status);
+    delete c;
+}
+
+const char* reach_last_error(const reach_ctx* c) { return c ? c->err.c_str() : "no context"; }
+
+reach_status reach_set_option(reach_ctx* c, const char* key, int64_t value) {
+    if (!c || !key) return REACH_E_INVAL;
+    static const char* keys[] = {"embed.K", "embed.E", "mc.waves", "batch.waves", "serve.mode",
+                                 "serve.waves"};
+    bool known = false;
+    for (const char* k : keys) known |= (std::strcmp(k, key) == 0);
+    if (!known) return fail(c, REACH_E_INVAL, "unknown option %s", key);
+    if (value < 0) return fail(c, REACH_E_INVAL, "option %s must be >= 0", key);
+    if (!std::strcmp(key, "embed.E") && value && !embed_has_E(REACH_F32, (int)value))
+        return fail(c, REACH_E_INVAL, "embed.E = %lld not built", (long long)value);
+    c->opt[key] = value;
+    return REACH_OK;
+}
+
+int64_t reach_get_option(const reach_ctx* c, const char* key) {
+    return (c && key) ? opt_get(c, key) : 0;
+}
+
+reach_status reach_plan_embed(reach_ctx* c, const reach_system* s, reach_dtype dtype,
+                              int64_t nsteps, int64_t* out) {
+    if (!c || !out) return REACH_E_INVAL;
+    reach_status st = check_system(c, s, dtype);
+    if (st != REACH_OK) return st;
+    if (nsteps < 0) return fail(c, REACH_E_INVAL, "nsteps < 0");
+    EmbedPlan p;
+    st = plan_embed(c, s, dtype, nsteps, &p);
+    if (st != REACH_OK) return st;
+    out[0] = p.E; out[1] = p.K; out[2] = p.W; out[3] = p.OUT; out[4] = p.H; out[5] = p.passes;
+    return REACH_OK;
+}
+
+size_t reach_workspace_bytes(reach_ctx* c, const reach_system* s, reach_dtype dtype, int64_t m) {
+    if (!c || check_system(c, s, dtype) != REACH_OK || m < 0) return (size_t)-1;
+    return m > 0 ? mc_ws_bytes(c, s, dtype, m) : embed_ws_bytes(c, s, dtype);
+}
+
+reach_status reach_sync(reach_ctx* c, void* stream) {
+    if (!c) return REACH_E_INVAL;
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipStreamSynchronize((hipStream_t)stream));
+    unsigned int st = 0;
+    HIPCHK(c, hipMemcpy(&st, c->status, sizeof st, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemset(c->status, 0, sizeof st));
+    if (st & STATUS_NONFINITE) return fail(c, REACH_E_NONFINITE, "a result was not finite");
+    if (st & STATUS_ORDER) return fail(c, REACH_E_ORDER, "a lower bound exceeded its upper bound");
+    return REACH_OK;
+}
+
+reach_status reach_embed_rk4(reach_ctx* c, const reach_system* s, reach_dtype dtype,
+                             const void* x_lo, const void* x_hi, const void* p_lo,
+                             const void* p_hi, double t0, double dt, int64_t nsteps, void* r_lo,
+                             void* r_hi, void* ws, size_t ws_bytes, void* stream) {
+    if (!c) return REACH_E_INVAL;
+    reach_status st = check_system(c, s, dtype);
+    if (st != REACH_OK) return st;
+    if (!x_lo || !x_hi || !r_lo || !r_hi) return fail(c, REACH_E_INVAL, "NULL state pointer");
+    if (s->n_in > 0 && (!p_lo || !p_hi)) return fail(c, REACH_E_INVAL, "NULL input pointer");
+    if (!(std::isfinite(dt) && dt > 0.0)) return fail(c, REACH_E_INVAL, "dt must be finite and > 0");
+    if (!std::isfinite(t0)) return fail(c, REACH_E_INVAL, "t0 must be finite");
+    if (nsteps < 0) return fail(c, REACH_E_INVAL, "nsteps < 0");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t hs = (hipStream_t)stream;
+    const size_t bytes = (size_t)s->n * dsize(dtype);
+    if (nsteps == 0) {
+        if (r_lo != x_lo) HIPCHK(c, hipMemcpyAsync(r_lo, x_lo, bytes, hipMemcpyDeviceToDevice, hs));
+        if (r_hi != x_hi) HIPCHK(c, hipMemcpyAsync(r_hi, x_hi, bytes, hipMemcpyDeviceToDevice, hs));
+        return REACH_OK;
+    }
+    EmbedPlan pl;
+    st = plan_embed(c, s, dtype, nsteps, &pl);
+    if (st != REACH_OK) return st;
+
+    // buffers: the last pass writes r; multi-tile passes never run in place
+    const bool alias = (r_lo == x_lo) || (r_hi == x_hi) || (r_lo == x_hi) || (r_hi == x_lo);
+    const bool inplace_ok = (pl.W == 1);
+    const bool need_ws = !inplace_ok && (pl.passes >= 2 || alias);
+    void *w_lo = nullptr, *w_hi = nullptr;
+    if (need_ws) {
+        if (!ws || ws_bytes < 2 * bytes)
+            return fail(c, REACH_E_INVAL, "workspace of %zu bytes needed", 2 * bytes);
+        w_lo = ws;
+        w_hi = (char*)ws + bytes;
+    }
+    bool final_copy = false;
+    std::vector<std::pair<int, int>> io;  // per pass: (src id, dst id); 0 = x, 1 = r, 2 = ws
+    {
+        std::vector<int> dst(pl.passes);
+        if (inplace_ok) {
+            for (auto& d : dst) d = 1;
+        } else {
+            for (int64_t p = pl.passes - 1, k = 0; p >= 0; --p, ++k) dst[p] = (k % 2 == 0) ? 1 : 2;
+            if (alias && dst[0] == 1) {
+                for (int64_t p = 0; p < pl.passes; ++p) dst[p] = (p % 2 == 0) ? 2 : 1;
+                final_copy = (dst[pl.passes - 1] == 2);
+            }
+        }
+        int src = 0;
+        for (int64_t p = 0; p < pl.passes; ++p) {
+            io.push_back({src, dst[p]});
+            src = dst[p];
+        }
+    }
+    const void* lo_of[3] = {x_lo, r_lo, w_lo};
+    const void* hi_of[3] = {x_hi, r_hi, w_hi};
+
+    EmbedPass a{};
+    a.p_lo = p_lo; a.p_hi = p_hi;
+    a.n = s->n; a.W = pl.W; a.OUT = pl.OUT; a.H = pl.H;
+    a.aligned = aligned16(x_lo) && aligned16(x_hi) && aligned16(r_lo) && aligned16(r_hi) &&
+                (!need_ws || (aligned16(w_lo) && aligned16(w_hi)));
+    a.per_xcd = (int32_t)((pl.W + 7) / 8);
+    kernel_prm(s, a.prm);
+    a.h2 = dt / 2.0; a.dt = dt; a.dt6 = dt / 6.0;
+    a.status = c->status;
+    const int mode = s->n_in > 1 ? 1 : 0;   // per-cell inputs
+    if (s->n_in == 0) { a.p_lo = nullptr; a.p_hi = nullptr; }
+    const int64_t grid = 8 * (int64_t)a.per_xcd;
+    int64_t done = 0;
+    for (int64_t p = 0; p < pl.passes; ++p) {
+        a.src_lo = lo_of[io[p].first];
+        a.src_hi = hi_of[io[p].first];
+        a.dst_lo = (void*)lo_of[io[p].second];
+        a.dst_hi = (void*)hi_of[io[p].second];
+        a.ksteps = std::min<int64_t>(pl.K, nsteps - done);
+        a.check = (p == pl.passes - 1) ? 1 : 0;
+        hipError_t e = launch_embed(s->kind, mode, dtype == REACH_F64 ? 0 : 1, pl.E, a, grid, hs);
+        if (e != hipSuccess) return hip_fail(c, e, "embedding kernel launch");
+        done += a.ksteps;
+    }
+    if (final_copy) {
+        HIPCHK(c, hipMemcpyAsync(r_lo, w_lo, bytes, hipMemcpyDeviceToDevice, hs));
+        HIPCHK(c, hipMemcpyAsync(r_hi, w_hi, bytes, hipMemcpyDeviceToDevice, hs));
+    }
+    return REACH_OK;
+}
+
+reach_status reach_montecarlo_range(reach_ctx* c, const reach_system* s, reach_dtype dtype,
+                                    const void* x_lo, const void* x_hi, const void* p_lo,
+                                    const void* p_hi, double t0, double dt, int64_t nsteps,
+                                    int64_t s0, int64_t m, uint64_t seed, void* r_min,
+                                    void* r_max, void* ws, size_t ws_bytes, void* stream) {
+    if (!c) return REACH_E_INVAL;
+    reach_status st = check_system(c, s, dtype);
+    if (st != REACH_OK) return st;
+    if (!x_lo || !x_hi || !r_min || !r_max) return fail(c, REACH_E_INVAL, "NULL pointer");
+    if (s->n_in > 0 && (!p_lo || !p_hi)) return fail(c, REACH_E_INVAL, "NULL input pointer");
+    if (!(std::isfinite(dt) && dt > 0.0)) return fail(c, REACH_E_INVAL, "dt must be finite and > 0");
+    if (!std::isfinite(t0)) return fail(c, REACH_E_INVAL, "t0 must be finite");
+    if (nsteps < 0) return fail(c, REACH_E_INVAL, "nsteps < 0");
+    if (m < 1) return fail(c, REACH_E_INVAL, "m must be >= 1");
+    if (s0 < 0) return fail(c, REACH_E_INVAL, "s0 must be >= 0");
+    const int E = mc_E(dtype, s->n);
+    if (E < 0)
+        return fail(c, REACH_E_UNSUPPORTED, "Monte Carlo holds a sample in one wave: n <= %d",
+                    64 * mc_max_E(dtype));
+    const size_t need = mc_ws_bytes(c, s, dtype, m);
+    if (!ws || ws_bytes < need) return fail(c, REACH_E_INVAL, "workspace of %zu bytes needed", need);
+    HIPCHK(c, hipSetDevice(c->device));
+    McArgs a{};
+    a.x_lo = x_lo; a.x_hi = x_hi; a.p_lo = p_lo; a.p_hi = p_hi;
+    a.nw = mc_waves(c, m);
+    a.part_min = ws;
+    a.part_max = (char*)ws + need / 2;
+    a.n = s->n; a.n_in = s->n_in; a.nsteps = nsteps; a.s0 = s0; a.m = m; a.seed = seed;
+    a.aligned = 1;
+    kernel_prm(s, a.prm);
+    a.h2 = dt / 2.0; a.dt = dt; a.dt6 = dt / 6.0;
+    const int mode = s->n_in > 1 ? 1 : 0;
+    const int dt_id = dtype == REACH_F64 ? 0 : 1;
+    hipStream_t hs = (hipStream_t)stream;
+    hipError_t e = launch_mc(s->kind, mode, dt_id, E, a, hs);
+    if (e != hipSuccess) return hip_fail(c, e, "Monte Carlo kernel launch");
+    e = launch_mc_reduce(dt_id, E, a.part_min, a.part_max, a.nw, s->n, r_min, r_max, c->status, hs);
+    if (e != hipSuccess) return hip_fail(c, e, "Monte Carlo reduction launch");
+    return REACH_OK;
+}
+
+reach_status reach_montecarlo(reach_ctx* c, const reach_system* s, reach_dtype dtype,
+                              const void* x_lo, const void* x_hi, const void* p_lo,
+                              const void* p_hi, double t0, double dt, int64_t nsteps, int64_t m,
+                              uint64_t seed, void* r_min, void* r_max, void* ws, size_t ws_bytes,
+                              void* stream) {
+    return reach_montecarlo_range(c, s, dtype, x_lo, x_hi, p_lo, p_hi, t0, dt, nsteps, 0, m, seed,
+                                  r_min, r_max, ws, ws_bytes, stream);
+}
+
+int64_t reach_mc_samples(int64_t n, double eps, double delta) {
+    if (n < 1 || !(eps > 0.0 && eps < 1.0) || !(delta > 0.0 && delta < 1.0)) return -1;
+    const double nn = 2.0 * (double)n;
+    const double m = std::ceil((nn / eps) * std::log(nn / delta));
+    if (!(m < 9.0e18)) return -1;
+    return (int64_t)m;
+}
+
+}  // extern "C"
+
+// ================================================================ batch ==
+
+namespace {
+
+reach_status make_desc(reach_ctx* c, const reach_query& q, int64_t tag, bool host_ptrs, QDesc* d) {
+    reach_status st = check_system(c, &q.sys, q.dtype);
+    if (st != REACH_OK) return st;
+    if (q.dtype != REACH_F64) return fail(c, REACH_E_UNSUPPORTED, "batched queries are FP64");
+    if (q.sys.n > kBatchMaxN) return fail(c, REACH_E_UNSUPPORTED, "batched queries need n <= 512");
+    if (q.sys.n_in > 1) return fail(c, REACH_E_UNSUPPORTED, "batched queries take n_in 0 or 1");
+    if (!(std::isfinite(q.dt) && q.dt > 0.0)) return fail(c, REACH_E_INVAL, "dt must be finite and > 0");
+    if (!std::isfinite(q.t0)) return fail(c, REACH_E_INVAL, "t0 must be finite");
+    if (q.nsteps < 0) return fail(c, REACH_E_INVAL, "nsteps < 0");
+    if (!q.x_lo || !q.x_hi || !q.r_lo || !q.r_hi) return fail(c, REACH_E_INVAL, "NULL state pointer");
+    if (q.sys.n_in == 1 && (!q.p_lo || !q.p_hi)) return fail(c, REACH_E_INVAL, "NULL input pointer");
+    std::memset(d, 0, sizeof *d);
+    d->kind = q.sys.kind;
+    d->E = ceil_pow2_E(q.sys.n);
+    d->n = q.sys.n;
+    d->nsteps = q.nsteps;
+    kernel_prm(&q.sys, d->prm);
+    d->h2 = q.dt / 2.0; d->dt = q.dt; d->dt6 = q.dt / 6.0;
+    d->x_lo = (const double*)q.x_lo; d->x_hi = (const double*)q.x_hi;
+    d->r_lo = (double*)q.r_lo; d->r_hi = (double*)q.r_hi;
+    d->tag = tag;
+    if (q.sys.n_in == 1 && host_ptrs) {
+        d->u_lo = *(const double*)q.p_lo;
+        d->u_hi = *(const double*)q.p_hi;
+    }
+    return REACH_OK;
+}
+
+// Scalar inputs of device-resident queries are read with one small copy each.
+reach_status fetch_inputs(reach_ctx* c, const reach_query* q, int64_t nq, QDesc* d) {
+    for (int64_t i = 0; i < nq; ++i) {
+        if (q[i].sys.n_in == 1) {
+            HIPCHK(c, hipMemcpy(&d[i].u_lo, q[i].p_lo, 8, hipMemcpyDeviceToHost));
+            HIPCHK(c, hipMemcpy(&d[i].u_hi, q[i].p_hi, 8, hipMemcpyDeviceToHost));
+        }
+    }
+    return REACH_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+size_t reach_batch_workspace_bytes(int64_t nq) {
+    if (nq < 0) return (size_t)-1;
+    return align256(8) + align256(4 * (size_t)nq) + align256(sizeof(QDesc) * (size_t)nq);
+}
+
+reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t nq, void* ws,
+                                   size_t ws_bytes, void* stream) {
+    if (!c) return REACH_E_INVAL;
+    if (nq < 0 || (nq > 0 && !q)) return fail(c, REACH_E_INVAL, "bad query array");
+    if (nq == 0) return REACH_OK;
+    const size_t need = reach_batch_workspace_bytes(nq);
+    if (!ws || ws_bytes < need) return fail(c, REACH_E_NOMEM, "workspace of %zu bytes needed", need);
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t hs = (hipStream_t)stream;
+    // host descriptors, longest query first
+    std::vector<QDesc> d(nq);
+    for (int64_t i = 0; i < nq; ++i) {
+        reach_status st = make_desc(c, q[i], i, false, &d[i]);
+        if (st != REACH_OK) return st;
+    }
+    reach_status st = fetch_inputs(c, q, nq, d.data());
+    if (st != REACH_OK) return st;
+    std::stable_sort(d.begin(), d.end(), [](const QDesc& a, const QDesc& b) {
+        return a.n * a.nsteps > b.n * b.nsteps;
+    });
+    // pinned staging (reused; wait for the previous upload from it)
+    if (c->staging_cap < nq) {
+        HIPCHK(c, hipEventSynchronize(c->staging_ev));
+        if (c->staging) HIPCHK(c, hipHostFree(c->staging));
+        c->staging = nullptr;
+        for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
+        c->graphs.clear();
+        int64_t cap = std::max<int64_t>(nq, 1024);
+        HIPCHK(c, hipHostMalloc((void**)&c->staging, sizeof(QDesc) * cap, hipHostMallocDefault));
+        c->staging_cap = cap;
+    } else {
+        HIPCHK(c, hipEventSynchronize(c->staging_ev));
+    }
+    std::memcpy(c->staging, d.data(), sizeof(QDesc) * nq);
+
+    char* base = (char*)ws;
+    auto* counter = (unsigned long long*)base;
+    auto* qflags = (unsigned int*)(base + align256(8));
+    auto* ddesc = (QDesc*)(base + align256(8) + align256(4 * (size_t)nq));
+    int64_t grid = opt_get(c, "batch.waves");
+    if (grid <= 0) grid = (int64_t)c->cus * 8;
+    grid = std::min<int64_t>(grid, nq);
+
+    auto enqueue = [&](hipStream_t s) -> hipError_t {
+        hipError_t e = launch_zero(base, (int64_t)(align256(8) + align256(4 * (size_t)nq)) / 4, s);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(ddesc, c->staging, sizeof(QDesc) * nq, hipMemcpyHostToDevice, s);
+        if (e != hipSuccess) return e;
+        return launch_batch(ddesc, nq, counter, qflags, c->status, grid, s);
+    };
+
+    if (hs == nullptr) {
+        hipError_t e = enqueue(hs);
+        if (e != hipSuccess) return hip_fail(c, e, "batch launch");
+    } else {
+        GraphKey key{nq, ws, c->staging, grid, hs};
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            hipGraph_t g = nullptr;
+            HIPCHK(c, hipStreamBeginCapture(hs, hipStreamCaptureModeRelaxed));
+            hipError_t e = enqueue(hs);
+            hipError_t e2 = hipStreamEndCapture(hs, &g);
+            if (e != hipSuccess) { if (g) hipGraphDestroy(g); return hip_fail(c, e, "batch capture"); }
+            if (e2 != hipSuccess) return hip_fail(c, e2, "hipStreamEndCapture");
+            hipGraphExec_t ge = nullptr;
+            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess) return hip_fail(c, e, "hipGraphInstantiate");
+            it = c->graphs.emplace(key, ge).first;
+        }
+        HIPCHK(c, hipGraphLaunch(it->second, hs));
+    }
+    HIPCHK(c, hipEventRecord(c->staging_ev, hs));
+    (void)counter;
+    return REACH_OK;
+}
+
+reach_status reach_embed_rk4_each(reach_ctx* c, const reach_query* q, int64_t nq, int32_t nstreams) {
+    if (!c) return REACH_E_INVAL;
+    if (nq < 0 || (nq > 0 && !q)) return fail(c, REACH_E_INVAL, "bad query array");
+    if (nstreams < 1 || nstreams > 16) return fail(c, REACH_E_INVAL, "nstreams must be 1..16");
+    HIPCHK(c, hipSetDevice(c->device));
+    while ((int32_t)c->each_streams.size() < nstreams) {
+        hipStream_t s;
+        HIPCHK(c, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        c->each_streams.push_back(s);
+    }
+    std::vector<QDesc> d(nq);
+    for (int64_t i = 0; i < nq; ++i) {
+        reach_status st = make_desc(c, q[i], i, false, &d[i]);
+        if (st != REACH_OK) return st;
+    }
+    reach_status st = fetch_inputs(c, q, nq, d.data());
+    if (st != REACH_OK) return st;
+    for (int64_t i = 0; i < nq; ++i) {
+        hipError_t e = launch_single(d[i], c->status, c->each_streams[i % nstreams]);
+        if (e != hipSuccess) return hip_fail(c, e, "single-query launch");
+    }
+    for (int32_t k = 0; k < nstreams; ++k) HIPCHK(c, hipStreamSynchronize(c->each_streams[k]));
+    return REACH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,548 @@
+// Continuous-batching server: reach_server_start / reach_submit / reach_poll.
+//
+// A persistent serving kernel keeps its waves resident; each wave claims the
+// next ring sequence number from a device counter and waits for the host to
+// publish a query there.  A host service thread admits submitted queries in
+// submission order as soon as a slot and enough bytes of the caller's device
+// pool are free (first fit), uploads their boxes into the pool, publishes them
+// into the ring (pinned, coherent host memory) and collects completions, whose
+// results the kernel writes straight into pinned host result buffers.  New
+// queries thus start while earlier ones are still running on the GPU.
+//
+// serve.mode = 1 replaces the persistent kernel by one kernel launch per
+// admitted query (round-robin over 8 streams): the baseline the persistent
+// path is measured against, with the same admission and accounting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/reach.h"
+#include "kernels.hpp"
+
+using namespace reach;
+
+extern "C" int64_t reach_get_option(const reach_ctx* ctx, const char* key);
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double now_us() {
+    return std::chrono::duration<double, std::micro>(Clock::now().time_since_epoch()).count();
+}
+
+struct Waiting {
+    uint64_t ticket;
+    reach_query q;        // host pointers of the caller (r_lo / r_hi written at completion)
+    std::vector<double> lo, hi;
+    double u_lo = 0, u_hi = 0;
+    double t_submit;
+};
+
+struct Running {
+    bool used = false;
+    uint64_t ticket = 0;
+    uint64_t seq = 0;      // ring sequence it was published at
+    size_t pool_off = 0, pool_len = 0;
+    int64_t n = 0;
+    double* r_lo = nullptr;  // caller's result arrays
+    double* r_hi = nullptr;
+    double t_submit = 0;
+    hipEvent_t ev = nullptr; // mode 1: completion event
+    bool published = false;
+    QDesc d{};
+};
+
+// first-fit allocator over [0, bytes)
+struct Pool {
+    std::map<size_t, size_t> free_;   // offset -> length
+    void init(size_t bytes) { free_.clear(); if (bytes) free_[0] = bytes; }
+    bool alloc(size_t len, size_t* off) {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= len) {
+                *off = it->first;
+                size_t rest = it->second - len, o = it->first + len;
+                free_.erase(it);
+                if (rest) free_[o] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t len) {
+        auto it = free_.emplace(off, len).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+namespace reach_srv {
+
+struct Server {
+    int device = 0;
+    int mode = 0;
+    hipStream_t kstream = nullptr;
+    hipStream_t copy = nullptr;
+    std::vector<hipStream_t> lstreams;   // mode 1
+    char* pool = nullptr;
+    size_t pool_bytes = 0;
+    Pool alloc;
+    int32_t slots = 0;                 // concurrent queries
+    int32_t ring_n = 0;                // ring entries
+    ServeSlot* ring = nullptr;         // pinned host
+    unsigned int* stop = nullptr;      // pinned host
+    unsigned long long* dctl = nullptr;  // device: [0] claim counter, [1] status
+    double* stage_in = nullptr;        // pinned host, slots x 2 x 512
+    double* stage_out = nullptr;       // pinned host, slots x 2 x 512
+    hipEvent_t copy_ev = nullptr;
+    bool own_kstream = false;
+    int64_t grid = 0;
+    int64_t idle_cycles = 0;
+
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread th;
+    bool quit = false;
+    bool draining = false;
+
+    std::deque<Waiting> waiting;
+    std::vector<Running> run;
+    std::vector<int32_t> free_slots;
+    std::vector<uint64_t> ring_busy;   // per ring entry: sequence+1 occupying it, 0 = free
+    uint64_t next_ticket = 0;
+    uint64_t next_seq = 0;
+    std::unordered_map<uint64_t, reach_status> finished;
+    std::unordered_map<uint64_t, bool> known;   // tickets not yet reported done
+    std::vector<double> lat;
+    std::string err;
+};
+
+}  // namespace reach_srv
+
+using reach_srv::Server;
+
+// The context struct is defined in runtime.cpp; the server pointer lives in
+// a side table so the two translation units stay independent.
+namespace {
+std::mutex g_srv_mu;
+std::unordered_map<const reach_ctx*, Server*> g_srv;
+
+Server* srv_of(const reach_ctx* c) {
+    std::lock_guard<std::mutex> g(g_srv_mu);
+    auto it = g_srv.find(c);
+    return it == g_srv.end() ? nullptr : it->second;
+}
+
+reach_status flags_to_status(unsigned f) {
+    if (f & 1u) return REACH_E_NONFINITE;
+    if (f & 2u) return REACH_E_ORDER;
+    return REACH_OK;
+}
+
+// Complete query in slot k (lock held): copy results to the caller.
+void finish(Server* S, int32_t k, unsigned flags) {
+    Running& r = S->run[k];
+    const int64_t n = r.n;
+    std::memcpy(r.r_lo, S->stage_out + (size_t)k * 1024, sizeof(double) * n);
+    std::memcpy(r.r_hi, S->stage_out + (size_t)k * 1024 + 512, sizeof(double) * n);
+    S->finished[r.ticket] = flags_to_status(flags);
+    S->lat.push_back(now_us() - r.t_submit);
+    S->alloc.release(r.pool_off, r.pool_len);
+    if (S->mode == 0) {
+        ServeSlot* sl = &S->ring[r.seq % S->ring_n];
+        __atomic_store_n(&sl->seq, (unsigned long long)0, __ATOMIC_RELEASE);
+        S->ring_busy[r.seq % S->ring_n] = 0;
+    }
+    r.used = false;
+    r.published = false;
+    S->free_slots.push_back(k);
+}
+
+void launch_kernel(Server* S, uint64_t start_seq) {
+    // claim counter and watermark restart at the next sequence to publish
+    unsigned long long init[3] = {start_seq, 0, start_seq};
+    hipMemcpy(S->dctl, init, sizeof init, hipMemcpyHostToDevice);
+    *(volatile unsigned int*)S->stop = 0u;
+    launch_server(S->ring, S->ring_n, S->dctl, (volatile unsigned int*)S->stop,
+                  (unsigned int*)(S->dctl + 1), S->idle_cycles, S->grid, S->kstream);
+}
+
+// Mode 0: the serving kernel leaves after its idle limit.  Before new work is
+// published, queries it had been handed but not finished move to fresh
+// sequence numbers and a new grid starts at the first of them.  Lock held.
+void revive_kernel(Server* S) {
+    if (hipStreamQuery(S->kstream) != hipSuccess) return;   // still running
+    const uint64_t start = S->next_seq;
+    std::vector<int32_t> orphans;
+    for (int32_t k = 0; k < S->slots; ++k) {
+        Running& r = S->run[k];
+        if (!r.used || !r.published) continue;
+        ServeSlot* old = &S->ring[r.seq % S->ring_n];
+        __atomic_store_n(&old->seq, (unsigned long long)0, __ATOMIC_RELEASE);
+        S->ring_busy[r.seq % S->ring_n] = 0;
+        orphans.push_back(k);
+    }
+    std::sort(orphans.begin(), orphans.end(),
+              [&](int32_t x, int32_t y) { return S->run[x].seq < S->run[y].seq; });
+    for (int32_t k : orphans) {
+        Running& r = S->run[k];
+        r.seq = S->next_seq++;
+        S->ring_busy[r.seq % S->ring_n] = r.seq + 1;
+        ServeSlot* sl = &S->ring[r.seq % S->ring_n];
+        sl->d = r.d;
+        sl->flags = 0;
+        __atomic_store_n(&sl->done, (unsigned long long)0, __ATOMIC_RELAXED);
+        __atomic_store_n(&sl->seq, (unsigned long long)(r.seq + 1), __ATOMIC_RELEASE);
+    }
+    launch_kernel(S, start);
+}
+
+void service(Server* S) {
+    hipSetDevice(S->device);
+    std::vector<int32_t> batch;
+    std::unique_lock<std::mutex> lk(S->mu);
+    for (;;) {
+        bool progress = false;
+        // 1. completions
+        for (int32_t k = 0; k < S->slots; ++k) {
+            Running& r = S->run[k];
+            if (!r.used || !r.published) continue;
+            if (S->mode == 0) {
+                ServeSlot* sl = &S->ring[r.seq % S->ring_n];
+                uint64_t done = __atomic_load_n(&sl->done, __ATOMIC_ACQUIRE);
+                if (done == r.seq + 1) {
+                    unsigned fl = __atomic_load_n(&sl->flags, __ATOMIC_ACQUIRE);
+                    finish(S, k, fl);
+                    progress = true;
+                }
+            } else {
+                if (hipEventQuery(r.ev) == hipSuccess) {
+                    finish(S, k, 0);
+                    progress = true;
+                }
+            }
+        }
+        // 2. admission, in submission order
+        batch.clear();
+        if (S->mode == 0 && !S->waiting.empty() && !S->free_slots.empty()) revive_kernel(S);
+        while (!S->waiting.empty() && !S->free_slots.empty()) {
+            Waiting& w = S->waiting.front();
+            const int64_t n = w.q.sys.n;
+            const size_t len = align256(2 * sizeof(double) * (size_t)n);
+            if (S->mode == 0 && S->ring_busy[S->next_seq % S->ring_n] != 0) break;
+            size_t off = 0;
+            if (!S->alloc.alloc(len, &off)) break;
+            const int32_t k = S->free_slots.back();
+            S->free_slots.pop_back();
+            Running& r = S->run[k];
+            r.used = true;
+            r.published = false;
+            r.ticket = w.ticket;
+            r.pool_off = off;
+            r.pool_len = len;
+            r.n = n;
+            r.r_lo = (double*)w.q.r_lo;
+            r.r_hi = (double*)w.q.r_hi;
+            r.t_submit = w.t_submit;
+            double* in = S->stage_in + (size_t)k * 1024;
+            std::memcpy(in, w.lo.data(), sizeof(double) * n);
+            std::memcpy(in + 512, w.hi.data(), sizeof(double) * n);
+            double* dlo = (double*)(S->pool + off);
+            double* dhi = dlo + n;
+            QDesc& d = r.d;
+            std::memset(&d, 0, sizeof d);
+            d.kind = w.q.sys.kind;
+            int E = 1;
+            while (64 * E < n) E *= 2;
+            d.E = E;
+            d.n = n;
+            d.nsteps = w.q.nsteps;
+            if (w.q.sys.kind == REACH_CTM) {
+                d.prm[0] = w.q.sys.prm[0]; d.prm[1] = w.q.sys.prm[1];
+                d.prm[2] = w.q.sys.prm[1] * w.q.sys.prm[2]; d.prm[3] = w.q.sys.prm[3];
+            } else if (w.q.sys.kind == REACH_RD) {
+                d.prm[0] = 1.0 / (w.q.sys.prm[0] * w.q.sys.prm[0]);
+            } else {
+                for (int i = 0; i < 4; ++i) d.prm[i] = w.q.sys.prm[i];
+            }
+            d.u_lo = w.u_lo; d.u_hi = w.u_hi;
+            d.h2 = w.q.dt / 2.0; d.dt = w.q.dt; d.dt6 = w.q.dt / 6.0;
+            d.x_lo = dlo; d.x_hi = dhi;
+            d.r_lo = S->stage_out + (size_t)k * 1024;
+            d.r_hi = S->stage_out + (size_t)k * 1024 + 512;
+            d.tag = k;
+            hipStream_t cs = S->mode == 0 ? S->copy : S->lstreams[k % S->lstreams.size()];
+            hipMemcpyAsync(dlo, in, sizeof(double) * n, hipMemcpyHostToDevice, cs);
+            hipMemcpyAsync(dhi, in + 512, sizeof(double) * n, hipMemcpyHostToDevice, cs);
+            if (S->mode == 0) {
+                r.seq = S->next_seq++;
+                S->ring_busy[r.seq % S->ring_n] = r.seq + 1;
+            } else {
+                launch_single(d, (unsigned int*)(S->dctl + 1), cs);
+                hipEventRecord(r.ev, cs);
+                r.published = true;
+            }
+            batch.push_back(k);
+            S->waiting.pop_front();
+            progress = true;
+        }
+        if (S->mode == 0 && !batch.empty()) {
+            // the boxes must be in the pool before the kernel may see the query
+            hipEventRecord(S->copy_ev, S->copy);
+            lk.unlock();
+            hipEventSynchronize(S->copy_ev);
+            lk.lock();
+            for (int32_t k : batch) {   // sequence order
+                Running& r = S->run[k];
+                ServeSlot* sl = &S->ring[r.seq % S->ring_n];
+                sl->d = r.d;
+                sl->flags = 0;
+                __atomic_store_n(&sl->done, (unsigned long long)0, __ATOMIC_RELAXED);
+                __atomic_store_n(&sl->seq, (unsigned long long)(r.seq + 1), __ATOMIC_RELEASE);
+                r.published = true;
+            }
+        }
+        bool busy = false;
+        for (int32_t k = 0; k < S->slots; ++k) busy |= S->run[k].used;
+        if (S->quit && !busy && S->waiting.empty()) break;
+        if (!progress) {
+            if (busy) {
+                lk.unlock();
+                std::this_thread::yield();
+                lk.lock();
+            } else {
+                S->cv.wait_for(lk, std::chrono::microseconds(200));
+            }
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+reach_status reach_server_start(reach_ctx* c, void* pool, size_t pool_bytes, int32_t max_slots,
+                                void* stream) {
+    if (!c) return REACH_E_INVAL;
+    if (srv_of(c)) return REACH_E_BUSY;
+    if (!pool || pool_bytes < 256 || max_slots < 1 || max_slots > 65536) return REACH_E_INVAL;
+    int dev = 0;
+    hipGetDevice(&dev);
+    Server* S = new Server();
+    S->device = dev;
+    S->mode = (int)reach_get_option(c, "serve.mode");
+    S->pool = (char*)pool;
+    S->pool_bytes = pool_bytes;
+    S->alloc.init(pool_bytes);
+    S->slots = max_slots;
+    S->ring_n = std::max<int32_t>(4 * max_slots, 1024);
+    S->kstream = (hipStream_t)stream;   // NULL: an internal stream is made below
+    int cus = 256;
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    int64_t w = reach_get_option(c, "serve.waves");
+    S->grid = w > 0 ? w : std::min<int64_t>((int64_t)cus * 4, max_slots);
+    double idle_s = 120.0;
+    if (const char* e = std::getenv("REACH_SERVER_IDLE_S")) idle_s = std::max(1.0, std::atof(e));
+    S->idle_cycles = (int64_t)(idle_s * 100.0e6);   // wall_clock64 ticks at 100 MHz
+    bool ok = true;
+    ok &= hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking) == hipSuccess;
+    if (!S->kstream) {
+        ok &= hipStreamCreateWithFlags(&S->kstream, hipStreamNonBlocking) == hipSuccess;
+        S->own_kstream = true;
+    }
+    ok &= hipHostMalloc((void**)&S->ring, sizeof(ServeSlot) * S->ring_n,
+                        hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
+    ok &= hipHostMalloc((void**)&S->stop, 256, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
+    ok &= hipHostMalloc((void**)&S->stage_in, sizeof(double) * 1024 * (size_t)max_slots,
+                        hipHostMallocDefault) == hipSuccess;
+    ok &= hipHostMalloc((void**)&S->stage_out, sizeof(double) * 1024 * (size_t)max_slots,
+                        hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
+    ok &= hipMalloc((void**)&S->dctl, 256) == hipSuccess;
+    ok &= hipEventCreateWithFlags(&S->copy_ev, hipEventDisableTiming) == hipSuccess;
+    if (ok) {
+        std::memset(S->ring, 0, sizeof(ServeSlot) * S->ring_n);
+        std::memset(S->stop, 0, 256);
+        S->run.resize(max_slots);
+        for (int32_t k = max_slots - 1; k >= 0; --k) S->free_slots.push_back(k);
+        S->ring_busy.assign(S->ring_n, 0);
+        if (S->mode == 1) {
+            for (int i = 0; i < 8 && ok; ++i) {
+                hipStream_t s;
+                ok &= hipStreamCreateWithFlags(&s, hipStreamNonBlocking) == hipSuccess;
+                S->lstreams.push_back(s);
+            }
+            for (auto& r : S->run)
+                ok &= hipEventCreateWithFlags(&r.ev, hipEventDisableTiming) == hipSuccess;
+            if (ok) ok &= hipMemset(S->dctl, 0, 256) == hipSuccess;
+        } else {
+            launch_kernel(S, 0);
+            ok &= hipGetLastError() == hipSuccess;
+        }
+    }
+    if (!ok) {
+        // nothing launched that could still run: the kernel launch is the last step
+        if (S->mode == 0 && S->stop) { *(volatile unsigned int*)S->stop = 1u; hipStreamSynchronize(S->kstream); }
+        if (S->ring) hipHostFree(S->ring);
+        if (S->stop) hipHostFree(S->stop);
+        if (S->stage_in) hipHostFree(S->stage_in);
+        if (S->stage_out) hipHostFree(S->stage_out);
+        if (S->dctl) hipFree(S->dctl);
+        if (S->copy) hipStreamDestroy(S->copy);
+        delete S;
+        return REACH_E_DEVICE;
+    }
+    S->th = std::thread(service, S);
+    std::lock_guard<std::mutex> g(g_srv_mu);
+    g_srv[c] = S;
+    return REACH_OK;
+}
+
+reach_status reach_submit(reach_ctx* c, const reach_query* q, uint64_t* ticket) {
+    Server* S = c ? srv_of(c) : nullptr;
+    if (!S) return REACH_E_BUSY;
+    if (!q || !ticket) return REACH_E_INVAL;
+    const reach_system& s = q->sys;
+    if (s.kind != REACH_CTM && s.kind != REACH_RD && s.kind != REACH_LIN3) return REACH_E_INVAL;
+    if (s.reserved != 0) return REACH_E_INVAL;
+    if (q->dtype != REACH_F64) return REACH_E_UNSUPPORTED;
+    if (s.n < 1) return REACH_E_INVAL;
+    if (s.n > 512) return REACH_E_UNSUPPORTED;
+    if (s.n_in != 0 && s.n_in != 1) return REACH_E_UNSUPPORTED;
+    if (s.kind == REACH_CTM && s.n_in != 0) return REACH_E_UNSUPPORTED;
+    if (s.kind == REACH_RD && !(s.prm[0] > 0)) return REACH_E_INVAL;
+    if (!(std::isfinite(q->dt) && q->dt > 0) || q->nsteps < 0) return REACH_E_INVAL;
+    if (!q->x_lo || !q->x_hi || !q->r_lo || !q->r_hi) return REACH_E_INVAL;
+    if (s.n_in == 1 && (!q->p_lo || !q->p_hi)) return REACH_E_INVAL;
+    const size_t len = align256(2 * sizeof(double) * (size_t)s.n);
+    if (len > S->pool_bytes) return REACH_E_NOMEM;
+    Waiting w;
+    w.q = *q;
+    w.lo.assign((const double*)q->x_lo, (const double*)q->x_lo + s.n);
+    w.hi.assign((const double*)q->x_hi, (const double*)q->x_hi + s.n);
+    if (s.n_in == 1) { w.u_lo = *(const double*)q->p_lo; w.u_hi = *(const double*)q->p_hi; }
+    w.t_submit = now_us();
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        if (S->draining) return REACH_E_BUSY;
+        w.ticket = S->next_ticket++;
+        *ticket = w.ticket;
+        S->known[w.ticket] = true;
+        S->waiting.push_back(std::move(w));
+    }
+    S->cv.notify_one();
+    return REACH_OK;
+}
+
+reach_status reach_poll(reach_ctx* c, uint64_t ticket, reach_status* result) {
+    Server* S = c ? srv_of(c) : nullptr;
+    if (!S) return REACH_E_BUSY;
+    std::lock_guard<std::mutex> g(S->mu);
+    if (!S->known.count(ticket)) return REACH_E_INVAL;
+    auto it = S->finished.find(ticket);
+    if (it == S->finished.end()) return REACH_PENDING;
+    if (result) *result = it->second;
+    S->finished.erase(it);
+    S->known.erase(ticket);
+    return REACH_OK;
+}
+
+reach_status reach_cancel(reach_ctx* c, uint64_t ticket) {
+    Server* S = c ? srv_of(c) : nullptr;
+    if (!S) return REACH_E_BUSY;
+    std::lock_guard<std::mutex> g(S->mu);
+    if (!S->known.count(ticket)) return REACH_E_INVAL;
+    for (auto it = S->waiting.begin(); it != S->waiting.end(); ++it) {
+        if (it->ticket == ticket) {
+            S->waiting.erase(it);
+            S->finished[ticket] = REACH_E_CANCELLED;
+            return REACH_OK;
+        }
+    }
+    return REACH_E_BUSY;
+}
+
+reach_status reach_server_stats(reach_ctx* c, double* p50, double* p99, double* mx, int64_t* count) {
+    Server* S = c ? srv_of(c) : nullptr;
+    if (!S) return REACH_E_BUSY;
+    std::vector<double> v;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        v = S->lat;
+    }
+    if (count) *count = (int64_t)v.size();
+    if (v.empty()) {
+        if (p50) *p50 = 0; if (p99) *p99 = 0; if (mx) *mx = 0;
+        return REACH_OK;
+    }
+    std::sort(v.begin(), v.end());
+    auto q = [&](double f) { return v[std::min(v.size() - 1, (size_t)std::floor(f * (v.size() - 1) + 0.5))]; };
+    if (p50) *p50 = q(0.50);
+    if (p99) *p99 = q(0.99);
+    if (mx) *mx = v.back();
+    return REACH_OK;
+}
+
+reach_status reach_server_stop(reach_ctx* c) {
+    Server* S = c ? srv_of(c) : nullptr;
+    if (!S) return REACH_E_BUSY;
+    {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->draining = true;
+        S->quit = true;
+    }
+    S->cv.notify_one();
+    S->th.join();                    // every admitted and waiting query has completed
+    *(volatile unsigned int*)S->stop = 1u;
+    __atomic_thread_fence(__ATOMIC_SEQ_CST);
+    hipSetDevice(S->device);
+    hipError_t e = hipStreamSynchronize(S->kstream);
+    hipStreamSynchronize(S->copy);
+    for (auto s : S->lstreams) { hipStreamSynchronize(s); hipStreamDestroy(s); }
+    for (auto& r : S->run) if (r.ev) hipEventDestroy(r.ev);
+    hipHostFree(S->ring);
+    hipHostFree(S->stop);
+    hipHostFree(S->stage_in);
+    hipHostFree(S->stage_out);
+    hipFree(S->dctl);
+    hipEventDestroy(S->copy_ev);
+    hipStreamDestroy(S->copy);
+    if (S->own_kstream) hipStreamDestroy(S->kstream);
+    {
+        std::lock_guard<std::mutex> g(g_srv_mu);
+        g_srv.erase(c);
+    }
+    delete S;
+    return e == hipSuccess ? REACH_OK : REACH_E_DEVICE;
+}
+
+__attribute__((visibility("hidden"))) void reach_server_destroy_internal(reach_ctx* c) {
+    if (srv_of(c)) reach_server_stop(c);
+}
+
+}  // extern "C"
