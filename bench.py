@@ -27,7 +27,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 FP64_PEAK = 78.6e12          # FLOP/s, MI355X FP64 vector (FMA = 2 flops)
-RD_FLOPS_PER_STATE_STEP = 45  # see the design doc: 4 x 8 (RHS) + 3 x 2 (stage inputs) + 5 + 2
+# Algorithmic FP64 operations of one RK4 state-step of the RD chain (an FMA
+# counts 2): four right-hand sides of 8 (two adds, a scaling by 1/h^2, 2*y,
+# y^3 as two products, the input and the reaction term), three stage inputs
+# z + c K of 2, the weighted sum K1 + 2K2 + 2K3 + K4 of 5 and z + dt/6 * sum of 2.
+RD_FLOPS_PER_STATE_STEP = 45
 
 
 def log(msg):
@@ -71,6 +75,113 @@ def cpu_baseline(p, steps: int):
                       f"{p.nsteps} RK4 steps (same box, inputs and dt)"}
 
 
+def query_mix(rc, R, torch, workloads, nq):
+    """A Poisson stream of nq CTM / RD queries at 5e4/s, n log-uniform
+    in [4, 512], 10-1000 RK4 steps, FP64.  Offline: one persistent-kernel batch
+    vs one launch per query.  Online: served with the persistent kernel vs
+    one launch per query, p50 / p99 from arrival to result on the host."""
+    p4 = workloads.serve_mix_f64()
+    qs = workloads.query_stream(nq, p4.extra["rate"], seed=p4.seed)
+    ns = np.array([q.problem.n for q in qs])
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    tot = int(offs[-1])
+    h_lo = np.empty(tot)
+    h_hi = np.empty(tot)
+    u_lo = np.zeros(nq)
+    u_hi = np.zeros(nq)
+    for i, q in enumerate(qs):
+        pr = q.problem
+        pr.box(out=(h_lo[offs[i]:offs[i + 1]], h_hi[offs[i]:offs[i + 1]]))
+        if pr.n_in:
+            u_lo[i], u_hi[i] = pr.p_lo[0], pr.p_hi[0]
+    state_steps = float(np.sum(2.0 * ns * np.array([q.problem.nsteps for q in qs])))
+    log(f"query mix: {nq} queries, {tot} cells, {state_steps:.3e} state-steps")
+    dev = torch.device("cuda", 0)
+    d_lo = torch.from_numpy(h_lo).to(dev)
+    d_hi = torch.from_numpy(h_hi).to(dev)
+    d_u = torch.from_numpy(np.stack([u_lo, u_hi], 1).reshape(-1)).to(dev)
+    r_lo = torch.empty_like(d_lo)
+    r_hi = torch.empty_like(d_hi)
+
+    def qstruct(i, base_lo, base_hi, out_lo, out_hi, ulo, uhi, el=8):
+        pr = qs[i].problem
+        return R.make_query(pr.kind, pr.n, pr.prm, R.REACH_F64, base_lo + el * offs[i],
+                            base_hi + el * offs[i], out_lo + el * offs[i], out_hi + el * offs[i],
+                            pr.dt, pr.nsteps, (ulo(i) if pr.n_in else None),
+                            (uhi(i) if pr.n_in else None), n_in=pr.n_in)
+
+    dq = R.query_array([qstruct(i, d_lo.data_ptr(), d_hi.data_ptr(), r_lo.data_ptr(),
+                                r_hi.data_ptr(), lambda i: d_u.data_ptr() + 16 * i,
+                                lambda i: d_u.data_ptr() + 16 * i + 8) for i in range(nq)])
+    nbw = R.reach_batch_workspace_bytes(nq)
+    wsb = torch.empty(nbw, dtype=torch.uint8, device=dev)
+    s = torch.cuda.Stream()
+    out = {"workload": f"{nq} queries, Poisson 5e4/s, CTM/RD, n log-uniform [4,512], "
+                       f"10-1000 RK4 steps, FP64", "state_steps": state_steps}
+    with torch.cuda.stream(s):
+        R.reach_embed_rk4_batch(rc.ctx, dq, wsb, nbw, s)        # capture + first replay
+        s.synchronize()
+        t = time.perf_counter()
+        R.reach_embed_rk4_batch(rc.ctx, dq, wsb, nbw, s)
+        s.synchronize()
+        tb = time.perf_counter() - t
+    assert rc.sync(s) == R.REACH_OK
+    ref_lo = r_lo.cpu().numpy()
+    t = time.perf_counter()
+    R.reach_embed_rk4_each(rc.ctx, dq, 8)
+    te = time.perf_counter() - t
+    assert rc.sync() == R.REACH_OK
+    same = bool(np.array_equal(r_lo.cpu().numpy(), ref_lo))
+    out["batch"] = {"queries_per_s": nq / tb, "seconds": round(tb, 4),
+                    "state_steps_per_s": state_steps / tb}
+    out["one_launch_per_query"] = {"queries_per_s": nq / te, "seconds": round(te, 4)}
+    out["batch_speedup"] = round(te / tb, 2)
+    out["batch_equals_per_query"] = same
+    log(f"batch {out['batch']}, per-query launches {out['one_launch_per_query']}")
+    del d_lo, d_hi, r_lo, r_hi, wsb
+
+    # online: host arrays, Poisson arrivals
+    o_lo = np.empty(tot)
+    o_hi = np.empty(tot)
+    hq = [qstruct(i, h_lo.ctypes.data, h_hi.ctypes.data, o_lo.ctypes.data, o_hi.ctypes.data,
+                  lambda i: u_lo.ctypes.data + 8 * i, lambda i: u_hi.ctypes.data + 8 * i)
+          for i in range(nq)]
+    arrivals = np.array([q.arrival for q in qs])
+    pool = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+    for mode, name in ((0, "served_persistent"), (1, "served_launch_per_query")):
+        rc.set_option("serve.mode", mode)
+        o_lo.fill(np.nan)
+        R.reach_server_start(rc.ctx, pool, pool.numel(), 1024)
+        tickets = []
+        t0 = time.perf_counter()
+        i = 0
+        while i < nq:
+            now = time.perf_counter() - t0
+            while i < nq and arrivals[i] <= now:
+                tickets.append(R.reach_submit(rc.ctx, hq[i]))
+                i += 1
+        pending = list(tickets)
+        while pending:
+            nxt = []
+            for tk in pending:
+                st, res = R.reach_poll(rc.ctx, tk)
+                if st == R.REACH_PENDING:
+                    nxt.append(tk)
+                else:
+                    assert res == R.REACH_OK
+            pending = nxt
+        wall = time.perf_counter() - t0
+        stats = R.reach_server_stats(rc.ctx)
+        R.reach_server_stop(rc.ctx)
+        same = bool(np.array_equal(o_lo, ref_lo))
+        out[name] = {"queries_per_s": nq / wall, "p50_us": round(stats["p50_us"], 1),
+                     "p99_us": round(stats["p99_us"], 1), "max_us": round(stats["max_us"], 1),
+                     "equals_batch": same}
+        log(f"{name}: {out[name]}")
+    rc.set_option("serve.mode", 0)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,20 +189,38 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--E", type=int, default=0, help="cells per lane (0 = tuned)")
     ap.add_argument("--K", type=int, default=0, help="RK4 steps per HBM pass (0 = tuned)")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=120)
+    ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-queries", action="store_true")
+    ap.add_argument("--queries", type=int, default=100000)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain device copy of one embedding pass's bytes "
+                         "(the reference kernel for HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the sharded design is described "
-                                   "in DESIGN.md and not launched", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "single-GPU library: runs with --gpus 1 only (the "
+                                   "multi-GPU decomposition is a design, not launched)",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
     import workloads
     import paper_2001_10635_amd as R
 
-    p = workloads.config(1)
+    p = workloads.rd_2p26_f64()
+    if args.copy_probe:
+        # one embedding pass reads 2n doubles and writes 2n doubles; a copy of
+        # 2n doubles moves exactly the same bytes
+        src = torch.ones(2 * p.n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": src.numel() * 8,
+                          "copy_probe_bytes_written": dst.numel() * 8}))
+        return
     log(f"workload {p.name}: n={p.n} N={p.nsteps} dt={p.dt}")
     lo, hi = p.box()
     pl, ph = p.inputs()
@@ -110,11 +239,17 @@ def main():
     if args.K:
         rc.set_option("embed.K", args.K)
     sysd = R.make_system(p.kind, p.n, p.prm, p.n_in)
-    plan = R.reach_plan_embed(rc.ctx, sysd, R.REACH_F64, p.nsteps)
-    log(f"plan {plan}")
-    nbytes = R.reach_workspace_bytes(rc.ctx, sysd, R.REACH_F64, 0)
+    nbytes = 2 * p.n * 8
     ws = rc.workspace(nbytes)
     stream = torch.cuda.current_stream()
+    tuned = None
+    if not (args.E or args.K or args.no_tune):
+        tuned = R.reach_autotune_embed(rc.ctx, sysd, R.REACH_F64, x_lo, x_hi, p_lo, p_hi, p.dt,
+                                       48, r_lo, r_hi, ws, nbytes, stream)
+        log(f"autotuned {tuned}")
+    plan = R.reach_plan_embed(rc.ctx, sysd, R.REACH_F64, p.nsteps)
+    log(f"plan {plan}")
+    assert R.reach_workspace_bytes(rc.ctx, sysd, R.REACH_F64, 0) <= nbytes
 
     def one():
         R.reach_embed_rk4(rc.ctx, sysd, R.REACH_F64, x_lo, x_hi, p_lo, p_hi, 0.0, p.dt,
@@ -184,6 +319,13 @@ def main():
         rc.set_option("embed.K", args.K)
         assert rc.sync(stream) == R.REACH_OK
         log(f"K=1 stream: {stream_k1}")
+    del x_lo, x_hi, p_lo, p_hi, r_lo, r_hi
+    rc._ws = None
+    torch.cuda.empty_cache()
+
+    queries = None
+    if not args.no_queries:
+        queries = query_mix(rc, R, torch, workloads, args.queries)
 
     cpu = None
     if not args.no_cpu:
@@ -208,9 +350,12 @@ def main():
                                "u in [-0.1,0.1], dt=0.1, 1000 RK4 steps (mixed-monotone "
                                "embedding, 2n states)",
                    "n": p.n, "rk4_steps": p.nsteps, "E": plan["E"], "K": plan["K"],
+                   "sides_per_wave": plan["S"],
                    "passes": plan["passes"], "parallelism": "single GPU"},
         "roofline": roof,
         "hbm_stream_k1": stream_k1,
+        "autotune": tuned,
+        "queries": queries,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

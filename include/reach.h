@@ -77,7 +77,7 @@ enum {
     REACH_E_INVAL = -1,         /* bad argument (sizes, pointers, parameters) */
     REACH_E_NOMEM = -2,         /* workspace / pool / slots too small */
     REACH_E_DEVICE = -3,        /* HIP runtime error */
-    REACH_E_UNSUPPORTED = -4,   /* valid request outside what this build runs */
+    REACH_E_UNSUPPORTED = -4,   /* valid request outside what the library runs */
     REACH_E_NONFINITE = -5,     /* device saw a non-finite result */
     REACH_E_ORDER = -6,         /* device saw r_lo > r_hi */
     REACH_E_CANCELLED = -7,     /* the query was cancelled */
@@ -135,6 +135,7 @@ const char* reach_last_error(const reach_ctx* ctx);
 /* Tuning overrides, mainly for tests and the autotuner:
      "embed.K"    steps fused per HBM pass (0 = tuned default)
      "embed.E"    cells per lane of the embedding kernel (0 = tuned default)
+     "embed.S"    sides per wavefront, 1 or 2 (0 = tuned default)
      "mc.waves"   resident waves of the Monte Carlo kernel (0 = default)
      "batch.waves" resident waves of the batch kernel (0 = default)
    Returns REACH_E_INVAL for an unknown key or a value out of range. */
@@ -145,9 +146,27 @@ int64_t reach_get_option(const reach_ctx* ctx, const char* key);
    count with the context's current tuning: out[0] = E (cells per lane),
    out[1] = K (RK4 steps per HBM pass), out[2] = tiles (one wavefront each),
    out[3] = tile stride in cells, out[4] = halo cells per cut edge,
-   out[5] = passes (kernel launches).  `out` is a host array of 6. */
+   out[5] = passes (kernel launches), out[6] = S, sides per wavefront (2: lower
+   and upper together; 1: one side per wavefront, twice the tiles, for the
+   cooperative CTM and RD chains).  `out` is a host array of 7. */
 reach_status reach_plan_embed(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
                               int64_t nsteps, int64_t* out);
+
+/* Autotuner for reach_embed_rk4: times every built tile shape (E cells per
+   lane) and steps-per-pass K on the caller's own buffers (trial_steps RK4
+   steps per trial, one warm-up and two timed calls, HIP events on `stream`),
+   and records the fastest for this system kind, dtype and power-of-two size
+   bucket of n in the context; later calls of that bucket use it.  Arguments
+   are those of reach_embed_rk4 (r_lo / r_hi receive scratch results).
+   best[0] = E, best[1] = K, best[2] = femtoseconds per state-step (2n per
+   step), best[3] = S (sides per wavefront).  `best` is a host array of 4.  With REACH_AUTOTUNE_CACHE set to a file name, results are appended
+   there and read back by reach_ctx_create on the same device architecture. */
+reach_status reach_autotune_embed(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
+                                  const void* x_lo, const void* x_hi,
+                                  const void* p_lo, const void* p_hi, double dt,
+                                  int64_t trial_steps, void* r_lo, void* r_hi,
+                                  void* workspace, size_t workspace_bytes, void* stream,
+                                  int64_t* best);
 
 /* Bytes of device workspace reach_embed_rk4 (m = 0) or reach_montecarlo
    (m = sample count) needs for this system and dtype with the context's

@@ -78,6 +78,8 @@ def lib() -> ctypes.CDLL:
         "reach_get_option": ([vp, ctypes.c_char_p], i64),
         "reach_workspace_bytes": ([vp, sysp, i32, i64], sz),
         "reach_plan_embed": ([vp, sysp, i32, i64, P(i64)], i32),
+        "reach_autotune_embed": ([vp, sysp, i32, vp, vp, vp, vp, d, i64, vp, vp, vp, sz, vp,
+                                  P(i64)], i32),
         "reach_sync": ([vp, vp], i32),
         "reach_embed_rk4": ([vp, sysp, i32, vp, vp, vp, vp, d, d, i64, vp, vp, vp, sz, vp], i32),
         "reach_montecarlo": ([vp, sysp, i32, vp, vp, vp, vp, d, d, i64, i64, u64, vp, vp, vp, sz,
@@ -192,10 +194,23 @@ def reach_workspace_bytes(ctx, sys: reach_system, dtype: int, m: int = 0) -> int
 
 
 def reach_plan_embed(ctx, sys: reach_system, dtype: int, nsteps: int) -> dict:
-    out = (ctypes.c_int64 * 6)()
+    out = (ctypes.c_int64 * 7)()
     _chk(ctx, lib().reach_plan_embed(ctx, ctypes.byref(sys), int(dtype), int(nsteps), out),
          "reach_plan_embed")
-    return dict(E=out[0], K=out[1], tiles=out[2], stride=out[3], halo=out[4], passes=out[5])
+    return dict(E=out[0], K=out[1], tiles=out[2], stride=out[3], halo=out[4], passes=out[5],
+                S=out[6])
+
+
+def reach_autotune_embed(ctx, sys: reach_system, dtype: int, x_lo, x_hi, p_lo, p_hi, dt: float,
+                         trial_steps: int, r_lo, r_hi, workspace=None, workspace_bytes: int = 0,
+                         stream=None) -> dict:
+    out = (ctypes.c_int64 * 4)()
+    _chk(ctx, lib().reach_autotune_embed(ctx, ctypes.byref(sys), int(dtype), _ptr(x_lo),
+                                         _ptr(x_hi), _ptr(p_lo), _ptr(p_hi), float(dt),
+                                         int(trial_steps), _ptr(r_lo), _ptr(r_hi),
+                                         _ptr(workspace), int(workspace_bytes), _stream(stream),
+                                         out), "reach_autotune_embed")
+    return dict(E=out[0], K=out[1], fs_per_state_step=out[2], S=out[3])
 
 
 def reach_sync(ctx, stream=None) -> int:
@@ -241,15 +256,22 @@ def reach_batch_workspace_bytes(nq: int) -> int:
     return int(lib().reach_batch_workspace_bytes(int(nq)))
 
 
+def query_array(queries):
+    """A ctypes array of reach_query (build once, pass to the batch calls)."""
+    if isinstance(queries, ctypes.Array):
+        return queries
+    return (reach_query * len(queries))(*queries)
+
+
 def reach_embed_rk4_batch(ctx, queries, workspace, workspace_bytes: int, stream=None) -> int:
-    arr = (reach_query * len(queries))(*queries)
+    arr = query_array(queries)
     st = lib().reach_embed_rk4_batch(ctx, arr, len(queries), _ptr(workspace),
                                      int(workspace_bytes), _stream(stream))
     return _chk(ctx, st, "reach_embed_rk4_batch")
 
 
 def reach_embed_rk4_each(ctx, queries, nstreams: int = 8) -> int:
-    arr = (reach_query * len(queries))(*queries)
+    arr = query_array(queries)
     st = lib().reach_embed_rk4_each(ctx, arr, len(queries), int(nstreams))
     return _chk(ctx, st, "reach_embed_rk4_each")
 

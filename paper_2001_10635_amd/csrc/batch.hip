@@ -38,14 +38,14 @@ __device__ __noinline__ unsigned run_query_E(const QDesc& d) {
         y[1][e] = (j < n) ? d.x_hi[j] : ghost<KIND, T>();
     }
     Inputs<T, E, 2, IN_SCALAR> U;
-    U.u[0] = d.u_lo;
-    U.u[1] = d.u_hi;
+    U.u[0] = d.p_lo ? *d.p_lo : T(0);
+    U.u[1] = d.p_hi ? *d.p_hi : T(0);
     SysPrm<T> P;
     P.a0 = d.prm[0]; P.a1 = d.prm[1]; P.a2 = d.prm[2]; P.a3 = d.prm[3]; P.a4 = d.prm[4];
     const Steps<T> st = {d.h2, d.dt, d.dt6};
     const int64_t left = n - (int64_t)lane * E;
-    Mask<E, MASKED> M{(int)(left < 0 ? 0 : (left > E ? E : left))};
-    rk4_steps<KIND, T, E, 2, IN_SCALAR, MASKED>(y, d.nsteps, P, U, st, M);
+    Mask<E, MASKED, true> M{(int)(left < 0 ? 0 : (left > E ? E : left))};
+    rk4_steps<KIND, T, E, 2, IN_SCALAR>(y, d.nsteps, P, U, st, M);
     unsigned bits = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {

@@ -6,8 +6,8 @@
 // needs only two cross-lane values per stage (the last cell of lane l-1 and
 // the first cell of lane l+1), moved with DPP whole-wave shifts; every other
 // neighbour is a register of the same lane.  Lanes past either end of the
-// wave receive a fill value, which is how the chain's boundary conditions
-// enter when the window starts at cell 0 or ends at cell n-1.
+// wave receive zero, which is how the chain's boundary conditions enter when
+// the window starts at cell 0 or ends at cell n-1 (see Mask below).
 //
 // The four stages of classical RK4 (Algorithm 1, read as the classical
 // method: stage inputs z + dt/2 K1, z + dt/2 K2, z + dt K3, update
@@ -26,31 +26,26 @@ constexpr int WAVE = 64;
 constexpr int DPP_WAVE_SHL1 = 0x130;  // lane l reads lane l+1
 constexpr int DPP_WAVE_SHR1 = 0x138;  // lane l reads lane l-1
 
-// Lane l receives x of lane l-1; lane 0 receives `fill`.
-__device__ __forceinline__ float from_left(float x, float fill) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(x),
-                                                      DPP_WAVE_SHR1, 0xF, 0xF, false));
+// Lane l receives x of lane l-1; lane 0 receives 0 (DPP bound control: the
+// out-of-wave source reads as zero, so no fill value has to be staged).
+__device__ __forceinline__ float from_left(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), DPP_WAVE_SHR1, 0xF,
+                                                      0xF, true));
 }
-// Lane l receives x of lane l+1; lane 63 receives `fill`.
-__device__ __forceinline__ float from_right(float x, float fill) {
-    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(x),
-                                                      DPP_WAVE_SHL1, 0xF, 0xF, false));
+// Lane l receives x of lane l+1; lane 63 receives 0.
+__device__ __forceinline__ float from_right(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), DPP_WAVE_SHL1, 0xF,
+                                                      0xF, true));
 }
-__device__ __forceinline__ double dpp64(double x, double fill, int which) {
+template <int CTRL>
+__device__ __forceinline__ double dpp64(double x) {
     const uint64_t xi = (uint64_t)__double_as_longlong(x);
-    const uint64_t fi = (uint64_t)__double_as_longlong(fill);
-    int lo, hi;
-    if (which == 0) {
-        lo = __builtin_amdgcn_update_dpp((int)(uint32_t)fi, (int)(uint32_t)xi, DPP_WAVE_SHR1, 0xF, 0xF, false);
-        hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(fi >> 32), (int)(uint32_t)(xi >> 32), DPP_WAVE_SHR1, 0xF, 0xF, false);
-    } else {
-        lo = __builtin_amdgcn_update_dpp((int)(uint32_t)fi, (int)(uint32_t)xi, DPP_WAVE_SHL1, 0xF, 0xF, false);
-        hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(fi >> 32), (int)(uint32_t)(xi >> 32), DPP_WAVE_SHL1, 0xF, 0xF, false);
-    }
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)xi, CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(xi >> 32), CTRL, 0xF, 0xF, true);
     return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
 }
-__device__ __forceinline__ double from_left(double x, double fill) { return dpp64(x, fill, 0); }
-__device__ __forceinline__ double from_right(double x, double fill) { return dpp64(x, fill, 1); }
+__device__ __forceinline__ double from_left(double x) { return dpp64<DPP_WAVE_SHR1>(x); }
+__device__ __forceinline__ double from_right(double x) { return dpp64<DPP_WAVE_SHL1>(x); }
 
 __device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
@@ -68,7 +63,7 @@ enum { IN_SCALAR = 0, IN_CELL = 1 };
 
 // Per-launch system constants, already converted to the kernel's type.
 template <class T> struct SysPrm {
-    T a0, a1, a2, a3, a4;   // CTM: v, w, c*w, q, -  RD: 1/h^2  LIN3: aL, aD, aR, b
+    T a0, a1, a2, a3, a4;   // CTM: v, w, c*w, q  RD: 1/h^2, 2/h^2  LIN3: aL, aD, aR, b
 };
 
 // Inputs seen by one lane: scalar (same for every cell) or one per cell.
@@ -94,21 +89,28 @@ __device__ __forceinline__ void rk_update(T k, T& y, T& acc, T& t, const Steps<T
     if (STAGE == 4) { acc = acc + k;           y = fmaT(st.dt6, acc, y); }
 }
 
-// Cell validity for windows that run past the chain's last cell: cells at
-// or beyond n hold the boundary's ghost value at every stage.
-template <int E, bool MASKED> struct Mask {
-    int nvalid;  // cells of this lane inside the chain (0..E)
-    __device__ __forceinline__ bool ok(int e) const { return !MASKED || e < nvalid; }
+// Where a window sits relative to the chain's right end.
+//   PAD : the window runs past cell n-1; cells at or beyond n hold the
+//         boundary's ghost value at every stage (nvalid cells of this lane are
+//         inside the chain).
+//   END : the window contains cell n-1, so lane 63's right neighbour is the
+//         ghost.  Zero-filled lane shifts already give the Dirichlet ghost 0;
+//         only the CTM's free outflow (ghost -inf) needs an explicit value.
+// A window's left end at cell 0 needs nothing: lane 0 receives 0 from the
+// left, which is both the Dirichlet ghost and the CTM's zero inflow flux.
+template <int E, bool PAD, bool END> struct Mask {
+    int nvalid;
+    __device__ __forceinline__ bool ok(int e) const { return !PAD || e < nvalid; }
 };
 
 // One RK4 stage for all cells of the lane, for every side s < S.
 //   in  : the stage input (y for stage 1, t otherwise)
 // For S == 2 the sides are (lower, upper) of the embedding; for S == 1 the
 // kernel integrates f itself (Monte Carlo).
-template <int KIND, int STAGE, class T, int E, int S, int MODE, bool MASKED>
+template <int KIND, int STAGE, class T, int E, int S, int MODE, bool MASKED, bool END>
 __device__ __forceinline__ void rk_stage(T (&y)[S][E], T (&acc)[S][E], T (&t)[S][E],
                                          const SysPrm<T>& P, const Inputs<T, E, S, MODE>& U,
-                                         const Steps<T>& st, const Mask<E, MASKED>& M)
+                                         const Steps<T>& st, const Mask<E, MASKED, END>& M)
 {
     T (&in)[S][E] = (STAGE == 1) ? y : t;
     if constexpr (KIND == K_CTM) {
@@ -118,11 +120,13 @@ __device__ __forceinline__ void rk_stage(T (&y)[S][E], T (&acc)[S][E], T (&t)[S]
         // window's first cell arrives from the left lane, 0 at lane 0 (zero
         // inflow into cell 0).
         const T v = P.a0, w = P.a1, wc = P.a2, q = P.a3;
+        const bool last_lane = (threadIdx.x & (WAVE - 1)) == WAVE - 1;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const T rn = from_right(in[s][0], neg_inf<T>());
+            T rn = from_right(in[s][0]);
+            if (END) rn = last_lane ? neg_inf<T>() : rn;
             const T Flast = minT(minT(v * in[s][E - 1], fmaT(-w, rn, wc)), q);
-            T Fprev = from_left(Flast, T(0));
+            T Fprev = from_left(Flast);
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const T F = (e == E - 1) ? Flast : minT(minT(v * in[s][e], fmaT(-w, in[s][e + 1], wc)), q);
@@ -138,20 +142,21 @@ __device__ __forceinline__ void rk_stage(T (&y)[S][E], T (&acc)[S][E], T (&t)[S]
             }
         }
     } else if constexpr (KIND == K_RD) {
-        // k = (y_{e-1} - 2 y_e + y_{e+1}) / h^2 - y_e^3 + u, Dirichlet ghosts 0.
-        const T ih2 = P.a0;
+        // k = (y_{e-1} - 2 y_e + y_{e+1}) / h^2 - y_e^3 + u, Dirichlet ghosts 0,
+        // regrouped into four fused operations:
+        //   k = (y_{e-1} + y_{e+1}) / h^2 + (u - y_e (y_e^2 + 2 / h^2)).
+        const T ih2 = P.a0, two_ih2 = P.a1;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const T ln = from_left(in[s][E - 1], T(0));
-            const T rn = from_right(in[s][0], T(0));
+            const T ln = from_left(in[s][E - 1]);
+            const T rn = from_right(in[s][0]);
             T left = ln;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const T mid = in[s][e];
                 const T right = (e == E - 1) ? rn : in[s][e + 1];
-                const T lap = fmaT(T(-2), mid, left + right);
-                const T base = fmaT(lap, ih2, U.at(s, e));
-                const T k = fmaT(-(mid * mid), mid, base);
+                const T loc = fmaT(-mid, fmaT(mid, mid, two_ih2), U.at(s, e));
+                const T k = fmaT(left + right, ih2, loc);
                 left = mid;
                 if (STAGE == 4) {
                     rk_update<4>(k, y[s][e], acc[s][e], t[s][e], st);
@@ -170,8 +175,8 @@ __device__ __forceinline__ void rk_stage(T (&y)[S][E], T (&acc)[S][E], T (&t)[S]
         T ln[S], rn[S], left[S];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            ln[s] = from_left(in[s][E - 1], T(0));
-            rn[s] = from_right(in[s][0], T(0));
+            ln[s] = from_left(in[s][E - 1]);
+            rn[s] = from_right(in[s][0]);
             left[s] = ln[s];
         }
 #pragma unroll
@@ -216,10 +221,10 @@ __device__ __forceinline__ void rk_stage(T (&y)[S][E], T (&acc)[S][E], T (&t)[S]
 }
 
 // `nsteps` classical RK4 steps on the lane's registers.
-template <int KIND, class T, int E, int S, int MODE, bool MASKED>
+template <int KIND, class T, int E, int S, int MODE, bool MASKED, bool END>
 __device__ __forceinline__ void rk4_steps(T (&y)[S][E], int64_t nsteps, const SysPrm<T>& P,
                                           const Inputs<T, E, S, MODE>& U, const Steps<T>& st,
-                                          const Mask<E, MASKED>& M)
+                                          const Mask<E, MASKED, END>& M)
 {
     T acc[S][E], t[S][E];
     for (int64_t k = 0; k < nsteps; ++k) {

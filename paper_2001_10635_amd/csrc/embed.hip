@@ -16,6 +16,8 @@
 // Global <-> register transfers go through LDS so that every global access is
 // a coalesced 16-byte vector access even though each lane owns E consecutive
 // cells (rows padded by 16 bytes to keep the LDS reads conflict-free).
+#include <algorithm>
+
 #include "dev.hpp"
 #include "kernels.hpp"
 
@@ -109,7 +111,12 @@ template <class T> __device__ __forceinline__ SysPrm<T> make_prm(const double (&
     return P;
 }
 
-template <int KIND, class T, int E, int MODE>
+// S = 2: a wave holds both sides of its window (any system, including the
+// coupled LIN3).  S = 1: a wave holds one side (cooperative systems only, whose
+// decomposition function reads one side), so the same registers cover twice
+// the cells and the halo share halves; tiles [0, W) are the lower side and
+// [W, 2W) the upper side.
+template <int KIND, class T, int E, int MODE, int S>
 __global__ __launch_bounds__(64) void embed_tile_kernel(EmbedPass a) {
     using IO = TileIO<T, E>;
     __shared__ __attribute__((aligned(16))) T lds[IO::LDS_ELEMS];
@@ -117,47 +124,54 @@ __global__ __launch_bounds__(64) void embed_tile_kernel(EmbedPass a) {
 
     // blockIdx -> tile: consecutive tiles on one XCD share halos in its L2.
     const int64_t b = blockIdx.x;
-    const int64_t w = (b & 7) * (int64_t)a.per_xcd + (b >> 3);
-    if (w >= a.W) return;
+    const int64_t g = (b & 7) * (int64_t)a.per_xcd + (b >> 3);
+    if (g >= (S == 1 ? 2 * a.W : a.W)) return;
+    const int side = (S == 1 && g >= a.W) ? 1 : 0;
+    const int64_t w = g - side * a.W;
 
     const int64_t span = (int64_t)WAVE * E;
     const int64_t ts = w * a.OUT;
     const bool reaches_end = ts + span >= a.n;
-    const bool masked = ts + span > a.n;
-    const bool fast = a.aligned && !masked;
+    const bool fast = a.aligned && ts + span <= a.n;
+    const T* src[2] = {(const T*)a.src_lo, (const T*)a.src_hi};
+    T* dst[2] = {(T*)a.dst_lo, (T*)a.dst_hi};
+    const T* pin[2] = {(const T*)a.p_lo, (const T*)a.p_hi};
 
-    T y[2][E];
-    IO::load(y[0], (const T*)a.src_lo, ts, a.n, ghost<KIND, T>(), fast, lds);
-    IO::load(y[1], (const T*)a.src_hi, ts, a.n, ghost<KIND, T>(), fast, lds);
-
-    Inputs<T, E, 2, MODE> U;
-    if constexpr (MODE == IN_SCALAR) {
-        U.u[0] = a.p_lo ? ((const T*)a.p_lo)[0] : T(0);
-        U.u[1] = a.p_hi ? ((const T*)a.p_hi)[0] : T(0);
-    } else {
+    T y[S][E];
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int64_t g = ts + (int64_t)lane * E + e;
-            U.u[0][e] = (g < a.n) ? ((const T*)a.p_lo)[g] : T(0);
-            U.u[1][e] = (g < a.n) ? ((const T*)a.p_hi)[g] : T(0);
+    for (int s = 0; s < S; ++s) IO::load(y[s], src[S == 1 ? side : s], ts, a.n, ghost<KIND, T>(), fast, lds);
+
+    Inputs<T, E, S, MODE> U;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const T* p = pin[S == 1 ? side : s];
+        if constexpr (MODE == IN_SCALAR) {
+            U.u[s] = p ? p[0] : T(0);
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t c = ts + (int64_t)lane * E + e;
+                U.u[s][e] = (c < a.n) ? p[c] : T(0);
+            }
         }
     }
     const SysPrm<T> P = make_prm<T>(a.prm);
     const Steps<T> st = {(T)a.h2, (T)a.dt, (T)a.dt6};
 
-    if (masked) {
+    if (reaches_end) {
+        // the window holding cell n-1 (cells past it, if any, are ghosts)
         const int64_t left = a.n - (ts + (int64_t)lane * E);
-        Mask<E, true> M{(int)(left < 0 ? 0 : (left > E ? E : left))};
-        rk4_steps<KIND, T, E, 2, MODE, true>(y, a.ksteps, P, U, st, M);
+        Mask<E, true, true> M{(int)(left < 0 ? 0 : (left > E ? E : left))};
+        rk4_steps<KIND, T, E, S, MODE>(y, a.ksteps, P, U, st, M);
     } else {
-        Mask<E, false> M{E};
-        rk4_steps<KIND, T, E, 2, MODE, false>(y, a.ksteps, P, U, st, M);
+        Mask<E, false, false> M{E};
+        rk4_steps<KIND, T, E, S, MODE>(y, a.ksteps, P, U, st, M);
     }
 
     const int olo = (w == 0) ? 0 : a.H;
     const int ohi = reaches_end ? (int)(a.n - ts) : (int)(span - a.H);
-    IO::store(y[0], (T*)a.dst_lo, ts, olo, ohi, fast, lds);
-    IO::store(y[1], (T*)a.dst_hi, ts, olo, ohi, fast, lds);
+#pragma unroll
+    for (int s = 0; s < S; ++s) IO::store(y[s], dst[S == 1 ? side : s], ts, olo, ohi, fast, lds);
 
     if (a.check) {
         unsigned bits = 0;
@@ -165,56 +179,121 @@ __global__ __launch_bounds__(64) void embed_tile_kernel(EmbedPass a) {
         for (int e = 0; e < E; ++e) {
             const int el = lane * E + e;
             if (el >= olo && el < ohi) {
-                if (!finiteT(y[0][e]) || !finiteT(y[1][e])) bits |= ST_NONFINITE;
-                if (y[0][e] > y[1][e]) bits |= ST_ORDER;
+#pragma unroll
+                for (int s = 0; s < S; ++s)
+                    if (!finiteT(y[s][e])) bits |= ST_NONFINITE;
+                if constexpr (S == 2) {
+                    if (y[0][e] > y[1][e]) bits |= ST_ORDER;
+                }
             }
         }
         report_status(a.status, bits);
     }
 }
 
-template <int KIND, class T, int E, int MODE>
+// Lower > upper check of a finished box (used after single-side passes, where
+// no wave sees both sides of a cell).
+template <class T>
+__global__ __launch_bounds__(256) void order_check_kernel(const T* __restrict__ lo,
+                                                          const T* __restrict__ hi, int64_t n,
+                                                          unsigned int* status) {
+    unsigned bits = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        if (lo[i] > hi[i]) bits = ST_ORDER;
+    report_status(status, bits);
+}
+
+template <int KIND, class T, int E, int MODE, int S>
 static hipError_t go(const EmbedPass& a, int64_t grid, hipStream_t s) {
-    hipLaunchKernelGGL((embed_tile_kernel<KIND, T, E, MODE>), dim3((unsigned)grid), dim3(WAVE), 0, s, a);
+    hipLaunchKernelGGL((embed_tile_kernel<KIND, T, E, MODE, S>), dim3((unsigned)grid), dim3(WAVE), 0, s, a);
     return hipGetLastError();
 }
 
+// Shapes built: S = 2 (both sides per wave) for every system, S = 1 (one side
+// per wave, wider tiles) for the cooperative CTM and RD chains.
 template <int KIND, class T, int MODE>
-static hipError_t by_E(int E, const EmbedPass& a, int64_t grid, hipStream_t s) {
-    switch (E) {
-        case 1: return go<KIND, T, 1, MODE>(a, grid, s);
-        case 2: return go<KIND, T, 2, MODE>(a, grid, s);
-        case 4: return go<KIND, T, 4, MODE>(a, grid, s);
-        case 8: return go<KIND, T, 8, MODE>(a, grid, s);
-        case 16: return go<KIND, T, 16, MODE>(a, grid, s);
-        case 32:
-            if constexpr (sizeof(T) == 4) return go<KIND, T, 32, MODE>(a, grid, s);
-            else return hipErrorInvalidValue;
-        default: return hipErrorInvalidValue;
+static hipError_t by_E(int E, int S, const EmbedPass& a, int64_t grid, hipStream_t s) {
+    constexpr bool F32 = sizeof(T) == 4;
+    constexpr bool COOP = KIND != K_LIN3;
+    if (S == 2) {
+        switch (E) {
+            case 1: return go<KIND, T, 1, MODE, 2>(a, grid, s);
+            case 2: return go<KIND, T, 2, MODE, 2>(a, grid, s);
+            case 4: return go<KIND, T, 4, MODE, 2>(a, grid, s);
+            case 8: return go<KIND, T, 8, MODE, 2>(a, grid, s);
+            case 12: return go<KIND, T, 12, MODE, 2>(a, grid, s);
+            case 16: return go<KIND, T, 16, MODE, 2>(a, grid, s);
+            case 32:
+                if constexpr (F32) return go<KIND, T, 32, MODE, 2>(a, grid, s);
+                else return hipErrorInvalidValue;
+            default: return hipErrorInvalidValue;
+        }
     }
-}
-
-bool embed_has_E(int dtype, int E) {
-    return E == 1 || E == 2 || E == 4 || E == 8 || E == 16 || (dtype == 1 && E == 32);
-}
-int embed_max_E(int dtype) { return dtype == 1 ? 32 : 16; }
-
-hipError_t launch_embed(int kind, int mode, int dtype, int E, const EmbedPass& a, int64_t grid,
-                        hipStream_t s) {
-    if (dtype == 0) {
-        if (kind == K_CTM) return by_E<K_CTM, double, IN_SCALAR>(E, a, grid, s);
-        if (kind == K_RD) return mode ? by_E<K_RD, double, IN_CELL>(E, a, grid, s)
-                                      : by_E<K_RD, double, IN_SCALAR>(E, a, grid, s);
-        if (kind == K_LIN3) return mode ? by_E<K_LIN3, double, IN_CELL>(E, a, grid, s)
-                                        : by_E<K_LIN3, double, IN_SCALAR>(E, a, grid, s);
-    } else {
-        if (kind == K_CTM) return by_E<K_CTM, float, IN_SCALAR>(E, a, grid, s);
-        if (kind == K_RD) return mode ? by_E<K_RD, float, IN_CELL>(E, a, grid, s)
-                                      : by_E<K_RD, float, IN_SCALAR>(E, a, grid, s);
-        if (kind == K_LIN3) return mode ? by_E<K_LIN3, float, IN_CELL>(E, a, grid, s)
-                                        : by_E<K_LIN3, float, IN_SCALAR>(E, a, grid, s);
+    if constexpr (COOP) {
+        if (S == 1) {
+            switch (E) {
+                case 1: return go<KIND, T, 1, MODE, 1>(a, grid, s);
+                case 2: return go<KIND, T, 2, MODE, 1>(a, grid, s);
+                case 4: return go<KIND, T, 4, MODE, 1>(a, grid, s);
+                case 8: return go<KIND, T, 8, MODE, 1>(a, grid, s);
+                case 16: return go<KIND, T, 16, MODE, 1>(a, grid, s);
+                case 24: return go<KIND, T, 24, MODE, 1>(a, grid, s);
+                case 32: return go<KIND, T, 32, MODE, 1>(a, grid, s);
+                case 48:
+                    if constexpr (F32) return go<KIND, T, 48, MODE, 1>(a, grid, s);
+                    else return hipErrorInvalidValue;
+                case 64:
+                    if constexpr (F32) return go<KIND, T, 64, MODE, 1>(a, grid, s);
+                    else return hipErrorInvalidValue;
+                default: return hipErrorInvalidValue;
+            }
+        }
     }
     return hipErrorInvalidValue;
+}
+
+bool embed_has_shape(int kind, int dtype, int E, int S) {
+    if (S == 2)
+        return E == 1 || E == 2 || E == 4 || E == 8 || E == 12 || E == 16 || (dtype == 1 && E == 32);
+    if (S == 1 && kind != K_LIN3)
+        return E == 1 || E == 2 || E == 4 || E == 8 || E == 16 || E == 24 || E == 32 ||
+               (dtype == 1 && (E == 48 || E == 64));
+    return false;
+}
+int embed_max_E(int dtype, int S) {
+    if (S == 1) return dtype == 1 ? 64 : 32;
+    return dtype == 1 ? 32 : 16;
+}
+
+hipError_t launch_embed(int kind, int mode, int dtype, int E, int S, const EmbedPass& a,
+                        int64_t grid, hipStream_t s) {
+    if (dtype == 0) {
+        if (kind == K_CTM) return by_E<K_CTM, double, IN_SCALAR>(E, S, a, grid, s);
+        if (kind == K_RD) return mode ? by_E<K_RD, double, IN_CELL>(E, S, a, grid, s)
+                                      : by_E<K_RD, double, IN_SCALAR>(E, S, a, grid, s);
+        if (kind == K_LIN3) return mode ? by_E<K_LIN3, double, IN_CELL>(E, S, a, grid, s)
+                                        : by_E<K_LIN3, double, IN_SCALAR>(E, S, a, grid, s);
+    } else {
+        if (kind == K_CTM) return by_E<K_CTM, float, IN_SCALAR>(E, S, a, grid, s);
+        if (kind == K_RD) return mode ? by_E<K_RD, float, IN_CELL>(E, S, a, grid, s)
+                                      : by_E<K_RD, float, IN_SCALAR>(E, S, a, grid, s);
+        if (kind == K_LIN3) return mode ? by_E<K_LIN3, float, IN_CELL>(E, S, a, grid, s)
+                                        : by_E<K_LIN3, float, IN_SCALAR>(E, S, a, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_order_check(int dtype, const void* lo, const void* hi, int64_t n,
+                              unsigned int* status, hipStream_t s) {
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+    if (dtype == 0)
+        hipLaunchKernelGGL(order_check_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (const double*)lo, (const double*)hi, n, status);
+    else
+        hipLaunchKernelGGL(order_check_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           (const float*)lo, (const float*)hi, n, status);
+    return hipGetLastError();
 }
 
 }  // namespace reach

@@ -8,6 +8,10 @@ namespace reach {
 // Bits of a context's device status word (the kernels use the same values).
 enum { STATUS_NONFINITE = 1, STATUS_ORDER = 2 };
 
+// Kernel-side parameters of a system (CTM {v, w, w*c, q}, RD {1/h^2, 2/h^2},
+// LIN3 {aL, aD, aR, b}) from the C-ABI parameter array.
+void kernel_params(int kind, const double* prm, double out[5]);
+
 // One HBM pass of the embedding: `ksteps` RK4 steps on every tile.
 // Tile w reads cells [w*OUT, w*OUT + 64E) of src and writes the cells it
 // owns to dst: [0, 64E - H) for tile 0, [w*OUT + H, w*OUT + 64E - H) for
@@ -33,12 +37,17 @@ struct EmbedPass {
 };
 
 // kind: 1 CTM, 2 RD, 3 LIN3; mode: 0 scalar input, 1 per-cell input;
-// dtype: 0 f64, 1 f32.  Returns hipErrorInvalidValue for an E this build
+// dtype: 0 f64, 1 f32.  Returns hipErrorInvalidValue for an E the library
 // does not instantiate.
-hipError_t launch_embed(int kind, int mode, int dtype, int E, const EmbedPass& a,
+// S: sides per wave (2 = lower and upper together, 1 = one side per wave;
+// 1 only for the cooperative CTM and RD chains).  W counts tiles per side.
+hipError_t launch_embed(int kind, int mode, int dtype, int E, int S, const EmbedPass& a,
                         int64_t grid, hipStream_t stream);
-bool embed_has_E(int dtype, int E);
-int embed_max_E(int dtype);
+bool embed_has_shape(int kind, int dtype, int E, int S);
+int embed_max_E(int dtype, int S);
+// Flags lower > upper anywhere in a finished box.
+hipError_t launch_order_check(int dtype, const void* lo, const void* hi, int64_t n,
+                              unsigned int* status, hipStream_t stream);
 
 struct McArgs {
     const void* x_lo;
@@ -73,7 +82,8 @@ struct QDesc {
     int64_t n;
     int64_t nsteps;
     double prm[5];
-    double u_lo, u_hi;  // scalar inputs (0 when n_in == 0)
+    const double* p_lo;  // scalar input interval (NULL when n_in == 0), device-visible
+    const double* p_hi;
     double h2, dt, dt6;
     const double* x_lo;
     const double* x_hi;

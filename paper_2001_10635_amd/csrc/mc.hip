@@ -97,12 +97,13 @@ __global__ __launch_bounds__(64) void mc_kernel(McArgs a) {
             }
         }
 
+        // the wave holds the whole chain: its window always contains cell n-1
         if (masked) {
-            Mask<E, true> M{nvalid};
-            rk4_steps<KIND, T, E, 1, MODE, true>(y, a.nsteps, P, U, st, M);
+            Mask<E, true, true> M{nvalid};
+            rk4_steps<KIND, T, E, 1, MODE>(y, a.nsteps, P, U, st, M);
         } else {
-            Mask<E, false> M{E};
-            rk4_steps<KIND, T, E, 1, MODE, false>(y, a.nsteps, P, U, st, M);
+            Mask<E, false, true> M{E};
+            rk4_steps<KIND, T, E, 1, MODE>(y, a.nsteps, P, U, st, M);
         }
 
 #pragma unroll

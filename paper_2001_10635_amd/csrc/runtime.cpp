@@ -25,6 +25,19 @@
 
 using namespace reach;
 
+void reach::kernel_params(int kind, const double* prm, double out[5]) {
+    for (int i = 0; i < 5; ++i) out[i] = 0.0;
+    if (kind == REACH_CTM) {
+        out[0] = prm[0]; out[1] = prm[1]; out[2] = prm[1] * prm[2]; out[3] = prm[3];
+    } else if (kind == REACH_RD) {
+        const double ih2 = 1.0 / (prm[0] * prm[0]);
+        out[0] = ih2;
+        out[1] = 2.0 * ih2;
+    } else {
+        out[0] = prm[0]; out[1] = prm[1]; out[2] = prm[2]; out[3] = prm[3];
+    }
+}
+
 namespace {
 
 constexpr int64_t kMaxN = (int64_t)1 << 40;
@@ -41,13 +54,14 @@ struct GraphKey {
     }
 };
 
-struct TuneEntry { int E; int K; };
+struct TuneEntry { int E; int K; int S; };
 
 }  // namespace
 
 struct reach_ctx {
     int device = 0;
     int cus = 256;
+    std::string arch;
     unsigned int* status = nullptr;      // device status word
     std::string err;
     std::map<std::string, int64_t> opt;
@@ -106,17 +120,7 @@ reach_status check_system(reach_ctx* c, const reach_system* s, reach_dtype dtype
     return REACH_OK;
 }
 
-// Kernel-side parameters: CTM {v, w, w*c, q}, RD {1/h^2}, LIN3 {aL, aD, aR, b}.
-void kernel_prm(const reach_system* s, double out[5]) {
-    for (int i = 0; i < 5; ++i) out[i] = 0.0;
-    if (s->kind == REACH_CTM) {
-        out[0] = s->prm[0]; out[1] = s->prm[1]; out[2] = s->prm[1] * s->prm[2]; out[3] = s->prm[3];
-    } else if (s->kind == REACH_RD) {
-        out[0] = 1.0 / (s->prm[0] * s->prm[0]);
-    } else {
-        out[0] = s->prm[0]; out[1] = s->prm[1]; out[2] = s->prm[2]; out[3] = s->prm[3];
-    }
-}
+void kernel_prm(const reach_system* s, double out[5]) { kernel_params(s->kind, s->prm, out); }
 
 bool aligned16(const void* p) { return ((uintptr_t)p & 15u) == 0; }
 
@@ -129,6 +133,7 @@ int ceil_pow2_E(int64_t n) {
 // ------------------------------------------------------------ planning --
 struct EmbedPlan {
     int E = 1;
+    int S = 2;           // sides per wave
     int K = 1;           // steps per pass
     int64_t W = 1;       // tiles
     int64_t OUT = 0;
@@ -136,8 +141,11 @@ struct EmbedPlan {
     int64_t passes = 1;
 };
 
-TuneEntry default_tune(int dtype) {
-    return dtype == REACH_F64 ? TuneEntry{8, 8} : TuneEntry{16, 8};
+// Defaults measured on MI355X for the 2^26-cell chains (overridden by the
+// autotuner or its cache).  Cooperative chains run one side per wave.
+TuneEntry default_tune(int kind, int dtype) {
+    if (kind == REACH_LIN3) return dtype == REACH_F64 ? TuneEntry{12, 12, 2} : TuneEntry{16, 8, 2};
+    return dtype == REACH_F64 ? TuneEntry{24, 12, 1} : TuneEntry{48, 12, 1};
 }
 
 int n_bucket(int64_t n) {
@@ -149,22 +157,33 @@ int n_bucket(int64_t n) {
 TuneEntry tuned(const reach_ctx* c, int kind, int dtype, int64_t n) {
     auto it = c->tune.find({kind, dtype, n_bucket(n)});
     if (it != c->tune.end()) return it->second;
-    return default_tune(dtype);
+    return default_tune(kind, dtype);
+}
+
+int smallest_E(int kind, int dtype, int S, int64_t n) {
+    for (int E : {1, 2, 4, 8, 12, 16, 24, 32, 48, 64})
+        if (embed_has_shape(kind, dtype, E, S) && (int64_t)64 * E >= n) return E;
+    return 0;
 }
 
 reach_status plan_embed(reach_ctx* c, const reach_system* s, reach_dtype dtype, int64_t nsteps,
                         EmbedPlan* p) {
     const int64_t n = s->n;
-    const int maxE = embed_max_E(dtype);
-    int64_t oE = opt_get(c, "embed.E"), oK = opt_get(c, "embed.K");
-    TuneEntry te = tuned(c, s->kind, dtype, n);
+    const int64_t oE = opt_get(c, "embed.E"), oK = opt_get(c, "embed.K"), oS = opt_get(c, "embed.S");
+    const TuneEntry te = tuned(c, s->kind, dtype, n);
+    int S = oS ? (int)oS : (oE ? (s->kind == REACH_LIN3 ? 2 : te.S) : te.S);
+    if (s->kind == REACH_LIN3 && S == 1)
+        return fail(c, REACH_E_INVAL, "the coupled LIN3 chain needs both sides per wave");
     int E = oE ? (int)oE : 0;
-    if (E && !embed_has_E(dtype, E)) return fail(c, REACH_E_INVAL, "embed.E = %d not built", E);
+    if (E && !embed_has_shape(s->kind, dtype, E, S))
+        return fail(c, REACH_E_INVAL, "tile shape E = %d, S = %d not built", E, S);
     if (!E) {
-        if (n <= (int64_t)64 * maxE) E = std::min(ceil_pow2_E(n), maxE);
-        else E = te.E;
+        const int small = smallest_E(s->kind, dtype, S, n);
+        E = (small && !oK) ? small : te.E;
+        if (!embed_has_shape(s->kind, dtype, E, S)) E = embed_max_E(dtype, S);
     }
     p->E = E;
+    p->S = S;
     const int64_t span = (int64_t)64 * E;
     if (n <= span && !oK) {
         // one window covers the chain: both ends are true boundaries, no halo
@@ -178,12 +197,8 @@ reach_status plan_embed(reach_ctx* c, const reach_system* s, reach_dtype dtype, 
     if ((int64_t)8 * K >= span) return fail(c, REACH_E_INVAL, "K = %d too large for E = %d", K, E);
     p->K = K;
     p->H = 4 * K;
-    if (n <= span) {
-        p->W = 1; p->OUT = span - 2 * p->H;
-    } else {
-        p->OUT = span - 2 * p->H;
-        p->W = 1 + (n - span + p->OUT - 1) / p->OUT;
-    }
+    p->OUT = span - 2 * p->H;
+    p->W = (n <= span) ? 1 : 1 + (n - span + p->OUT - 1) / p->OUT;
     p->passes = (nsteps + K - 1) / K;
     return REACH_OK;
 }
@@ -214,6 +229,33 @@ size_t mc_ws_bytes(const reach_ctx* c, const reach_system* s, reach_dtype dtype,
     return (size_t)2 * (size_t)mc_waves(c, m) * (size_t)(64 * E) * dsize(dtype);
 }
 
+
+// Autotune cache: one line per entry, "arch kind dtype bucket E K S ps_per_state_step".
+void load_tune_cache(reach_ctx* c) {
+    const char* path = std::getenv("REACH_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return;
+    char arch[64];
+    int kind, dtype, bucket, E, K, S;
+    double ps;
+    while (std::fscanf(f, "%63s %d %d %d %d %d %d %lf", arch, &kind, &dtype, &bucket, &E, &K, &S,
+                       &ps) == 8) {
+        if (c->arch == arch && embed_has_shape(kind, dtype, E, S) && K >= 1 && 8 * K < 64 * E)
+            c->tune[{kind, dtype, bucket}] = TuneEntry{E, K, S};
+    }
+    std::fclose(f);
+}
+
+void save_tune_entry(const reach_ctx* c, int kind, int dtype, int bucket, TuneEntry t, double ps) {
+    const char* path = std::getenv("REACH_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "%s %d %d %d %d %d %d %.3f\n", c->arch.empty() ? "unknown" : c->arch.c_str(),
+                 kind, dtype, bucket, t.E, t.K, t.S, ps);
+    std::fclose(f);
+}
 }  // namespace
 
 // =================================================================== ABI ==
@@ -231,6 +273,13 @@ reach_status reach_ctx_create(int device, reach_ctx** out) {
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->cus = cus;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        c->arch = prop.gcnArchName;
+        const size_t colon = c->arch.find(':');
+        if (colon != std::string::npos) c->arch.resize(colon);
+    }
+    load_tune_cache(c);
     if (hipMalloc((void**)&c->status, 256) != hipSuccess) { delete c; return REACH_E_DEVICE; }
     if (hipMemset(c->status, 0, 256) != hipSuccess) { hipFree(c->status); delete c; return REACH_E_DEVICE; }
     if (hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming) != hipSuccess) {
@@ -259,14 +308,17 @@ const char* reach_last_error(const reach_ctx* c) { return c ? c->err.c_str() : "
 
 reach_status reach_set_option(reach_ctx* c, const char* key, int64_t value) {
     if (!c || !key) return REACH_E_INVAL;
-    static const char* keys[] = {"embed.K", "embed.E", "mc.waves", "batch.waves", "serve.mode",
-                                 "serve.waves"};
+    static const char* keys[] = {"embed.K", "embed.E", "embed.S", "mc.waves", "batch.waves",
+                                 "serve.mode", "serve.waves"};
     bool known = false;
     for (const char* k : keys) known |= (std::strcmp(k, key) == 0);
     if (!known) return fail(c, REACH_E_INVAL, "unknown option %s", key);
     if (value < 0) return fail(c, REACH_E_INVAL, "option %s must be >= 0", key);
-    if (!std::strcmp(key, "embed.E") && value && !embed_has_E(REACH_F32, (int)value))
+    if (!std::strcmp(key, "embed.E") && value && !embed_has_shape(REACH_CTM, REACH_F32, (int)value, 2) &&
+        !embed_has_shape(REACH_CTM, REACH_F32, (int)value, 1))
         return fail(c, REACH_E_INVAL, "embed.E = %lld not built", (long long)value);
+    if (!std::strcmp(key, "embed.S") && value != 0 && value != 1 && value != 2)
+        return fail(c, REACH_E_INVAL, "embed.S must be 0, 1 or 2");
     c->opt[key] = value;
     return REACH_OK;
 }
@@ -285,6 +337,7 @@ reach_status reach_plan_embed(reach_ctx* c, const reach_system* s, reach_dtype d
     st = plan_embed(c, s, dtype, nsteps, &p);
     if (st != REACH_OK) return st;
     out[0] = p.E; out[1] = p.K; out[2] = p.W; out[3] = p.OUT; out[4] = p.H; out[5] = p.passes;
+    out[6] = p.S;
     return REACH_OK;
 }
 
@@ -367,7 +420,8 @@ reach_status reach_embed_rk4(reach_ctx* c, const reach_system* s, reach_dtype dt
     a.n = s->n; a.W = pl.W; a.OUT = pl.OUT; a.H = pl.H;
     a.aligned = aligned16(x_lo) && aligned16(x_hi) && aligned16(r_lo) && aligned16(r_hi) &&
                 (!need_ws || (aligned16(w_lo) && aligned16(w_hi)));
-    a.per_xcd = (int32_t)((pl.W + 7) / 8);
+    const int64_t tiles = pl.S == 1 ? 2 * pl.W : pl.W;
+    a.per_xcd = (int32_t)((tiles + 7) / 8);
     kernel_prm(s, a.prm);
     a.h2 = dt / 2.0; a.dt = dt; a.dt6 = dt / 6.0;
     a.status = c->status;
@@ -382,14 +436,83 @@ reach_status reach_embed_rk4(reach_ctx* c, const reach_system* s, reach_dtype dt
         a.dst_hi = (void*)hi_of[io[p].second];
         a.ksteps = std::min<int64_t>(pl.K, nsteps - done);
         a.check = (p == pl.passes - 1) ? 1 : 0;
-        hipError_t e = launch_embed(s->kind, mode, dtype == REACH_F64 ? 0 : 1, pl.E, a, grid, hs);
+        hipError_t e = launch_embed(s->kind, mode, dtype == REACH_F64 ? 0 : 1, pl.E, pl.S, a, grid,
+                                    hs);
         if (e != hipSuccess) return hip_fail(c, e, "embedding kernel launch");
         done += a.ksteps;
+    }
+    if (pl.S == 1) {
+        hipError_t e = launch_order_check(dtype == REACH_F64 ? 0 : 1, lo_of[io.back().second],
+                                          hi_of[io.back().second], s->n, c->status, hs);
+        if (e != hipSuccess) return hip_fail(c, e, "order check launch");
     }
     if (final_copy) {
         HIPCHK(c, hipMemcpyAsync(r_lo, w_lo, bytes, hipMemcpyDeviceToDevice, hs));
         HIPCHK(c, hipMemcpyAsync(r_hi, w_hi, bytes, hipMemcpyDeviceToDevice, hs));
     }
+    return REACH_OK;
+}
+
+
+reach_status reach_autotune_embed(reach_ctx* c, const reach_system* s, reach_dtype dtype,
+                                  const void* x_lo, const void* x_hi, const void* p_lo,
+                                  const void* p_hi, double dt, int64_t trial_steps, void* r_lo,
+                                  void* r_hi, void* ws, size_t ws_bytes, void* stream,
+                                  int64_t* best) {
+    if (!c || !best) return REACH_E_INVAL;
+    reach_status st = check_system(c, s, dtype);
+    if (st != REACH_OK) return st;
+    if (trial_steps < 1) return fail(c, REACH_E_INVAL, "trial_steps must be >= 1");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t hs = (hipStream_t)stream;
+    const int64_t saveE = opt_get(c, "embed.E"), saveK = opt_get(c, "embed.K");
+    static const int Es[] = {4, 8, 12, 16, 24, 32, 48, 64};
+    static const int Ks[] = {2, 4, 6, 8, 10, 12, 16, 20, 24};
+    const int64_t saveS = opt_get(c, "embed.S");
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    double best_ps = 1e300;
+    TuneEntry bt{0, 0, 0};
+    st = REACH_OK;
+    for (int S : {2, 1})
+    for (int E : Es) {
+        if (st != REACH_OK) break;
+        if (!embed_has_shape(s->kind, dtype, E, S) || (int64_t)64 * E >= 4 * s->n) continue;
+        for (int K : Ks) {
+            if (8 * K >= 64 * E) continue;
+            c->opt["embed.E"] = E;
+            c->opt["embed.K"] = K;
+            c->opt["embed.S"] = S;
+            reach_status r0 = reach_embed_rk4(c, s, dtype, x_lo, x_hi, p_lo, p_hi, 0.0, dt,
+                                              trial_steps, r_lo, r_hi, ws, ws_bytes, stream);
+            if (r0 != REACH_OK) { st = r0; break; }
+            hipEventRecord(e0, hs);
+            for (int rep = 0; rep < 2 && st == REACH_OK; ++rep)
+                st = reach_embed_rk4(c, s, dtype, x_lo, x_hi, p_lo, p_hi, 0.0, dt, trial_steps,
+                                     r_lo, r_hi, ws, ws_bytes, stream);
+            hipEventRecord(e1, hs);
+            if (hipEventSynchronize(e1) != hipSuccess) { st = REACH_E_DEVICE; break; }
+            float ms = 0.f;
+            hipEventElapsedTime(&ms, e0, e1);
+            const double ps = (double)ms * 1e9 / (2.0 * 2.0 * (double)s->n * (double)trial_steps);
+            if (ps < best_ps) { best_ps = ps; bt = TuneEntry{E, K, S}; }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->opt["embed.E"] = saveE;
+    c->opt["embed.K"] = saveK;
+    c->opt["embed.S"] = saveS;
+    if (st != REACH_OK) return st;
+    if (bt.E == 0) return fail(c, REACH_E_UNSUPPORTED, "n too small to tile: nothing to tune");
+    const int bucket = n_bucket(s->n);
+    c->tune[{s->kind, dtype, bucket}] = bt;
+    save_tune_entry(c, s->kind, dtype, bucket, bt, best_ps);
+    best[0] = bt.E;
+    best[1] = bt.K;
+    best[2] = (int64_t)std::llround(best_ps * 1000.0);
+    best[3] = bt.S;
     return REACH_OK;
 }
 
@@ -457,7 +580,7 @@ int64_t reach_mc_samples(int64_t n, double eps, double delta) {
 
 namespace {
 
-reach_status make_desc(reach_ctx* c, const reach_query& q, int64_t tag, bool host_ptrs, QDesc* d) {
+reach_status make_desc(reach_ctx* c, const reach_query& q, int64_t tag, QDesc* d) {
     reach_status st = check_system(c, &q.sys, q.dtype);
     if (st != REACH_OK) return st;
     if (q.dtype != REACH_F64) return fail(c, REACH_E_UNSUPPORTED, "batched queries are FP64");
@@ -478,20 +601,9 @@ reach_status make_desc(reach_ctx* c, const reach_query& q, int64_t tag, bool hos
     d->x_lo = (const double*)q.x_lo; d->x_hi = (const double*)q.x_hi;
     d->r_lo = (double*)q.r_lo; d->r_hi = (double*)q.r_hi;
     d->tag = tag;
-    if (q.sys.n_in == 1 && host_ptrs) {
-        d->u_lo = *(const double*)q.p_lo;
-        d->u_hi = *(const double*)q.p_hi;
-    }
-    return REACH_OK;
-}
-
-// Scalar inputs of device-resident queries are read with one small copy each.
-reach_status fetch_inputs(reach_ctx* c, const reach_query* q, int64_t nq, QDesc* d) {
-    for (int64_t i = 0; i < nq; ++i) {
-        if (q[i].sys.n_in == 1) {
-            HIPCHK(c, hipMemcpy(&d[i].u_lo, q[i].p_lo, 8, hipMemcpyDeviceToHost));
-            HIPCHK(c, hipMemcpy(&d[i].u_hi, q[i].p_hi, 8, hipMemcpyDeviceToHost));
-        }
+    if (q.sys.n_in == 1) {
+        d->p_lo = (const double*)q.p_lo;
+        d->p_hi = (const double*)q.p_hi;
     }
     return REACH_OK;
 }
@@ -519,11 +631,9 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     // host descriptors, longest query first
     std::vector<QDesc> d(nq);
     for (int64_t i = 0; i < nq; ++i) {
-        reach_status st = make_desc(c, q[i], i, false, &d[i]);
+        reach_status st = make_desc(c, q[i], i, &d[i]);
         if (st != REACH_OK) return st;
     }
-    reach_status st = fetch_inputs(c, q, nq, d.data());
-    if (st != REACH_OK) return st;
     std::stable_sort(d.begin(), d.end(), [](const QDesc& a, const QDesc& b) {
         return a.n * a.nsteps > b.n * b.nsteps;
     });
@@ -596,11 +706,9 @@ reach_status reach_embed_rk4_each(reach_ctx* c, const reach_query* q, int64_t nq
     }
     std::vector<QDesc> d(nq);
     for (int64_t i = 0; i < nq; ++i) {
-        reach_status st = make_desc(c, q[i], i, false, &d[i]);
+        reach_status st = make_desc(c, q[i], i, &d[i]);
         if (st != REACH_OK) return st;
     }
-    reach_status st = fetch_inputs(c, q, nq, d.data());
-    if (st != REACH_OK) return st;
     for (int64_t i = 0; i < nq; ++i) {
         hipError_t e = launch_single(d[i], c->status, c->each_streams[i % nstreams]);
         if (e != hipSuccess) return hip_fail(c, e, "single-query launch");

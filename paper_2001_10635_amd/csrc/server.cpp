@@ -19,6 +19,7 @@
 #include <chrono>
 #include <condition_variable>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -100,6 +101,11 @@ struct Pool {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// pinned staging per slot: inputs x_lo, x_hi, u_lo, u_hi (2 * 512 + 2 doubles,
+// rounded up) and results r_lo at +0, r_hi at +512
+constexpr size_t kInDoubles = 1040;
+constexpr size_t kOutDoubles = 1024;
+
 }  // namespace
 
 namespace reach_srv {
@@ -122,6 +128,9 @@ struct Server {
     double* stage_out = nullptr;       // pinned host, slots x 2 x 512
     hipEvent_t copy_ev = nullptr;
     bool own_kstream = false;
+    double last_probe_us = 0;
+    double last_progress_us = 0;
+    double drain_limit_us = 60.0e6;
     int64_t grid = 0;
     int64_t idle_cycles = 0;
 
@@ -169,8 +178,8 @@ reach_status flags_to_status(unsigned f) {
 void finish(Server* S, int32_t k, unsigned flags) {
     Running& r = S->run[k];
     const int64_t n = r.n;
-    std::memcpy(r.r_lo, S->stage_out + (size_t)k * 1024, sizeof(double) * n);
-    std::memcpy(r.r_hi, S->stage_out + (size_t)k * 1024 + 512, sizeof(double) * n);
+    std::memcpy(r.r_lo, S->stage_out + (size_t)k * kOutDoubles, sizeof(double) * n);
+    std::memcpy(r.r_hi, S->stage_out + (size_t)k * kOutDoubles + 512, sizeof(double) * n);
     S->finished[r.ticket] = flags_to_status(flags);
     S->lat.push_back(now_us() - r.t_submit);
     S->alloc.release(r.pool_off, r.pool_len);
@@ -250,11 +259,21 @@ void service(Server* S) {
         }
         // 2. admission, in submission order
         batch.clear();
-        if (S->mode == 0 && !S->waiting.empty() && !S->free_slots.empty()) revive_kernel(S);
+        if (S->mode == 0) {
+            bool inflight = false;
+            for (int32_t k = 0; k < S->slots && !inflight; ++k)
+                inflight = S->run[k].used && S->run[k].published;
+            const double t = now_us();
+            if ((!S->waiting.empty() && !S->free_slots.empty()) ||
+                (inflight && t - S->last_probe_us > 1000.0)) {
+                S->last_probe_us = t;
+                revive_kernel(S);
+            }
+        }
         while (!S->waiting.empty() && !S->free_slots.empty()) {
             Waiting& w = S->waiting.front();
             const int64_t n = w.q.sys.n;
-            const size_t len = align256(2 * sizeof(double) * (size_t)n);
+            const size_t len = align256(sizeof(double) * (2 * (size_t)n + 2));
             if (S->mode == 0 && S->ring_busy[S->next_seq % S->ring_n] != 0) break;
             size_t off = 0;
             if (!S->alloc.alloc(len, &off)) break;
@@ -270,10 +289,12 @@ void service(Server* S) {
             r.r_lo = (double*)w.q.r_lo;
             r.r_hi = (double*)w.q.r_hi;
             r.t_submit = w.t_submit;
-            double* in = S->stage_in + (size_t)k * 1024;
+            double* in = S->stage_in + (size_t)k * kInDoubles;
             std::memcpy(in, w.lo.data(), sizeof(double) * n);
-            std::memcpy(in + 512, w.hi.data(), sizeof(double) * n);
-            double* dlo = (double*)(S->pool + off);
+            std::memcpy(in + n, w.hi.data(), sizeof(double) * n);
+            in[2 * n] = w.u_lo;
+            in[2 * n + 1] = w.u_hi;
+            double* dlo = (double*)(S->pool + off);   // pool block: x_lo, x_hi, u_lo, u_hi
             double* dhi = dlo + n;
             QDesc& d = r.d;
             std::memset(&d, 0, sizeof d);
@@ -283,23 +304,15 @@ void service(Server* S) {
             d.E = E;
             d.n = n;
             d.nsteps = w.q.nsteps;
-            if (w.q.sys.kind == REACH_CTM) {
-                d.prm[0] = w.q.sys.prm[0]; d.prm[1] = w.q.sys.prm[1];
-                d.prm[2] = w.q.sys.prm[1] * w.q.sys.prm[2]; d.prm[3] = w.q.sys.prm[3];
-            } else if (w.q.sys.kind == REACH_RD) {
-                d.prm[0] = 1.0 / (w.q.sys.prm[0] * w.q.sys.prm[0]);
-            } else {
-                for (int i = 0; i < 4; ++i) d.prm[i] = w.q.sys.prm[i];
-            }
-            d.u_lo = w.u_lo; d.u_hi = w.u_hi;
+            kernel_params(w.q.sys.kind, w.q.sys.prm, d.prm);
+            if (w.q.sys.n_in == 1) { d.p_lo = dlo + 2 * n; d.p_hi = dlo + 2 * n + 1; }
             d.h2 = w.q.dt / 2.0; d.dt = w.q.dt; d.dt6 = w.q.dt / 6.0;
             d.x_lo = dlo; d.x_hi = dhi;
-            d.r_lo = S->stage_out + (size_t)k * 1024;
-            d.r_hi = S->stage_out + (size_t)k * 1024 + 512;
+            d.r_lo = S->stage_out + (size_t)k * kOutDoubles;
+            d.r_hi = S->stage_out + (size_t)k * kOutDoubles + 512;
             d.tag = k;
             hipStream_t cs = S->mode == 0 ? S->copy : S->lstreams[k % S->lstreams.size()];
-            hipMemcpyAsync(dlo, in, sizeof(double) * n, hipMemcpyHostToDevice, cs);
-            hipMemcpyAsync(dhi, in + 512, sizeof(double) * n, hipMemcpyHostToDevice, cs);
+            hipMemcpyAsync(dlo, in, sizeof(double) * (2 * n + 2), hipMemcpyHostToDevice, cs);
             if (S->mode == 0) {
                 r.seq = S->next_seq++;
                 S->ring_busy[r.seq % S->ring_n] = r.seq + 1;
@@ -331,6 +344,19 @@ void service(Server* S) {
         bool busy = false;
         for (int32_t k = 0; k < S->slots; ++k) busy |= S->run[k].used;
         if (S->quit && !busy && S->waiting.empty()) break;
+        if (progress) S->last_progress_us = now_us();
+        if (S->quit && now_us() - S->last_progress_us > S->drain_limit_us) {
+            // bounded drain: whatever has not finished is reported as timed out
+            for (int32_t k = 0; k < S->slots; ++k) {
+                Running& r = S->run[k];
+                if (!r.used) continue;
+                S->finished[r.ticket] = REACH_E_TIMEOUT;
+                r.used = false;
+            }
+            for (auto& w : S->waiting) S->finished[w.ticket] = REACH_E_TIMEOUT;
+            S->waiting.clear();
+            break;
+        }
         if (!progress) {
             if (busy) {
                 lk.unlock();
@@ -369,7 +395,11 @@ reach_status reach_server_start(reach_ctx* c, void* pool, size_t pool_bytes, int
     S->grid = w > 0 ? w : std::min<int64_t>((int64_t)cus * 4, max_slots);
     double idle_s = 120.0;
     if (const char* e = std::getenv("REACH_SERVER_IDLE_S")) idle_s = std::max(1.0, std::atof(e));
-    S->idle_cycles = (int64_t)(idle_s * 100.0e6);   // wall_clock64 ticks at 100 MHz
+    int rate_khz = 0;   // wall_clock64 tick rate
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess ||
+        rate_khz <= 0)
+        rate_khz = 100000;
+    S->idle_cycles = (int64_t)(idle_s * 1000.0 * (double)rate_khz);
     bool ok = true;
     ok &= hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking) == hipSuccess;
     if (!S->kstream) {
@@ -379,9 +409,9 @@ reach_status reach_server_start(reach_ctx* c, void* pool, size_t pool_bytes, int
     ok &= hipHostMalloc((void**)&S->ring, sizeof(ServeSlot) * S->ring_n,
                         hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
     ok &= hipHostMalloc((void**)&S->stop, 256, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
-    ok &= hipHostMalloc((void**)&S->stage_in, sizeof(double) * 1024 * (size_t)max_slots,
+    ok &= hipHostMalloc((void**)&S->stage_in, sizeof(double) * kInDoubles * (size_t)max_slots,
                         hipHostMallocDefault) == hipSuccess;
-    ok &= hipHostMalloc((void**)&S->stage_out, sizeof(double) * 1024 * (size_t)max_slots,
+    ok &= hipHostMalloc((void**)&S->stage_out, sizeof(double) * kOutDoubles * (size_t)max_slots,
                         hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
     ok &= hipMalloc((void**)&S->dctl, 256) == hipSuccess;
     ok &= hipEventCreateWithFlags(&S->copy_ev, hipEventDisableTiming) == hipSuccess;
@@ -439,7 +469,7 @@ reach_status reach_submit(reach_ctx* c, const reach_query* q, uint64_t* ticket) 
     if (!(std::isfinite(q->dt) && q->dt > 0) || q->nsteps < 0) return REACH_E_INVAL;
     if (!q->x_lo || !q->x_hi || !q->r_lo || !q->r_hi) return REACH_E_INVAL;
     if (s.n_in == 1 && (!q->p_lo || !q->p_hi)) return REACH_E_INVAL;
-    const size_t len = align256(2 * sizeof(double) * (size_t)s.n);
+    const size_t len = align256(sizeof(double) * (2 * (size_t)s.n + 2));
     if (len > S->pool_bytes) return REACH_E_NOMEM;
     Waiting w;
     w.q = *q;
@@ -515,6 +545,9 @@ reach_status reach_server_stop(reach_ctx* c) {
         std::lock_guard<std::mutex> g(S->mu);
         S->draining = true;
         S->quit = true;
+        S->last_progress_us = now_us();
+        if (const char* e = std::getenv("REACH_SERVER_DRAIN_S"))
+            S->drain_limit_us = std::max(1.0, std::atof(e)) * 1.0e6;
     }
     S->cv.notify_one();
     S->th.join();                    // every admitted and waiting query has completed

@@ -1,0 +1,174 @@
+"""Batched small queries (persistent kernel, captured hipGraph) and the
+one-launch-per-query baseline: every result equals the query run alone."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.gpu_util import assert_rel, say, to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+R = pytest.importorskip("paper_2001_10635_amd")
+
+
+@pytest.fixture(scope="module")
+def rc():
+    r = R.Reach(0)
+    yield r
+    r.close()
+
+
+class Batch:
+    """Device buffers for a list of workload queries."""
+
+    def __init__(self, queries):
+        self.items = []
+        for q in queries:
+            p = q.problem
+            lo, hi = p.box()
+            pl, ph = p.inputs()
+            d = dict(p=p, lo=lo, hi=hi, pl=pl, ph=ph, x_lo=to_dev(lo), x_hi=to_dev(hi),
+                     r_lo=torch.full((p.n,), np.nan, dtype=torch.float64, device="cuda"),
+                     r_hi=torch.full((p.n,), np.nan, dtype=torch.float64, device="cuda"),
+                     p_lo=None if pl is None else to_dev(pl), p_hi=None if ph is None else to_dev(ph))
+            self.items.append(d)
+
+    def queries(self):
+        out = []
+        for d in self.items:
+            p = d["p"]
+            out.append(R.make_query(p.kind, p.n, p.prm, R.REACH_F64, d["x_lo"], d["x_hi"],
+                                    d["r_lo"], d["r_hi"], p.dt, p.nsteps, d["p_lo"], d["p_hi"],
+                                    n_in=p.n_in))
+        return out
+
+    def results(self):
+        return [(to_host(d["r_lo"]), to_host(d["r_hi"])) for d in self.items]
+
+    def clear(self):
+        for d in self.items:
+            d["r_lo"].fill_(np.nan)
+            d["r_hi"].fill_(np.nan)
+
+
+def alone(rc, d):
+    p = d["p"]
+    r_lo, r_hi = rc.embed(p.kind, p.prm, d["x_lo"], d["x_hi"], p.dt, p.nsteps, p_lo=d["p_lo"],
+                          p_hi=d["p_hi"])
+    assert rc.sync() == R.REACH_OK
+    return to_host(r_lo), to_host(r_hi)
+
+
+@pytest.fixture(scope="module")
+def mix():
+    return Batch(workloads.query_stream(400, 5.0e4, seed=4242))
+
+
+def test_batch_equals_alone_and_oracle(rc, mix):
+    qs = mix.queries()
+    nb = R.reach_batch_workspace_bytes(len(qs))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    say("batch 400 queries")
+    R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
+    assert rc.sync() == R.REACH_OK
+    got = mix.results()
+    for k, d in enumerate(mix.items):
+        a = alone(rc, d)
+        assert np.array_equal(got[k][0], a[0]) and np.array_equal(got[k][1], a[1]), f"query {k}"
+    for k in range(0, len(mix.items), 23):
+        d = mix.items[k]
+        p = d["p"]
+        o_lo, o_hi = oracle.embed_rk4(p.kind, p.prm, d["lo"], d["hi"], d["pl"], d["ph"], dt=p.dt,
+                                      nsteps=p.nsteps)
+        assert_rel(got[k][0], o_lo, 1e-12, f"query {k} lower")
+        assert_rel(got[k][1], o_hi, 1e-12, f"query {k} upper")
+
+
+def test_batch_graph_replays_match_eager(rc, mix):
+    """The captured graph (counter reset kernel, descriptor upload, worker) is
+    replayed with eager work and synchronisation in between; every replay
+    equals the eager result."""
+    qs = mix.queries()
+    nb = R.reach_batch_workspace_bytes(len(qs))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    mix.clear()
+    R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)        # eager (default stream, no graph)
+    assert rc.sync() == R.REACH_OK
+    ref = mix.results()
+    s = torch.cuda.Stream()
+    for rep in range(4):
+        mix.clear()
+        torch.cuda.synchronize()
+        say(f"graph replay {rep}")
+        with torch.cuda.stream(s):
+            R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, s)
+        assert rc.sync(s) == R.REACH_OK
+        x = torch.randn(1000, device="cuda").sum()      # eager work between replays
+        torch.cuda.synchronize()
+        got = mix.results()
+        for k in range(len(ref)):
+            assert np.array_equal(got[k][0], ref[k][0]) and np.array_equal(got[k][1], ref[k][1])
+
+
+def test_each_equals_batch(rc, mix):
+    qs = mix.queries()
+    nb = R.reach_batch_workspace_bytes(len(qs))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    mix.clear()
+    R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
+    assert rc.sync() == R.REACH_OK
+    ref = mix.results()
+    mix.clear()
+    say("one launch per query")
+    R.reach_embed_rk4_each(rc.ctx, qs, 8)
+    assert rc.sync() == R.REACH_OK
+    got = mix.results()
+    for k in range(len(ref)):
+        assert np.array_equal(got[k][0], ref[k][0]) and np.array_equal(got[k][1], ref[k][1])
+
+
+@pytest.mark.parametrize("waves", [1, 3, 64])
+def test_batch_wave_count_invariance(rc, mix, waves):
+    qs = mix.queries()[:60]
+    nb = R.reach_batch_workspace_bytes(len(qs))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    rc.set_option("batch.waves", waves)
+    try:
+        R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
+        assert rc.sync() == R.REACH_OK
+    finally:
+        rc.set_option("batch.waves", 0)
+    got = mix.results()[:60]
+    for k in range(60):
+        a = alone(rc, mix.items[k])
+        assert np.array_equal(got[k][0], a[0]) and np.array_equal(got[k][1], a[1])
+
+
+def test_batch_rejections_and_flags(rc):
+    p = workloads.small_problem(workloads.KIND_CTM, 600, 3, 10)
+    lo, hi = p.box()
+    x_lo, x_hi = to_dev(lo), to_dev(hi)
+    r = torch.empty(600, dtype=torch.float64, device="cuda")
+    q = R.make_query(p.kind, 600, p.prm, R.REACH_F64, x_lo, x_hi, r, r, p.dt, p.nsteps)
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    with pytest.raises(R.ReachError) as e:
+        R.reach_embed_rk4_batch(rc.ctx, [q], ws, 1 << 20, 0)
+    assert e.value.status == R.REACH_E_UNSUPPORTED
+    q32 = R.make_query(p.kind, 100, p.prm, R.REACH_F32, x_lo, x_hi, r, r, p.dt, p.nsteps)
+    with pytest.raises(R.ReachError) as e:
+        R.reach_embed_rk4_batch(rc.ctx, [q32], ws, 1 << 20, 0)
+    assert e.value.status == R.REACH_E_UNSUPPORTED
+    good = R.make_query(p.kind, 100, p.prm, R.REACH_F64, x_lo, x_hi, r, r, p.dt, p.nsteps)
+    with pytest.raises(R.ReachError) as e:
+        R.reach_embed_rk4_batch(rc.ctx, [good] * 10, ws, 16, 0)
+    assert e.value.status == R.REACH_E_NOMEM
+    bad = lo.copy()
+    bad[7] = np.inf
+    xb = to_dev(bad)
+    r2 = torch.empty(600, dtype=torch.float64, device="cuda")
+    qb = R.make_query(p.kind, 100, p.prm, R.REACH_F64, xb, x_hi, r2, r2[300:], p.dt, p.nsteps)
+    R.reach_embed_rk4_batch(rc.ctx, [good, qb], ws, 1 << 20, 0)
+    assert rc.sync() == R.REACH_E_NONFINITE
+    assert rc.sync() == R.REACH_OK

@@ -27,10 +27,10 @@ def rc():
 
 @pytest.fixture(autouse=True)
 def _reset_options(rc):
-    for k in ("embed.E", "embed.K"):
+    for k in ("embed.E", "embed.K", "embed.S"):
         rc.set_option(k, 0)
     yield
-    for k in ("embed.E", "embed.K"):
+    for k in ("embed.E", "embed.K", "embed.S"):
         rc.set_option(k, 0)
 
 
@@ -93,15 +93,20 @@ def test_embed_matches_oracle(rc, variant, n, dtype):
     assert_rel(g_hi, o_hi, rt, "upper")
 
 
-@pytest.mark.parametrize("E,K", [(1, 1), (2, 3), (4, 7), (8, 8), (16, 4)])
-@pytest.mark.parametrize("variant", ["ctm", "rd", "lin3", "lin3_cell"])
-def test_multitile_halos_match_oracle(rc, variant, E, K):
+@pytest.mark.parametrize("E,K,S", [(1, 1, 2), (2, 3, 2), (4, 7, 2), (8, 8, 2), (16, 4, 2),
+                                   (12, 5, 2), (1, 1, 1), (4, 3, 1), (8, 9, 1), (24, 11, 1),
+                                   (32, 6, 1)])
+@pytest.mark.parametrize("variant", ["ctm", "rd", "rd_cell", "lin3", "lin3_cell"])
+def test_multitile_halos_match_oracle(rc, variant, E, K, S):
     """Forced small tiles: many windows, cut edges, a masked last window."""
+    if S == 1 and variant.startswith("lin3"):
+        pytest.skip("the coupled LIN3 chain runs both sides per wave")
     n, nsteps = 3001, 29
     case = make_case(variant, n, np.float64, seed=77)
+    rc.set_option("embed.S", S)
     rc.set_option("embed.E", E)
     rc.set_option("embed.K", K)
-    say(f"multitile {variant} E={E} K={K}")
+    say(f"multitile {variant} E={E} K={K} S={S}")
     g_lo, g_hi, st = run_gpu(rc, *case, nsteps)
     assert st == R.REACH_OK
     o_lo, o_hi = run_oracle(*case, nsteps)
@@ -116,11 +121,15 @@ def test_tile_shape_invariance_is_bitwise(rc, variant, dtype):
     n, nsteps = 20011, 41
     case = make_case(variant, n, dtype, seed=5)
     outs = []
-    shapes = [(2, 1), (4, 3), (8, 8), (16, 8), (8, 1)] + ([(32, 16)] if dtype == np.float32 else [])
-    for E, K in shapes:
+    shapes = [(2, 1, 2), (4, 3, 2), (8, 8, 2), (12, 12, 2), (16, 8, 2), (8, 1, 1), (16, 10, 1),
+              (24, 12, 1), (32, 16, 1)]
+    if dtype == np.float32:
+        shapes += [(32, 16, 2), (48, 12, 1), (64, 20, 1)]
+    for E, K, S in shapes:
+        rc.set_option("embed.S", S)
         rc.set_option("embed.E", E)
         rc.set_option("embed.K", K)
-        say(f"shape {variant} E={E} K={K}")
+        say(f"shape {variant} E={E} K={K} S={S}")
         outs.append(run_gpu(rc, *case, nsteps)[:2])
     for lo, hi in outs[1:]:
         assert np.array_equal(lo, outs[0][0]) and np.array_equal(hi, outs[0][1])
@@ -144,10 +153,12 @@ def test_repeat_is_bitwise(rc):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+@pytest.mark.parametrize("S", [1, 2])
 @pytest.mark.parametrize("nsteps", [8, 16, 17, 40])
-def test_in_place_output(rc, nsteps):
+def test_in_place_output(rc, nsteps, S):
     """r may alias x, whatever the number of passes."""
     kind, prm, lo, hi, pl, ph, dt = make_case("ctm", 9000, np.float64, seed=11)
+    rc.set_option("embed.S", S)
     rc.set_option("embed.E", 4)
     rc.set_option("embed.K", 8)
     ref = run_gpu(rc, kind, prm, lo, hi, pl, ph, dt, nsteps)
@@ -164,10 +175,12 @@ def test_zero_steps_copies_box(rc):
     assert st == R.REACH_OK and np.array_equal(g_lo, lo) and np.array_equal(g_hi, hi)
 
 
-def test_nonfinite_and_order_reported(rc):
-    kind, prm, lo, hi, pl, ph, dt = make_case("rd", 1000, np.float64, seed=13)
+@pytest.mark.parametrize("S", [1, 2])
+def test_nonfinite_and_order_reported(rc, S):
+    kind, prm, lo, hi, pl, ph, dt = make_case("rd", 100000, np.float64, seed=13)
+    rc.set_option("embed.S", S)
     bad = lo.copy()
-    bad[500] = np.nan
+    bad[50000] = np.nan
     say("nan input")
     _, _, st = run_gpu(rc, kind, prm, bad, hi, pl, ph, dt, 5)
     assert st == R.REACH_E_NONFINITE
@@ -209,10 +222,10 @@ def test_invalid_arguments_rejected(rc):
 
 # --------------------------------------------------------- full-size configs
 
-def test_config0_ctm64_embedding(rc):
-    p = workloads.config(0)
+def test_ctm64_f64_embedding(rc):
+    p = workloads.ctm64_f64()
     lo, hi = p.box()
-    say("config 0 embedding")
+    say("ctm64 embedding")
     g_lo, g_hi, st = run_gpu(rc, p.kind, p.prm, lo, hi, None, None, p.dt, p.nsteps)
     assert st == R.REACH_OK
     o_lo, o_hi = oracle.embed_rk4(p.kind, p.prm, lo, hi, dt=p.dt, nsteps=p.nsteps)
@@ -234,38 +247,38 @@ def _windows(n, count, width, seed):
     return [(0, width), (n - width, n)] + [(int(s), int(s) + width) for s in starts]
 
 
-def test_config1_rd_2p26_f64_light_cone_windows(rc):
+def test_rd_2p26_f64_light_cone_windows(rc):
     """RD, n = 2^26, FP64, 1000 steps: the benchmark launch; sampled windows
     against the oracle's light-cone windows (bitwise equal to a whole-chain run)."""
-    p = workloads.config(1)
-    say("config 1 inputs")
+    p = workloads.rd_2p26_f64()
+    say("rd 2^26 inputs")
     lo, hi = p.box()
     pl, ph = p.inputs()
-    say("config 1 GPU run")
+    say("rd 2^26 GPU run")
     g_lo, g_hi, st = run_gpu(rc, p.kind, p.prm, lo, hi, pl, ph, p.dt, p.nsteps)
     assert st == R.REACH_OK
     del lo, hi
-    say("config 1 oracle windows")
+    say("rd 2^26 oracle windows")
     _window_check(g_lo, g_hi, p, _windows(p.n, 10, 512, 1), 1e-12, pl, ph)
 
 
-def test_config2_ctm_2p31_f32_light_cone_windows(rc):
+def test_ctm_2p31_f32_light_cone_windows(rc):
     """CTM, n = 2^31 (64-bit indexing), FP32, 200 steps, windows vs oracle."""
-    p = workloads.config(2)
+    p = workloads.ctm_2p31_f32()
     free, _ = torch.cuda.mem_get_info()
     need = 6 * p.n * 4 + (1 << 30)
     if free < need:
         pytest.skip(f"needs {need >> 30} GiB of free device memory")
-    say("config 2 inputs")
+    say("ctm 2^31 inputs")
     lo = np.empty(p.n, dtype=np.float32)
     hi = np.empty(p.n, dtype=np.float32)
     p.box(out=(lo, hi))
     x_lo, x_hi = torch.from_numpy(lo).to("cuda"), torch.from_numpy(hi).to("cuda")
     del lo, hi
-    say("config 2 GPU run")
+    say("ctm 2^31 GPU run")
     r_lo, r_hi = rc.embed(p.kind, p.prm, x_lo, x_hi, p.dt, p.nsteps, r_lo=x_lo, r_hi=x_hi)
     assert rc.sync() == R.REACH_OK
-    say("config 2 oracle windows")
+    say("ctm 2^31 oracle windows")
     wins = _windows(p.n, 8, 256, 2)
     # the last cells sit past 2^31 - 1: exercise 64-bit indexing explicitly
     wins.append((p.n - 4096, p.n - 3840))
@@ -279,3 +292,22 @@ def test_config2_ctm_2p31_f32_light_cone_windows(rc):
     del x_lo, x_hi, r_lo, r_hi
     rc._ws = None
     torch.cuda.empty_cache()
+
+
+def test_autotuner_picks_a_built_shape_and_keeps_results(rc):
+    """The autotuner's choice changes speed only: results stay bitwise equal."""
+    kind, prm, lo, hi, pl, ph, dt = make_case("rd", 300001, np.float64, seed=21)
+    x_lo, x_hi, p_lo, p_hi = to_dev(lo), to_dev(hi), to_dev(pl), to_dev(ph)
+    ref = run_gpu(rc, kind, prm, lo, hi, pl, ph, dt, 40)
+    sysd = R.make_system(kind, lo.size, prm, 1)
+    ws = torch.empty(2 * lo.size * 8, dtype=torch.uint8, device="cuda")
+    r_lo, r_hi = torch.empty_like(x_lo), torch.empty_like(x_hi)
+    say("autotune")
+    best = R.reach_autotune_embed(rc.ctx, sysd, R.REACH_F64, x_lo, x_hi, p_lo, p_hi, dt, 16,
+                                  r_lo, r_hi, ws, ws.numel())
+    assert best["E"] in (4, 8, 12, 16, 24, 32) and 8 * best["K"] < 64 * best["E"]
+    assert best["S"] in (1, 2) and best["fs_per_state_step"] > 0
+    plan = R.reach_plan_embed(rc.ctx, sysd, R.REACH_F64, 40)
+    assert (plan["E"], plan["K"], plan["S"]) == (best["E"], best["K"], best["S"])
+    got = run_gpu(rc, kind, prm, lo, hi, pl, ph, dt, 40)
+    assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])

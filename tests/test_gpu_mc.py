@@ -114,10 +114,10 @@ def test_mc_rejects_bad_requests(rc):
     assert rc.sync() == R.REACH_OK
 
 
-def test_config0_mc_1000_samples(rc):
-    p = workloads.config(0)
+def test_ctm64_f64_mc_1000_samples(rc):
+    p = workloads.ctm64_f64()
     lo, hi = p.box()
-    say("config 0 MC")
+    say("ctm64 MC")
     g_min, g_max, st = run_mc(rc, p.kind, p.prm, lo, hi, None, None, p.dt, p.nsteps, p.m, p.seed)
     assert st == R.REACH_OK
     o_min, o_max = oracle.montecarlo(p.kind, p.prm, lo, hi, dt=p.dt, nsteps=p.nsteps, m=p.m,
@@ -128,12 +128,12 @@ def test_config0_mc_1000_samples(rc):
     assert np.all(g_min >= e_lo) and np.all(g_max <= e_hi)
 
 
-def test_config3_mc_ctm4096_f32(rc):
+def test_mc_ctm4096_f32(rc):
     """n = 4096 FP32, 500 steps: oracle parity on a 256-sample prefix, then
     the full 2^20 samples with containment in the FP64 embedding box."""
-    p = workloads.config(3)
+    p = workloads.mc_ctm4096_f32()
     lo, hi = p.box()
-    say("config 3 MC prefix")
+    say("mc ctm4096 MC prefix")
     m_sub = 256
     g_min, g_max, st = run_mc(rc, p.kind, p.prm, lo, hi, None, None, p.dt, p.nsteps, m_sub, p.seed)
     assert st == R.REACH_OK
@@ -141,11 +141,11 @@ def test_config3_mc_ctm4096_f32(rc):
                                      dt=p.dt, nsteps=p.nsteps, m=m_sub, seed=p.seed, ubits=24)
     assert_rel(g_min, o_min, 1e-5, "min")
     assert_rel(g_max, o_max, 1e-5, "max")
-    say("config 3 MC full")
+    say("mc ctm4096 MC full")
     f_min, f_max, st = run_mc(rc, p.kind, p.prm, lo, hi, None, None, p.dt, p.nsteps, p.m, p.seed)
     assert st == R.REACH_OK
     assert np.all(f_min <= g_min) and np.all(f_max >= g_max)    # prefix nesting
-    say("config 3 FP64 embedding box")
+    say("mc ctm4096 FP64 embedding box")
     e_lo, e_hi, st = run_embed64(rc, p, lo, hi)
     assert st == R.REACH_OK
     o_elo, o_ehi = oracle.embed_rk4(p.kind, p.prm, lo.astype(np.float64), hi.astype(np.float64),

@@ -150,26 +150,39 @@ class Problem:
         return (np.array(self.p_lo, dtype=self.dtype), np.array(self.p_hi, dtype=self.dtype))
 
 
-def config(k: int) -> Problem:
-    """The five benchmark configurations, sizes as specified for this build."""
-    seed = BASE_SEED + k
-    if k == 0:
-        return Problem("ctm64_f64", KIND_CTM, 64, CTM_PRM, np.float64, CTM_RANDW,
-                       (CTM_BOX_A, CTM_BOX_D), seed, 0.01, 100, m=1000)
-    if k == 1:
-        return Problem("rd_2^26_f64", KIND_RD, 1 << 26, RD_PRM, np.float64, SIN, (RD_BOX_W,),
-                       seed, 0.1, 1000, n_in=1, p_lo=(RD_U[0],), p_hi=(RD_U[1],))
-    if k == 2:
-        return Problem("ctm_2^31_f32", KIND_CTM, 1 << 31, CTM_PRM, np.float32, CTM_RANDW,
-                       (CTM_BOX_A, CTM_BOX_D), seed, 0.01, 200)
-    if k == 3:
-        return Problem("mc_ctm4096_f32", KIND_CTM, 4096, CTM_PRM, np.float32, CTM_FIXEDW,
-                       (CTM_BOX_A, CTM_BOX_D), seed, 0.01, 500, m=1 << 20)
-    if k == 4:
-        return Problem("serve_mix_f64", KIND_CTM, 512, CTM_PRM, np.float64, CTM_RANDW,
-                       (CTM_BOX_A, CTM_BOX_D), seed, 0.01, 1000,
-                       extra=dict(nq=100000, rate=5.0e4))
-    raise KeyError(k)
+def ctm64_f64() -> Problem:
+    """Cell-transmission chain, n = 64, FP64, dt = 0.01, 100 RK4 steps, with a
+    1000-sample Monte Carlo check."""
+    return Problem("ctm64_f64", KIND_CTM, 64, CTM_PRM, np.float64, CTM_RANDW,
+                   (CTM_BOX_A, CTM_BOX_D), BASE_SEED + 0, 0.01, 100, m=1000)
+
+
+def rd_2p26_f64() -> Problem:
+    """Reaction-diffusion chain, n = 2^26, FP64, input u in [-0.1, 0.1],
+    dt = 0.1, 1000 RK4 steps."""
+    return Problem("rd_2^26_f64", KIND_RD, 1 << 26, RD_PRM, np.float64, SIN, (RD_BOX_W,),
+                   BASE_SEED + 1, 0.1, 1000, n_in=1, p_lo=(RD_U[0],), p_hi=(RD_U[1],))
+
+
+def ctm_2p31_f32() -> Problem:
+    """Cell-transmission chain, n = 2^31, FP32, dt = 0.01, 200 RK4 steps."""
+    return Problem("ctm_2^31_f32", KIND_CTM, 1 << 31, CTM_PRM, np.float32, CTM_RANDW,
+                   (CTM_BOX_A, CTM_BOX_D), BASE_SEED + 2, 0.01, 200)
+
+
+def mc_ctm4096_f32() -> Problem:
+    """Monte Carlo on the cell-transmission chain, n = 4096, box width 0.05c,
+    2^20 samples, FP32, dt = 0.01, 500 RK4 steps."""
+    return Problem("mc_ctm4096_f32", KIND_CTM, 4096, CTM_PRM, np.float32, CTM_FIXEDW,
+                   (CTM_BOX_A, CTM_BOX_D), BASE_SEED + 3, 0.01, 500, m=1 << 20)
+
+
+def serve_mix_f64() -> Problem:
+    """Parameters of the served query mix: 10^5 queries at 5e4/s (see
+    query_stream for the draws)."""
+    return Problem("serve_mix_f64", KIND_CTM, 512, CTM_PRM, np.float64, CTM_RANDW,
+                   (CTM_BOX_A, CTM_BOX_D), BASE_SEED + 4, 0.01, 1000,
+                   extra=dict(nq=100000, rate=5.0e4))
 
 
 def small_problem(kind: int, n: int, seed: int, nsteps: int, dtype=np.float64,
