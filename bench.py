@@ -27,11 +27,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 FP64_PEAK = 78.6e12          # FLOP/s, MI355X FP64 vector (FMA = 2 flops)
+FP32_PEAK = 157.3e12         # FLOP/s, MI355X FP32 vector (published, packed)
 # Algorithmic FP64 operations of one RK4 state-step of the RD chain (an FMA
 # counts 2): four right-hand sides of 8 (two adds, a scaling by 1/h^2, 2*y,
 # y^3 as two products, the input and the reaction term), three stage inputs
 # z + c K of 2, the weighted sum K1 + 2K2 + 2K3 + K4 of 5 and z + dt/6 * sum of 2.
 RD_FLOPS_PER_STATE_STEP = 45
+# The same count for the CTM chain: per right-hand side one flux (v*y, c - y,
+# w*(c - y), two minimum operations) and its difference with the neighbour's,
+# 6; plus 13 for the stage inputs and the update.
+CTM_OPS_PER_STATE_STEP = 37
 
 
 def log(msg):
@@ -46,19 +51,23 @@ def source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(per_launch_units: float):
-    """HBM bytes per launch from the committed PMC summary, if it matches the
-    current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "embed_tile_rd2p26_f64_pmc.json")
+def traffic_from_profile():
+    """HBM bytes per launch from the committed PMC summary of the embedding
+    pass, if it was taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "embed_tile_kernel_rd2p26_f64_pmc.txt")
     if not os.path.exists(path):
         return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != source_hash():
+        return None
     try:
-        d = json.load(open(path))
-    except Exception:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
         return None
-    if d.get("source_hash") != source_hash():
-        return None
-    return d.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(p, steps: int):
@@ -182,6 +191,84 @@ def query_mix(rc, R, torch, workloads, nq):
     return out
 
 
+def extra_ctm_2p31_f32(rc, R, torch, workloads, steps=2):
+    """CTM chain n = 2^31 FP32, 200 RK4 steps: the largest single-GPU embedding."""
+    p = workloads.ctm_2p31_f32()
+    lo = np.empty(p.n, dtype=np.float32)
+    hi = np.empty(p.n, dtype=np.float32)
+    t = time.perf_counter()
+    p.box(out=(lo, hi))
+    log(f"ctm 2^31 inputs in {time.perf_counter() - t:.1f} s")
+    x_lo = torch.from_numpy(lo).cuda()
+    x_hi = torch.from_numpy(hi).cuda()
+    del lo, hi
+    r_lo, r_hi = torch.empty_like(x_lo), torch.empty_like(x_hi)
+    sysd = R.make_system(p.kind, p.n, p.prm, 0)
+    nb = R.reach_workspace_bytes(rc.ctx, sysd, R.REACH_F32, 0)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+    plan = R.reach_plan_embed(rc.ctx, sysd, R.REACH_F32, p.nsteps)
+    run = lambda: R.reach_embed_rk4(rc.ctx, sysd, R.REACH_F32, x_lo, x_hi, None, None, 0.0, p.dt,
+                                    p.nsteps, r_lo, r_hi, ws, nb, None)
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    assert rc.sync() == R.REACH_OK
+    sec = e0.elapsed_time(e1) / 1e3 / steps
+    launch = sec / plan["passes"]
+    ops = 2.0 * p.n * plan["K"] * CTM_OPS_PER_STATE_STEP
+    byts = 4.0 * p.n * 4
+    out = {"workload": "CTM chain n=2^31 FP32, dt=0.01, 200 RK4 steps",
+           "state_steps_per_s": 2.0 * p.n * p.nsteps / sec, "seconds": round(sec, 4),
+           "plan": plan, "launch_us": round(launch * 1e6, 1),
+           "alu_frac_fp32_published": round(ops / launch / FP32_PEAK, 4),
+           "alu_frac_fp32_nonpacked": round(ops / launch / (FP32_PEAK / 2), 4),
+           "hbm_frac": round(byts / launch / HBM_PEAK, 4)}
+    del x_lo, x_hi, r_lo, r_hi, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def extra_mc_ctm4096(rc, R, torch, workloads, cpu_samples):
+    """Monte Carlo, CTM n = 4096 FP32, 2^20 samples, 500 RK4 steps."""
+    import oracle
+    p = workloads.mc_ctm4096_f32()
+    lo, hi = p.box()
+    x_lo, x_hi = torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda()
+    rc.montecarlo(p.kind, p.prm, x_lo, x_hi, p.dt, p.nsteps, 4096, p.seed)   # warm-up
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    mn, mx = rc.montecarlo(p.kind, p.prm, x_lo, x_hi, p.dt, p.nsteps, p.m, p.seed)
+    e1.record()
+    torch.cuda.synchronize()
+    assert rc.sync() == R.REACH_OK
+    sec = e0.elapsed_time(e1) / 1e3
+    cell_steps = float(p.n) * p.m * p.nsteps
+    ops = cell_steps * CTM_OPS_PER_STATE_STEP
+    out = {"workload": "Monte Carlo, CTM n=4096 FP32, 2^20 samples, dt=0.01, 500 RK4 steps",
+           "cell_steps_per_s": cell_steps / sec, "seconds": round(sec, 4),
+           "roofline": {"bound": "alu", "achieved": round(ops / sec / 1e12, 3),
+                        "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
+                        "frac": round(ops / sec / FP32_PEAK, 4),
+                        "frac_of_nonpacked_peak": round(ops / sec / (FP32_PEAK / 2), 4)}}
+    if cpu_samples:
+        t = time.perf_counter()
+        oracle.montecarlo(p.kind, p.prm, lo.astype(np.float64), hi.astype(np.float64), dt=p.dt,
+                          nsteps=p.nsteps, m=cpu_samples, seed=p.seed, ubits=24)
+        el = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": float(p.n) * cpu_samples * p.nsteps / el,
+                               "unit": "cell-steps/s", "kind": "oracle", "seconds": round(el, 2),
+                               "cores": int(os.environ.get("OMP_NUM_THREADS",
+                                                           os.cpu_count() or 1)),
+                               "sample": f"first {cpu_samples} of the 2^20 samples"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,10 +276,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--E", type=int, default=0, help="cells per lane (0 = tuned)")
     ap.add_argument("--K", type=int, default=0, help="RK4 steps per HBM pass (0 = tuned)")
+    ap.add_argument("--S", type=int, default=0, help="sides per wavefront, 1 or 2 (0 = tuned)")
     ap.add_argument("--cpu-steps", type=int, default=120)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-queries", action="store_true")
     ap.add_argument("--queries", type=int, default=100000)
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the FP32 2^31-cell embedding and the Monte Carlo run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
@@ -238,12 +328,14 @@ def main():
         rc.set_option("embed.E", args.E)
     if args.K:
         rc.set_option("embed.K", args.K)
+    if args.S:
+        rc.set_option("embed.S", args.S)
     sysd = R.make_system(p.kind, p.n, p.prm, p.n_in)
     nbytes = 2 * p.n * 8
     ws = rc.workspace(nbytes)
     stream = torch.cuda.current_stream()
     tuned = None
-    if not (args.E or args.K or args.no_tune):
+    if not (args.E or args.K or args.S or args.no_tune):
         tuned = R.reach_autotune_embed(rc.ctx, sysd, R.REACH_F64, x_lo, x_hi, p_lo, p_hi, p.dt,
                                        48, r_lo, r_hi, ws, nbytes, stream)
         log(f"autotuned {tuned}")
@@ -285,7 +377,7 @@ def main():
     hbm_ach = bytes_per_launch / launch_s
     alu_ach = flops_per_launch / launch_s
     hbm_frac, alu_frac = hbm_ach / HBM_PEAK, alu_ach / FP64_PEAK
-    traffic = traffic_from_profile(bytes_per_launch)
+    traffic = traffic_from_profile()
     if alu_frac >= hbm_frac:
         roof = {"bound": "alu", "achieved": round(alu_ach / 1e12, 3), "peak": FP64_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": traffic,
@@ -326,6 +418,13 @@ def main():
     queries = None
     if not args.no_queries:
         queries = query_mix(rc, R, torch, workloads, args.queries)
+    extra = {}
+    if not args.no_extra:
+        extra["embed_ctm_2p31_f32"] = extra_ctm_2p31_f32(rc, R, torch, workloads)
+        log(f"ctm 2^31 f32: {extra['embed_ctm_2p31_f32']}")
+        extra["mc_ctm4096_f32"] = extra_mc_ctm4096(rc, R, torch, workloads,
+                                                   0 if args.no_cpu else 64)
+        log(f"mc: {extra['mc_ctm4096_f32']}")
 
     cpu = None
     if not args.no_cpu:
@@ -356,6 +455,7 @@ def main():
         "hbm_stream_k1": stream_k1,
         "autotune": tuned,
         "queries": queries,
+        "other_rows": extra,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

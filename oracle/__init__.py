@@ -58,6 +58,10 @@ def lib():
         L.or_montecarlo.argtypes = [ctypes.c_int, vp, i64, i64, vp, vp, vp, vp, d, d, i64,
                                     i64, i64, ctypes.c_uint64, ctypes.c_int, vp, vp, vp]
         L.or_montecarlo.restype = ctypes.c_int
+        L.or_growth_bound.argtypes = [ctypes.c_int, vp, i64, i64, i64, i64, vp, vp, vp, vp,
+                                      d, d, i64, vp, vp]
+        L.or_growth_bound.restype = ctypes.c_int
+        L.or_contraction_matrix.argtypes = [ctypes.c_int, vp, vp]
         L.or_mc_samples.argtypes = [i64, d, d]
         L.or_mc_samples.restype = i64
         _lib = L
@@ -165,6 +169,32 @@ def montecarlo(kind, prm, x_lo, x_hi, p_lo=None, p_hi=None, t0=0.0, dt=0.01, nst
     if return_samples:
         return r_min, r_max, samples
     return r_min, r_max
+
+
+def growth_bound(kind, prm, x_lo, x_hi, p_lo=None, p_hi=None, t0=0.0, dt=0.01, nsteps=1,
+                 n_total=None, g0=0):
+    """Algorithm 2: contraction / growth-bound box; returns (r_lo, r_hi)."""
+    x_lo, x_hi = _f64(x_lo), _f64(x_hi)
+    length = x_lo.size
+    n_in = _nin(p_lo)
+    pl, ph = _f64(p_lo), _f64(p_hi if p_hi is not None else p_lo)
+    r_lo = np.empty(length, dtype=np.float64)
+    r_hi = np.empty(length, dtype=np.float64)
+    pr = _prm(prm)
+    rc = lib().or_growth_bound(kind, _p(pr), length if n_total is None else n_total, g0, length,
+                               n_in, _p(x_lo), _p(x_hi), _p(pl), _p(ph), t0, dt, nsteps,
+                               _p(r_lo), _p(r_hi))
+    if rc != 0:
+        raise RuntimeError(f"or_growth_bound failed ({rc})")
+    return r_lo, r_hi
+
+
+def contraction_matrix(kind, prm):
+    """(sub, diag, super, input factor) of the tridiagonal contraction matrix."""
+    pr = _prm(prm)
+    out = np.zeros(4, dtype=np.float64)
+    lib().or_contraction_matrix(kind, _p(pr), _p(out))
+    return tuple(out)
 
 
 def mc_samples(n: int, eps: float, delta: float) -> int:

@@ -25,6 +25,11 @@
  *   - Sec. 3.2, Algorithm 3 (mixed monotonicity: one RK4 run on the 2n-state
  *     embedding) and Algorithm 4 (Monte Carlo: m independent RK4 runs, then a
  *     per-dimension min / max).
+ *   - Sec. 2.1, contraction / growth bound, and Sec. 3.2, Algorithm 2: the
+ *     center of the box follows f at the center input; the half-width follows
+ *     the growth dynamics r' = C r + [p], with a contraction matrix C whose
+ *     diagonal bounds the Jacobian's diagonal and whose off-diagonal entries
+ *     bound the Jacobian's off-diagonal magnitudes; the box is [c - r, c + r].
  *   - Sec. 5.1, the n-link road traffic (cell transmission) chain.
  *
  * The case-study systems (the paper gives no decomposition functions; these
@@ -381,6 +386,74 @@ int or_montecarlo(int kind, const double* prm, int64_t n, int64_t n_in,
         free(z); free(mn); free(p);
     }
     return failed ? -2 : 0;
+}
+
+/* ------------------------------------------------------- growth bound --
+ * Contraction matrices (tridiagonal, as {sub, diag, super}) valid over all
+ * states, from the Jacobians of the chains:
+ *   CTM:  df_i/dy_i = dF_{i-1}/dy_i - dF_i/dy_i lies in {-w-v, -w, -v, 0}, so
+ *         C_ii = 0; |df_i/dy_{i-1}| <= v, |df_i/dy_{i+1}| <= w.
+ *   RD:   df_i/dy_i = -2/h^2 - 3 y_i^2 <= -2/h^2; off-diagonals 1/h^2.
+ *   LIN3: C = (|aL|, aD, |aR|).
+ * The input enters additively (RD) or through b (LIN3), so the half-width of
+ * the input interval enters r' with the factor |b| (1 for RD).
+ */
+static void or_contraction(int kind, const double* prm, double C[4])
+{
+    if (kind == OR_CTM) {
+        C[0] = prm[0]; C[1] = 0.0; C[2] = prm[1]; C[3] = 0.0;
+    } else if (kind == OR_RD) {
+        const double h = prm[0];
+        C[0] = 1.0 / (h * h); C[1] = -2.0 / (h * h); C[2] = 1.0 / (h * h); C[3] = 1.0;
+    } else {
+        C[0] = fabs(prm[0]); C[1] = prm[1]; C[2] = fabs(prm[2]); C[3] = fabs(prm[3]);
+    }
+}
+
+void or_contraction_matrix(int kind, const double* prm, double* C) { or_contraction(kind, prm, C); }
+
+/* Algorithm 2 on window cells [g0, g0+len) of an n_total-cell chain:
+ *   c0 = (lo + hi) / 2, r0 = (hi - lo) / 2         (one parallel loop)
+ *   p* = (p_lo + p_hi) / 2, [p] = (p_hi - p_lo) / 2
+ *   c1 = RK4^N of x' = f(x, p*) from c0
+ *   r1 = RK4^N of r' = C r + |b| [p] from r0 (zero ghosts, as the chain's)
+ *   box = [c1 - r1, c1 + r1]
+ */
+int or_growth_bound(int kind, const double* prm, int64_t n_total, int64_t g0, int64_t len,
+                    int64_t n_in, const double* x_lo, const double* x_hi,
+                    const double* p_lo, const double* p_hi, double t0, double dt,
+                    int64_t nsteps, double* r_lo, double* r_hi)
+{
+    (void)t0;
+    if (len < 1 || nsteps < 0) return -1;
+    const int64_t np = n_in > 0 ? n_in : 1;
+    double* buf = (double*)malloc(sizeof(double) * ((size_t)len * 7 + 2 * (size_t)np));
+    if (!buf) return -2;
+    double *c = buf, *r = buf + len, *w = buf + 2 * len;
+    double *pc = buf + 7 * len, *pr = pc + np;
+    int64_t i;
+    #pragma omp parallel for schedule(static)
+    for (i = 0; i < len; ++i) {
+        c[i] = (x_lo[i] + x_hi[i]) / 2.0;
+        r[i] = (x_hi[i] - x_lo[i]) / 2.0;
+    }
+    for (i = 0; i < np; ++i) {
+        pc[i] = n_in > 0 ? (p_lo[i] + p_hi[i]) / 2.0 : 0.0;
+        pr[i] = n_in > 0 ? (p_hi[i] - p_lo[i]) / 2.0 : 0.0;
+    }
+    or_sys S = {kind, prm, n_total, g0, len, n_in};
+    or_traj(&S, c, pc, dt, nsteps, w);                       /* center run */
+    double C[8] = {0};
+    or_contraction(kind, prm, C);
+    or_sys G = {OR_LIN3, C, n_total, g0, len, n_in};
+    or_traj(&G, r, pr, dt, nsteps, w);                       /* radius run */
+    #pragma omp parallel for schedule(static)
+    for (i = 0; i < len; ++i) {
+        r_lo[i] = c[i] - r[i];
+        r_hi[i] = c[i] + r[i];
+    }
+    free(buf);
+    return 0;
 }
 
 /* Sample count of the Monte Carlo guarantee (Sec. 2.1, Algorithm 4):

@@ -31,6 +31,12 @@ MUTATIONS = [
     ("rd_spacing_not_squared", [("/ (h * h)", "/ h")]),
     ("mc_wrong_stream", [("#define OR_MC_STREAM 2", "#define OR_MC_STREAM 1")]),
     ("mc_uniform_bits", [("ldexp((double)(w >> 11), -53)", "ldexp((double)(w >> 12), -52)")]),
+    ("gb_signed_offdiagonal", [("C[0] = fabs(prm[0]);", "C[0] = prm[0];")]),
+    ("gb_center_input_is_lower", [("pc[i] = n_in > 0 ? (p_lo[i] + p_hi[i]) / 2.0 : 0.0;",
+                                   "pc[i] = n_in > 0 ? p_lo[i] : 0.0;")]),
+    ("gb_radius_not_halved", [("r[i] = (x_hi[i] - x_lo[i]) / 2.0;", "r[i] = (x_hi[i] - x_lo[i]);")]),
+    ("gb_ctm_diagonal_negative", [("C[0] = prm[0]; C[1] = 0.0; C[2] = prm[1]; C[3] = 0.0;",
+                                   "C[0] = prm[0]; C[1] = -prm[0]; C[2] = prm[1]; C[3] = 0.0;")]),
 ]
 
 PINS = [
@@ -47,6 +53,10 @@ PINS = [
     pins.test_ctm_flux_uses_downstream_supply,
     pins.test_uniform_draw_layout,
     pins.test_mc_zero_steps_returns_extreme_draws,
+    pins.test_growth_bound_radius_exact_rational,
+    pins.test_growth_bound_equals_embedding_on_cooperative_linear_chain,
+    lambda: pins.test_contraction_matrix_bounds_the_jacobian(pins.oracle.CTM),
+    lambda: pins.test_contraction_matrix_bounds_the_jacobian(pins.oracle.RD),
 ]
 
 

@@ -436,3 +436,96 @@ def test_mc_probabilistic_guarantee_holds_statistically():
         fails += outside > eps
     # P(fails >= 15 | p <= 0.2, 30 trials) < 1e-4
     assert fails < 15
+
+
+# ------------------------------------------------------------ growth bound
+
+def test_growth_bound_equals_embedding_on_cooperative_linear_chain():
+    """For x' = A x + b u with A Metzler, the embedding's center and half-width
+    obey c' = A c + b u*, r' = A r + |b| [u], which is the growth bound with
+    C = A: both methods give the same box (Sec. 2.1)."""
+    rng = np.random.default_rng(14)
+    n = 30
+    coef = (0.4, -1.3, 0.25, -0.7)
+    lo = rng.uniform(-1, 1, n)
+    hi = lo + rng.uniform(0, 0.4, n)
+    pl, ph = [-0.2], [0.3]
+    g = oracle.growth_bound(oracle.LIN3, coef, lo, hi, pl, ph, dt=0.05, nsteps=60)
+    m = oracle.embed_rk4(oracle.LIN3, coef, lo, hi, pl, ph, dt=0.05, nsteps=60)
+    np.testing.assert_allclose(g[0], m[0], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(g[1], m[1], rtol=1e-12, atol=1e-13)
+
+
+def test_growth_bound_radius_exact_rational():
+    """The half-width follows RK4 of r' = C r + |b| [u] exactly (R(hC), S(hC))."""
+    n, coef = 4, (-0.5, -1.0, 0.75, -2.0)
+    lo = [0.5, -1.0, 0.25, 1.5]
+    hi = [0.75, -0.5, 1.25, 1.625]
+    pl, ph = [-0.25], [0.5]
+    h, N = 0.0625, 5
+    C = cf.tridiag(n, 0.5, -1.0, 0.75)
+    half_u = Fraction(1, 2) * (Fraction(0.5) - Fraction(-0.25))
+    r0 = [(Fraction(b) - Fraction(a)) / 2 for a, b in zip(lo, hi)]
+    r1 = cf.rk4_linear_exact(C, [Fraction(2) * half_u] * n, r0, h, N)
+    c1 = cf.rk4_linear_exact(cf.tridiag(n, -0.5, -1.0, 0.75),
+                             [Fraction(-2) * (Fraction(-0.25) + Fraction(0.5)) / 2] * n,
+                             [(Fraction(a) + Fraction(b)) / 2 for a, b in zip(lo, hi)], h, N)
+    g_lo, g_hi = oracle.growth_bound(oracle.LIN3, coef, lo, hi, pl, ph, dt=h, nsteps=N)
+    np.testing.assert_allclose(g_hi - g_lo, 2 * cf.to_float(r1), rtol=1e-14, atol=1e-14)
+    np.testing.assert_allclose((g_hi + g_lo) / 2, cf.to_float(c1), rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("kind", [oracle.CTM, oracle.RD])
+def test_contraction_matrix_bounds_the_jacobian(kind):
+    """C_ii >= J_ii and C_ij >= |J_ij| at random states (central differences)."""
+    prm = CTM_PRM if kind == oracle.CTM else (1.0,)
+    sub, diag, sup, _ = oracle.contraction_matrix(kind, prm)
+    rng = np.random.default_rng(15)
+    n, eps = 12, 1e-6
+    for trial in range(30):
+        y = rng.uniform(0, 40, n) if kind == oracle.CTM else rng.uniform(-2, 2, n)
+        p = None if kind == oracle.CTM else [0.05]
+        for j in range(n):
+            e = np.zeros(n)
+            e[j] = eps
+            col = (oracle.rhs(kind, prm, y + e, p, use_f=True)
+                   - oracle.rhs(kind, prm, y - e, p, use_f=True)) / (2 * eps)
+            assert col[j] <= diag + 1e-6
+            if j > 0:
+                assert abs(col[j - 1]) <= sup + 1e-6      # d f_{j-1} / d y_j
+            if j < n - 1:
+                assert abs(col[j + 1]) <= sub + 1e-6      # d f_{j+1} / d y_j
+
+
+@pytest.mark.parametrize("kind", [oracle.CTM, oracle.RD])
+def test_growth_bound_contains_embedding_and_samples(kind):
+    p = workloads.small_problem(kind, 48, 16, 80)
+    lo, hi = p.box()
+    pl, ph = p.inputs()
+    g = oracle.growth_bound(kind, p.prm, lo, hi, pl, ph, dt=p.dt, nsteps=p.nsteps)
+    m = oracle.embed_rk4(kind, p.prm, lo, hi, pl, ph, dt=p.dt, nsteps=p.nsteps)
+    assert np.all(g[0] <= m[0] + 1e-12) and np.all(g[1] >= m[1] - 1e-12)
+    _, _, S = oracle.montecarlo(kind, p.prm, lo, hi, pl, ph, dt=p.dt, nsteps=p.nsteps, m=200,
+                                seed=4, return_samples=True)
+    assert np.all(S >= g[0]) and np.all(S <= g[1])
+
+
+def test_growth_bound_degenerate_box_is_the_trajectory():
+    p = workloads.small_problem(oracle.CTM, 25, 17, 40)
+    lo, _ = p.box()
+    g = oracle.growth_bound(p.kind, p.prm, lo, lo, dt=p.dt, nsteps=p.nsteps)
+    traj = oracle.f_rk4(p.kind, p.prm, lo, None, dt=p.dt, nsteps=p.nsteps)
+    assert np.array_equal(g[0], traj) and np.array_equal(g[1], traj)
+
+
+def test_growth_bound_window_is_bitwise_whole_chain():
+    p = workloads.small_problem(oracle.RD, 600, 18, 20)
+    lo, hi = p.box()
+    pl, ph = p.inputs()
+    full = oracle.growth_bound(p.kind, p.prm, lo, hi, pl, ph, dt=p.dt, nsteps=p.nsteps)
+    a, b = 250, 300
+    r = 4 * p.nsteps
+    w = oracle.growth_bound(p.kind, p.prm, lo[a - r:b + r], hi[a - r:b + r], pl, ph, dt=p.dt,
+                            nsteps=p.nsteps, n_total=p.n, g0=a - r)
+    assert np.array_equal(w[0][r:r + b - a], full[0][a:b])
+    assert np.array_equal(w[1][r:r + b - a], full[1][a:b])
