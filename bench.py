@@ -278,6 +278,7 @@ def main():
     ap.add_argument("--K", type=int, default=0, help="RK4 steps per HBM pass (0 = tuned)")
     ap.add_argument("--S", type=int, default=0, help="sides per wavefront, 1 or 2 (0 = tuned)")
     ap.add_argument("--cpu-steps", type=int, default=120)
+    ap.add_argument("--cpu-mc-samples", type=int, default=4096)
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-queries", action="store_true")
     ap.add_argument("--queries", type=int, default=100000)
@@ -423,7 +424,7 @@ def main():
         extra["embed_ctm_2p31_f32"] = extra_ctm_2p31_f32(rc, R, torch, workloads)
         log(f"ctm 2^31 f32: {extra['embed_ctm_2p31_f32']}")
         extra["mc_ctm4096_f32"] = extra_mc_ctm4096(rc, R, torch, workloads,
-                                                   0 if args.no_cpu else 64)
+                                                   0 if args.no_cpu else args.cpu_mc_samples)
         log(f"mc: {extra['mc_ctm4096_f32']}")
 
     cpu = None

@@ -136,6 +136,7 @@ const char* reach_last_error(const reach_ctx* ctx);
      "embed.K"    steps fused per HBM pass (0 = tuned default)
      "embed.E"    cells per lane of the embedding kernel (0 = tuned default)
      "embed.S"    sides per wavefront, 1 or 2 (0 = tuned default)
+     "gb.E", "gb.K"  cells per lane / steps per pass of the growth-bound kernel
      "mc.waves"   resident waves of the Monte Carlo kernel (0 = default)
      "batch.waves" resident waves of the batch kernel (0 = default)
    Returns REACH_E_INVAL for an unknown key or a value out of range. */
@@ -200,6 +201,41 @@ reach_status reach_embed_rk4(reach_ctx* ctx, const reach_system* sys, reach_dtyp
                              double t0, double dt, int64_t nsteps,
                              void* r_lo, void* r_hi,
                              void* workspace, size_t workspace_bytes, void* stream);
+
+/* Reach tube: the embedding box after every `every` steps, as in the paper's
+ * vehicle study, which computes a reach set per time step (Sec. 5).  Slot k
+ * (0 <= k < nsteps / every) of tube_lo / tube_hi (device arrays of
+ * (nsteps / every) x n elements, slot-major) receives the box at step
+ * (k + 1) * every, bitwise equal to reach_embed_rk4 run for that many steps.
+ * nsteps must be a positive multiple of every.  Other arguments as
+ * reach_embed_rk4 (the same workspace). */
+reach_status reach_embed_rk4_tube(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
+                                  const void* x_lo, const void* x_hi,
+                                  const void* p_lo, const void* p_hi,
+                                  double t0, double dt, int64_t nsteps, int64_t every,
+                                  void* tube_lo, void* tube_hi,
+                                  void* workspace, size_t workspace_bytes, void* stream);
+
+/* -------------------------------------------------------- growth bound --
+ * Contraction / growth-bound box (Sec. 2.1, Algorithm 2): the center
+ * c = (x_lo + x_hi)/2 follows x' = f(x, p*) at the center input
+ * p* = (p_lo + p_hi)/2, the half-width r = (x_hi - x_lo)/2 follows the growth
+ * dynamics r' = C r + |b| [p] with [p] = (p_hi - p_lo)/2 and the tridiagonal
+ * contraction matrix C (C_ii >= J_ii, C_ij >= |J_ij| over all states):
+ *   CTM  C = (v, 0, w) (sub, diagonal, super), no input;
+ *   RD   C = (1/h^2, -2/h^2, 1/h^2), input factor 1;
+ *   LIN3 C = (|aL|, aD, |aR|), input factor |b|.
+ * Both runs use the same RK4 as reach_embed_rk4; the result is
+ * [c - r, c + r] in (r_lo, r_hi).  Arguments as reach_embed_rk4; workspace:
+ * reach_growth_bound_workspace_bytes bytes (4 n elements). */
+size_t reach_growth_bound_workspace_bytes(reach_ctx* ctx, const reach_system* sys,
+                                          reach_dtype dtype);
+reach_status reach_growth_bound(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
+                                const void* x_lo, const void* x_hi,
+                                const void* p_lo, const void* p_hi,
+                                double t0, double dt, int64_t nsteps,
+                                void* r_lo, void* r_hi,
+                                void* workspace, size_t workspace_bytes, void* stream);
 
 /* --------------------------------------------------------- Monte Carlo --
  * Monte Carlo box (Sec. 2.1, Algorithm 4) over samples s = s0 .. s0+m-1:

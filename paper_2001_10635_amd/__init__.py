@@ -87,6 +87,10 @@ def lib() -> ctypes.CDLL:
         "reach_montecarlo_range": ([vp, sysp, i32, vp, vp, vp, vp, d, d, i64, i64, i64, u64, vp,
                                     vp, vp, sz, vp], i32),
         "reach_mc_samples": ([i64, d, d], i64),
+        "reach_embed_rk4_tube": ([vp, sysp, i32, vp, vp, vp, vp, d, d, i64, i64, vp, vp, vp, sz,
+                                  vp], i32),
+        "reach_growth_bound_workspace_bytes": ([vp, sysp, i32], sz),
+        "reach_growth_bound": ([vp, sysp, i32, vp, vp, vp, vp, d, d, i64, vp, vp, vp, sz, vp], i32),
         "reach_batch_workspace_bytes": ([i64], sz),
         "reach_embed_rk4_batch": ([vp, qp, i64, vp, sz, vp], i32),
         "reach_embed_rk4_each": ([vp, qp, i64, i32], i32),
@@ -248,6 +252,33 @@ def reach_montecarlo_range(ctx, sys: reach_system, dtype: int, x_lo, x_hi, p_lo,
     return _chk(ctx, st, "reach_montecarlo_range")
 
 
+def reach_embed_rk4_tube(ctx, sys: reach_system, dtype: int, x_lo, x_hi, p_lo, p_hi, t0: float,
+                         dt: float, nsteps: int, every: int, tube_lo, tube_hi, workspace=None,
+                         workspace_bytes: int = 0, stream=None) -> int:
+    st = lib().reach_embed_rk4_tube(ctx, ctypes.byref(sys), int(dtype), _ptr(x_lo), _ptr(x_hi),
+                                    _ptr(p_lo), _ptr(p_hi), float(t0), float(dt), int(nsteps),
+                                    int(every), _ptr(tube_lo), _ptr(tube_hi), _ptr(workspace),
+                                    int(workspace_bytes), _stream(stream))
+    return _chk(ctx, st, "reach_embed_rk4_tube")
+
+
+def reach_growth_bound_workspace_bytes(ctx, sys: reach_system, dtype: int) -> int:
+    v = lib().reach_growth_bound_workspace_bytes(ctx, ctypes.byref(sys), int(dtype))
+    if v == ctypes.c_size_t(-1).value:
+        raise ReachError(REACH_E_INVAL, f"reach_growth_bound_workspace_bytes: {reach_last_error(ctx)}")
+    return int(v)
+
+
+def reach_growth_bound(ctx, sys: reach_system, dtype: int, x_lo, x_hi, p_lo, p_hi, t0: float,
+                       dt: float, nsteps: int, r_lo, r_hi, workspace=None, workspace_bytes: int = 0,
+                       stream=None) -> int:
+    st = lib().reach_growth_bound(ctx, ctypes.byref(sys), int(dtype), _ptr(x_lo), _ptr(x_hi),
+                                  _ptr(p_lo), _ptr(p_hi), float(t0), float(dt), int(nsteps),
+                                  _ptr(r_lo), _ptr(r_hi), _ptr(workspace), int(workspace_bytes),
+                                  _stream(stream))
+    return _chk(ctx, st, "reach_growth_bound")
+
+
 def reach_mc_samples(n: int, eps: float, delta: float) -> int:
     return int(lib().reach_mc_samples(int(n), float(eps), float(delta)))
 
@@ -399,6 +430,24 @@ class Reach:
         reach_montecarlo_range(self.ctx, sys, dtc, x_lo, x_hi, p_lo, p_hi, t0, dt, nsteps, s0, m,
                                seed, r_min, r_max, ws, nb, stream)
         return r_min, r_max
+
+    def growth_bound(self, kind, prm, x_lo, x_hi, dt, nsteps, p_lo=None, p_hi=None, t0=0.0,
+                     r_lo=None, r_hi=None, stream=None):
+        n = x_lo.numel()
+        n_in = 0 if p_lo is None else p_lo.numel()
+        dtc = dtype_code(x_lo.dtype)
+        _check_tensor(x_lo, "x_lo", x_lo.dtype, n, x_lo.device)
+        _check_tensor(x_hi, "x_hi", x_lo.dtype, n, x_lo.device)
+        if r_lo is None:
+            r_lo = torch.empty_like(x_lo)
+        if r_hi is None:
+            r_hi = torch.empty_like(x_hi)
+        sys = make_system(kind, n, prm, n_in)
+        nb = reach_growth_bound_workspace_bytes(self.ctx, sys, dtc)
+        ws = self.workspace(nb)
+        reach_growth_bound(self.ctx, sys, dtc, x_lo, x_hi, p_lo, p_hi, t0, dt, nsteps, r_lo, r_hi,
+                           ws, nb, stream)
+        return r_lo, r_hi
 
     def sync(self, stream=None) -> int:
         return reach_sync(self.ctx, stream)

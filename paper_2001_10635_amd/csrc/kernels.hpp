@@ -49,6 +49,29 @@ int embed_max_E(int dtype, int S);
 hipError_t launch_order_check(int dtype, const void* lo, const void* hi, int64_t n,
                               unsigned int* status, hipStream_t stream);
 
+// One pass of the growth-bound method: tiles [0, W) advance the center, tiles
+// [W, 2W) the half-width; `first` forms them from the box (x_lo, x_hi).
+struct GbPass {
+    const void* x_lo;
+    const void* x_hi;
+    const void* src_c;
+    const void* src_r;
+    void* dst_c;
+    void* dst_r;
+    const void* p_lo;
+    const void* p_hi;
+    int64_t n, W, OUT, ksteps;
+    int32_t H, first, per_xcd, pad;
+    double prm[5];     // the system (kernel_params)
+    double prm_r[5];   // the growth dynamics: {C_sub, C_diag, C_sup, |b|}
+    double h2, dt, dt6;
+};
+hipError_t launch_gb(int kind, int mode, int dtype, int E, const GbPass& a, int64_t grid,
+                     hipStream_t stream);
+hipError_t launch_gb_combine(int dtype, const void* c, const void* r, int64_t n, void* lo,
+                             void* hi, unsigned int* status, hipStream_t stream);
+bool gb_has_E(int E);
+
 struct McArgs {
     const void* x_lo;
     const void* x_hi;

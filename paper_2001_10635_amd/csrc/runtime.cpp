@@ -145,7 +145,7 @@ struct EmbedPlan {
 // autotuner or its cache).  Cooperative chains run one side per wave.
 TuneEntry default_tune(int kind, int dtype) {
     if (kind == REACH_LIN3) return dtype == REACH_F64 ? TuneEntry{12, 12, 2} : TuneEntry{16, 8, 2};
-    return dtype == REACH_F64 ? TuneEntry{24, 12, 1} : TuneEntry{48, 12, 1};
+    return dtype == REACH_F64 ? TuneEntry{24, 20, 1} : TuneEntry{48, 12, 1};
 }
 
 int n_bucket(int64_t n) {
@@ -309,7 +309,7 @@ const char* reach_last_error(const reach_ctx* c) { return c ? c->err.c_str() : "
 reach_status reach_set_option(reach_ctx* c, const char* key, int64_t value) {
     if (!c || !key) return REACH_E_INVAL;
     static const char* keys[] = {"embed.K", "embed.E", "embed.S", "mc.waves", "batch.waves",
-                                 "serve.mode", "serve.waves"};
+                                 "serve.mode", "serve.waves", "gb.E", "gb.K"};
     bool known = false;
     for (const char* k : keys) known |= (std::strcmp(k, key) == 0);
     if (!known) return fail(c, REACH_E_INVAL, "unknown option %s", key);
@@ -454,6 +454,35 @@ reach_status reach_embed_rk4(reach_ctx* c, const reach_system* s, reach_dtype dt
 }
 
 
+reach_status reach_embed_rk4_tube(reach_ctx* c, const reach_system* s, reach_dtype dtype,
+                                  const void* x_lo, const void* x_hi, const void* p_lo,
+                                  const void* p_hi, double t0, double dt, int64_t nsteps,
+                                  int64_t every, void* tube_lo, void* tube_hi, void* ws,
+                                  size_t ws_bytes, void* stream) {
+    if (!c) return REACH_E_INVAL;
+    reach_status st = check_system(c, s, dtype);
+    if (st != REACH_OK) return st;
+    if (every < 1 || nsteps < 1 || nsteps % every != 0)
+        return fail(c, REACH_E_INVAL, "nsteps must be a positive multiple of every");
+    if (!tube_lo || !tube_hi) return fail(c, REACH_E_INVAL, "NULL tube pointer");
+    const size_t bytes = (size_t)s->n * dsize(dtype);
+    const int64_t slots = nsteps / every;
+    const void* src_lo = x_lo;
+    const void* src_hi = x_hi;
+    for (int64_t k = 0; k < slots; ++k) {
+        void* dlo = (char*)tube_lo + (size_t)k * bytes;
+        void* dhi = (char*)tube_hi + (size_t)k * bytes;
+        // each slot continues from the previous one: resumed runs are bitwise
+        // the same as one run
+        st = reach_embed_rk4(c, s, dtype, src_lo, src_hi, p_lo, p_hi, t0 + (double)(k * every) * dt,
+                             dt, every, dlo, dhi, ws, ws_bytes, stream);
+        if (st != REACH_OK) return st;
+        src_lo = dlo;
+        src_hi = dhi;
+    }
+    return REACH_OK;
+}
+
 reach_status reach_autotune_embed(reach_ctx* c, const reach_system* s, reach_dtype dtype,
                                   const void* x_lo, const void* x_hi, const void* p_lo,
                                   const void* p_hi, double dt, int64_t trial_steps, void* r_lo,
@@ -572,6 +601,110 @@ int64_t reach_mc_samples(int64_t n, double eps, double delta) {
     const double m = std::ceil((nn / eps) * std::log(nn / delta));
     if (!(m < 9.0e18)) return -1;
     return (int64_t)m;
+}
+
+}  // extern "C"
+
+
+// ---------------------------------------------------------- growth bound --
+namespace {
+
+void contraction_params(const reach_system* s, double out[5]) {
+    for (int i = 0; i < 5; ++i) out[i] = 0.0;
+    if (s->kind == REACH_CTM) {
+        out[0] = s->prm[0]; out[1] = 0.0; out[2] = s->prm[1]; out[3] = 0.0;
+    } else if (s->kind == REACH_RD) {
+        const double h2 = s->prm[0] * s->prm[0];
+        out[0] = 1.0 / h2; out[1] = -2.0 / h2; out[2] = 1.0 / h2; out[3] = 1.0;
+    } else {
+        out[0] = std::fabs(s->prm[0]); out[1] = s->prm[1]; out[2] = std::fabs(s->prm[2]);
+        out[3] = std::fabs(s->prm[3]);
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t reach_growth_bound_workspace_bytes(reach_ctx* c, const reach_system* s, reach_dtype dtype) {
+    if (!c || check_system(c, s, dtype) != REACH_OK) return (size_t)-1;
+    return (size_t)4 * (size_t)s->n * dsize(dtype);
+}
+
+reach_status reach_growth_bound(reach_ctx* c, const reach_system* s, reach_dtype dtype,
+                                const void* x_lo, const void* x_hi, const void* p_lo,
+                                const void* p_hi, double t0, double dt, int64_t nsteps,
+                                void* r_lo, void* r_hi, void* ws, size_t ws_bytes, void* stream) {
+    if (!c) return REACH_E_INVAL;
+    reach_status st = check_system(c, s, dtype);
+    if (st != REACH_OK) return st;
+    if (!x_lo || !x_hi || !r_lo || !r_hi) return fail(c, REACH_E_INVAL, "NULL state pointer");
+    if (s->n_in > 0 && (!p_lo || !p_hi)) return fail(c, REACH_E_INVAL, "NULL input pointer");
+    if (!(std::isfinite(dt) && dt > 0.0)) return fail(c, REACH_E_INVAL, "dt must be finite and > 0");
+    if (!std::isfinite(t0)) return fail(c, REACH_E_INVAL, "t0 must be finite");
+    if (nsteps < 0) return fail(c, REACH_E_INVAL, "nsteps < 0");
+    const size_t bytes = (size_t)s->n * dsize(dtype);
+    if (!ws || ws_bytes < 4 * bytes) return fail(c, REACH_E_INVAL, "workspace of %zu bytes needed", 4 * bytes);
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t hs = (hipStream_t)stream;
+    // plan: one side per wave, as the one-side embedding tiles
+    int E = (int)opt_get(c, "gb.E");
+    int K = (int)opt_get(c, "gb.K");
+    if (E && !gb_has_E(E)) return fail(c, REACH_E_INVAL, "gb.E = %d not built", E);
+    const int64_t n = s->n;
+    bool single = false;
+    if (!E) {
+        for (int e : {1, 4, 8, 16, 24, 32})
+            if ((int64_t)64 * e >= n) { E = e; break; }
+        if (E && !K) single = true;
+        if (!E) E = dtype == REACH_F64 ? 24 : 32;
+    } else if ((int64_t)64 * E >= n && !K) {
+        single = true;
+    }
+    const int64_t span = (int64_t)64 * E;
+    GbPass a{};
+    a.x_lo = x_lo; a.x_hi = x_hi;
+    a.p_lo = s->n_in ? p_lo : nullptr;
+    a.p_hi = s->n_in ? p_hi : nullptr;
+    a.n = n;
+    kernel_prm(s, a.prm);
+    contraction_params(s, a.prm_r);
+    a.h2 = dt / 2.0; a.dt = dt; a.dt6 = dt / 6.0;
+    int64_t passes;
+    if (single) {
+        K = (int)std::min<int64_t>(std::max<int64_t>(nsteps, 1), INT32_MAX);
+        a.W = 1; a.OUT = 0; a.H = 0;
+        passes = 1;
+    } else {
+        if (!K) K = 12;
+        if ((int64_t)8 * K >= span) return fail(c, REACH_E_INVAL, "gb.K = %d too large for E = %d", K, E);
+        a.H = 4 * K;
+        a.OUT = span - 2 * a.H;
+        a.W = (n <= span) ? 1 : 1 + (n - span + a.OUT - 1) / a.OUT;
+        passes = std::max<int64_t>(1, (nsteps + K - 1) / K);
+    }
+    a.per_xcd = (int32_t)((2 * a.W + 7) / 8);
+    const int64_t grid = 8 * (int64_t)a.per_xcd;
+    // (c, r) ping-pong in the workspace; the last pass writes buffer A
+    char* A = (char*)ws;
+    char* B = (char*)ws + 2 * bytes;
+    const int mode = s->n_in > 1 ? 1 : 0;
+    const int dt_id = dtype == REACH_F64 ? 0 : 1;
+    int64_t done = 0;
+    for (int64_t p = 0; p < passes; ++p) {
+        char* dst = ((passes - 1 - p) % 2 == 0) ? A : B;
+        char* src = ((passes - 1 - p) % 2 == 0) ? B : A;
+        a.first = (p == 0) ? 1 : 0;
+        a.src_c = src; a.src_r = src + bytes;
+        a.dst_c = dst; a.dst_r = dst + bytes;
+        a.ksteps = std::min<int64_t>(K, nsteps - done);
+        hipError_t e = launch_gb(s->kind, mode, dt_id, E, a, grid, hs);
+        if (e != hipSuccess) return hip_fail(c, e, "growth-bound kernel launch");
+        done += a.ksteps;
+    }
+    hipError_t e = launch_gb_combine(dt_id, A, A + bytes, n, r_lo, r_hi, c->status, hs);
+    if (e != hipSuccess) return hip_fail(c, e, "growth-bound combine launch");
+    return REACH_OK;
 }
 
 }  // extern "C"

@@ -311,3 +311,27 @@ def test_autotuner_picks_a_built_shape_and_keeps_results(rc):
     assert (plan["E"], plan["K"], plan["S"]) == (best["E"], best["K"], best["S"])
     got = run_gpu(rc, kind, prm, lo, hi, pl, ph, dt, 40)
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
+
+
+@pytest.mark.parametrize("variant,n", [("ctm", 7), ("rd", 40000), ("lin3", 3000)])
+def test_reach_tube_slots_equal_single_runs(rc, variant, n):
+    """Slot k of the tube is the box after (k+1)*every steps, bitwise."""
+    kind, prm, lo, hi, pl, ph, dt = make_case(variant, n, np.float64, seed=31)
+    every, slots = 9, 5
+    x_lo, x_hi = to_dev(lo), to_dev(hi)
+    dev = lambda a: None if a is None else to_dev(a)
+    sysd = R.make_system(kind, n, prm, 0 if pl is None else pl.size)
+    tube_lo = torch.empty(slots * n, dtype=torch.float64, device="cuda")
+    tube_hi = torch.empty_like(tube_lo)
+    ws = torch.empty(2 * n * 8, dtype=torch.uint8, device="cuda")
+    say(f"tube {variant} n={n}")
+    R.reach_embed_rk4_tube(rc.ctx, sysd, R.REACH_F64, x_lo, x_hi, dev(pl), dev(ph), 0.0, dt,
+                           every * slots, every, tube_lo, tube_hi, ws, ws.numel())
+    assert rc.sync() == R.REACH_OK
+    t_lo, t_hi = to_host(tube_lo).reshape(slots, n), to_host(tube_hi).reshape(slots, n)
+    for k in range(slots):
+        g = run_gpu(rc, kind, prm, lo, hi, pl, ph, dt, (k + 1) * every)
+        assert np.array_equal(t_lo[k], g[0]) and np.array_equal(t_hi[k], g[1])
+    o_lo, o_hi = run_oracle(kind, prm, lo, hi, pl, ph, dt, 2 * every)
+    assert_rel(t_lo[1], o_lo, 1e-12, "slot 1 lower")
+    assert_rel(t_hi[1], o_hi, 1e-12, "slot 1 upper")
