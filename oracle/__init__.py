@@ -4,7 +4,8 @@ A plain, slow, obviously correct implementation of what the GPU library
 computes, written from the PIRK paper (arXiv 2001.10635): the mixed-monotone
 embedding system integrated by classical RK4 (Sec. 2.1, Algorithms 1 and 3)
 and the Monte Carlo batch of sampled RK4 trajectories with its per-dimension
-min / max (Sec. 2.1, Algorithm 4).  See ``oracle.c`` for the equations.
+min / max (Sec. 2.1, Algorithm 4), the growth-bound method (Algorithm 2), on
+the chain systems and the 3-D heat diffusion case study (Sec. 5).  See ``oracle.c`` for the equations.
 
 Only the tests, the smoke check and the benchmark's CPU-baseline leg use this
 package.  It shares no code with the GPU library and does not import it.
@@ -21,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-CTM, RD, LIN3 = 1, 2, 3
+CTM, RD, LIN3, HEAT3D = 1, 2, 3, 4
 
 
 def build(verbose: bool = False) -> str:
@@ -53,6 +54,8 @@ def lib():
         L.or_embed_rk4.argtypes = [ctypes.c_int, vp, i64, i64, i64, i64, vp, vp, vp, vp,
                                    d, d, i64, vp, vp]
         L.or_embed_rk4.restype = ctypes.c_int
+        L.or_embed_rk4_grid.argtypes = [vp, vp, vp, vp, vp, d, i64, vp, vp]
+        L.or_embed_rk4_grid.restype = ctypes.c_int
         L.or_f_rk4.argtypes = [ctypes.c_int, vp, i64, i64, vp, vp, d, d, i64, vp]
         L.or_f_rk4.restype = ctypes.c_int
         L.or_montecarlo.argtypes = [ctypes.c_int, vp, i64, i64, vp, vp, vp, vp, d, d, i64,
@@ -136,6 +139,51 @@ def embed_rk4(kind, prm, x_lo, x_hi, p_lo=None, p_hi=None, t0=0.0, dt=0.01, nste
     if rc != 0:
         raise RuntimeError(f"or_embed_rk4 failed ({rc})")
     return r_lo, r_hi
+
+
+def heat3d_prm(nx, ny, nz, alpha, dx):
+    """Parameters of the 3-D heat system: grid extents, diffusivity, spacing."""
+    return [float(nx), float(ny), float(nz), float(alpha), float(dx)]
+
+
+def embed_rk4_grid(prm, x_lo, x_hi, org, dim, dt=0.01, nsteps=1):
+    """Algorithm 3 on the window box [org, org + dim) of a 3-D heat grid.
+
+    x_lo / x_hi hold the window's cells (x fastest).  Cells farther than
+    4 nsteps from every cut face are bitwise those of a whole-grid run.
+    """
+    x_lo, x_hi = _f64(x_lo), _f64(x_hi)
+    o = np.asarray(org, dtype=np.int64)
+    dm = np.asarray(dim, dtype=np.int64)
+    length = int(np.prod(dm))
+    assert x_lo.size == length and x_hi.size == length
+    r_lo = np.empty(length, dtype=np.float64)
+    r_hi = np.empty(length, dtype=np.float64)
+    pr = _prm(prm)
+    rc = lib().or_embed_rk4_grid(_p(pr), _p(o), _p(dm), _p(x_lo), _p(x_hi), dt, nsteps,
+                                 _p(r_lo), _p(r_hi))
+    if rc != 0:
+        raise RuntimeError(f"or_embed_rk4_grid failed ({rc})")
+    return r_lo, r_hi
+
+
+def heat3d_window(prm, box_fn, a, b, nsteps, dt=0.01):
+    """Output cells of the box [a, b) (per-axis (x, y, z) bounds) of a
+    whole-grid 3-D heat embedding run, from the light cone.
+
+    ``box_fn(org, dim)`` returns the input cells (lo, hi) of the box
+    [org, org + dim), x fastest.  Returns (r_lo, r_hi) of shape (z, y, x).
+    """
+    G = [int(prm[0]), int(prm[1]), int(prm[2])]
+    r = 4 * nsteps
+    org = [max(0, a[d] - r) for d in range(3)]
+    end = [min(G[d], b[d] + r) for d in range(3)]
+    dim = [end[d] - org[d] for d in range(3)]
+    x_lo, x_hi = box_fn(org, dim)
+    r_lo, r_hi = embed_rk4_grid(prm, x_lo, x_hi, org, dim, dt, nsteps)
+    sl = tuple(slice(a[d] - org[d], b[d] - org[d]) for d in (2, 1, 0))
+    shp = (dim[2], dim[1], dim[0])
+    return r_lo.reshape(shp)[sl], r_hi.reshape(shp)[sl]
 
 
 def f_rk4(kind, prm, x0, p=None, t0=0.0, dt=0.01, nsteps=1):

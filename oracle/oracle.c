@@ -30,7 +30,8 @@
  *     the growth dynamics r' = C r + [p], with a contraction matrix C whose
  *     diagonal bounds the Jacobian's diagonal and whose off-diagonal entries
  *     bound the Jacobian's off-diagonal magnitudes; the box is [c - r, c + r].
- *   - Sec. 5.1, the n-link road traffic (cell transmission) chain.
+ *   - Sec. 5.1, the n-link road traffic (cell transmission) chain, and the
+ *     3-D heat diffusion case study of Sec. 5.
  *
  * The case-study systems (the paper gives no decomposition functions; these
  * are the tight ones for sign-stable Jacobians):
@@ -45,6 +46,11 @@
  *        0.  d_i = aD x_i + aL+ x_{i-1} + aL- xh_{i-1} + aR+ x_{i+1}
  *                + aR- xh_{i+1} + b+ p_i + b- ph_i, with a+ = max(a, 0),
  *        a- = min(a, 0).
+ *   HEAT3D (nx, ny, nz, alpha, dx):  the heat diffusion case study (Sec. 5):
+ *        the heat equation on an nx * ny * nz grid, second differences along
+ *        each axis scaled by alpha / dx^2, insulated faces except x = nx - 1,
+ *        which touches an outside held at temperature 0.  Linear with
+ *        non-negative off-diagonal entries (cooperative), so d = f.  No inputs.
  * Inputs: n_in = 0 (none), 1 (one scalar shared by all cells) or n (per cell).
  *
  * Sub-domains ("windows"): every routine works on cells [g0, g0+len) of an
@@ -62,7 +68,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { OR_CTM = 1, OR_RD = 2, OR_LIN3 = 3 };
+enum { OR_CTM = 1, OR_RD = 2, OR_LIN3 = 3, OR_HEAT3D = 4 };
 
 /* ------------------------------------------------------------------ RNG --
  * Philox4x64-10 (Salmon et al., SC'11), written from its published
@@ -117,7 +123,20 @@ typedef struct {
     const double* prm;
     int64_t n_total, g0, len;
     int64_t n_in;
+    /* HEAT3D only: the window is the box of grid cells [org, org + dim) along
+       (x, y, z); left zero, it is the whole grid. */
+    int64_t org[3], dim[3];
 } or_sys;
+
+/* Fill in the whole-grid window of a HEAT3D system (no-op for chains). */
+static void or_grid_default(or_sys* S)
+{
+    if (S->kind != OR_HEAT3D || S->dim[0] > 0) return;
+    S->org[0] = S->org[1] = S->org[2] = 0;
+    S->dim[0] = (int64_t)S->prm[0];
+    S->dim[1] = (int64_t)S->prm[1];
+    S->dim[2] = (int64_t)S->prm[2];
+}
 
 static double or_min2(double a, double b) { return a < b ? a : b; }
 static double or_min3(double a, double b, double c) { return or_min2(or_min2(a, b), c); }
@@ -152,10 +171,46 @@ static double or_ctm_flux(const or_sys* S, const double* y, int64_t i)
     return or_min3(v * yi, w * (c - yn), q);
 }
 
+/* 3-D heat diffusion (Sec. 5, heat diffusion case study): the heat equation
+   on a box of nx * ny * nz grid cells of spacing dx, state = the temperature
+   of each cell, cell (a, b, c) stored at a + nx (b + ny c).  Each of the six
+   directions adds alpha / dx^2 (u_nb - u) (the second difference along each
+   axis).  A direction that leaves the grid adds nothing (insulated face),
+   except +x at a = nx - 1: that face touches the outside, held at
+   temperature 0, and adds alpha / dx^2 (0 - u).  Past a window's cut edge
+   the missing neighbour is taken as 0. */
+static double or_heat3d_f(const or_sys* S, const double* y, int64_t i)
+{
+    const int64_t G[3] = {(int64_t)S->prm[0], (int64_t)S->prm[1], (int64_t)S->prm[2]};
+    const double alpha = S->prm[3], dx = S->prm[4];
+    const int64_t wx = S->dim[0], wy = S->dim[1];
+    const int64_t a[3] = {i % wx, (i / wx) % wy, i / (wx * wy)};
+    const double u = y[i];
+    double sum = 0.0;
+    int d, s;
+    for (d = 0; d < 3; ++d) {
+        for (s = -1; s <= 1; s += 2) {
+            int64_t g = S->org[d] + a[d] + s;        /* neighbour's grid coordinate */
+            if (g < 0 || g >= G[d]) {
+                if (d == 0 && s == 1) sum += 0.0 - u;   /* the face open to the outside */
+                continue;                                /* insulated face */
+            }
+            int64_t b[3] = {a[0], a[1], a[2]};
+            b[d] += s;
+            double v = (b[d] < 0 || b[d] >= S->dim[d]) ? 0.0
+                                                      : y[b[0] + wx * (b[1] + wy * b[2])];
+            sum += v - u;
+        }
+    }
+    return alpha / (dx * dx) * sum;
+}
+
 /* f_i(y, p) of the original system at window cell i. */
 static double or_f(const or_sys* S, const double* y, const double* p, int64_t i)
 {
-    if (S->kind == OR_CTM) {
+    if (S->kind == OR_HEAT3D) {
+        return or_heat3d_f(S, y, i);
+    } else if (S->kind == OR_CTM) {
         return or_ctm_flux(S, y, i - 1) - or_ctm_flux(S, y, i);
     } else if (S->kind == OR_RD) {
         const double h = S->prm[0];
@@ -183,7 +238,7 @@ static double or_d(const or_sys* S, const double* x, const double* p,
         return aD * x[i] + or_pos(aL) * xm + or_neg(aL) * hm + or_pos(aR) * xp
              + or_neg(aR) * hp + or_pos(b) * or_input(S, p, i) + or_neg(b) * or_input(S, ph, i);
     }
-    /* CTM and RD are cooperative: d(x, p, xh, ph) = f(x, p). */
+    /* CTM, RD and HEAT3D are cooperative: d(x, p, xh, ph) = f(x, p). */
     (void)xh; (void)ph;
     return or_f(S, x, p, i);
 }
@@ -194,6 +249,7 @@ void or_rhs(int kind, const double* prm, int64_t n_total, int64_t g0, int64_t le
             const double* ph, int use_f, double* out)
 {
     or_sys S = {kind, prm, n_total, g0, len, n_in};
+    or_grid_default(&S);
     int64_t i;
     for (i = 0; i < len; ++i)
         out[i] = use_f ? or_f(&S, x, p, i) : or_d(&S, x, p, xh, ph, i);
@@ -229,14 +285,13 @@ static void or_axpy(int64_t len, const double* z, double a, const double* k, dou
     for (i = 0; i < len; ++i) out[i] = z[i] + a * k[i];
 }
 
-int or_embed_rk4(int kind, const double* prm, int64_t n_total, int64_t g0, int64_t len,
-                 int64_t n_in, const double* x_lo, const double* x_hi,
-                 const double* p_lo, const double* p_hi, double t0, double dt,
-                 int64_t nsteps, double* r_lo, double* r_hi)
+static int or_embed_core(const or_sys* Sp, const double* x_lo, const double* x_hi,
+                         const double* p_lo, const double* p_hi, double dt, int64_t nsteps,
+                         double* r_lo, double* r_hi)
 {
-    (void)t0;
+    const or_sys S = *Sp;
+    const int64_t len = S.len;
     if (len < 1 || nsteps < 0) return -1;
-    or_sys S = {kind, prm, n_total, g0, len, n_in};
     const int64_t L = 2 * len;   /* z = [x ; xh] stored back to back */
     double* buf = (double*)malloc(sizeof(double) * (size_t)L * 6);
     if (!buf) return -2;
@@ -262,6 +317,34 @@ int or_embed_rk4(int kind, const double* prm, int64_t n_total, int64_t g0, int64
     memcpy(r_hi, z + len, sizeof(double) * (size_t)len);
     free(buf);
     return 0;
+}
+
+int or_embed_rk4(int kind, const double* prm, int64_t n_total, int64_t g0, int64_t len,
+                 int64_t n_in, const double* x_lo, const double* x_hi,
+                 const double* p_lo, const double* p_hi, double t0, double dt,
+                 int64_t nsteps, double* r_lo, double* r_hi)
+{
+    (void)t0;
+    if (kind == OR_HEAT3D && (g0 != 0 || len != n_total)) return -1;  /* use or_embed_rk4_grid */
+    or_sys S = {kind, prm, n_total, g0, len, n_in};
+    or_grid_default(&S);
+    return or_embed_core(&S, x_lo, x_hi, p_lo, p_hi, dt, nsteps, r_lo, r_hi);
+}
+
+/* Algorithm 3 on the window box [org, org + dim) of a HEAT3D grid (no
+   inputs).  Cells farther than 4 * nsteps cells from every cut face of the
+   window are bitwise those of a whole-grid run. */
+int or_embed_rk4_grid(const double* prm, const int64_t* org, const int64_t* dim,
+                      const double* x_lo, const double* x_hi, double dt, int64_t nsteps,
+                      double* r_lo, double* r_hi)
+{
+    const int64_t n = (int64_t)prm[0] * (int64_t)prm[1] * (int64_t)prm[2];
+    const int64_t len = dim[0] * dim[1] * dim[2];
+    or_sys S = {OR_HEAT3D, prm, n, 0, len, 0, {org[0], org[1], org[2]}, {dim[0], dim[1], dim[2]}};
+    int d;
+    for (d = 0; d < 3; ++d)
+        if (dim[d] < 1 || org[d] < 0 || org[d] + dim[d] > (int64_t)prm[d]) return -1;
+    return or_embed_core(&S, x_lo, x_hi, NULL, NULL, dt, nsteps, r_lo, r_hi);
 }
 
 /* ----------------------------------------------------------- one trajectory
@@ -301,6 +384,7 @@ int or_f_rk4(int kind, const double* prm, int64_t n, int64_t n_in, const double*
     (void)t0;
     if (n < 1 || nsteps < 0) return -1;
     or_sys S = {kind, prm, n, 0, n, n_in};
+    or_grid_default(&S);
     double* w = (double*)malloc(sizeof(double) * (size_t)n * 5);
     if (!w) return -2;
     memcpy(out, x0, sizeof(double) * (size_t)n);
@@ -341,6 +425,7 @@ int or_montecarlo(int kind, const double* prm, int64_t n, int64_t n_in,
     (void)t0;
     if (n < 1 || m < 1 || nsteps < 0 || (n_in != 0 && n_in != 1 && n_in != n)) return -1;
     or_sys S = {kind, prm, n, 0, n, n_in};
+    or_grid_default(&S);
     int64_t j;
     for (j = 0; j < n; ++j) { r_min[j] = INFINITY; r_max[j] = -INFINITY; }
     int failed = 0;
@@ -389,8 +474,10 @@ int or_montecarlo(int kind, const double* prm, int64_t n, int64_t n_in,
 }
 
 /* ------------------------------------------------------- growth bound --
- * Contraction matrices (tridiagonal, as {sub, diag, super}) valid over all
- * states, from the Jacobians of the chains:
+ * Contraction matrices valid over all states.  HEAT3D is linear with
+ * non-negative off-diagonal entries, so its own matrix is one (the radius
+ * follows the heat equation too).  For the chains (tridiagonal, as
+ * {sub, diag, super}), from their Jacobians:
  *   CTM:  df_i/dy_i = dF_{i-1}/dy_i - dF_i/dy_i lies in {-w-v, -w, -v, 0}, so
  *         C_ii = 0; |df_i/dy_{i-1}| <= v, |df_i/dy_{i+1}| <= w.
  *   RD:   df_i/dy_i = -2/h^2 - 3 y_i^2 <= -2/h^2; off-diagonals 1/h^2.
@@ -441,11 +528,14 @@ int or_growth_bound(int kind, const double* prm, int64_t n_total, int64_t g0, in
         pc[i] = n_in > 0 ? (p_lo[i] + p_hi[i]) / 2.0 : 0.0;
         pr[i] = n_in > 0 ? (p_hi[i] - p_lo[i]) / 2.0 : 0.0;
     }
+    if (kind == OR_HEAT3D && (g0 != 0 || len != n_total)) { free(buf); return -1; }
     or_sys S = {kind, prm, n_total, g0, len, n_in};
+    or_grid_default(&S);
     or_traj(&S, c, pc, dt, nsteps, w);                       /* center run */
     double C[8] = {0};
     or_contraction(kind, prm, C);
     or_sys G = {OR_LIN3, C, n_total, g0, len, n_in};
+    if (kind == OR_HEAT3D) G = S;  /* linear and Metzler: C = the system matrix itself */
     or_traj(&G, r, pr, dt, nsteps, w);                       /* radius run */
     #pragma omp parallel for schedule(static)
     for (i = 0; i < len; ++i) {

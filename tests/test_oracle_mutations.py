@@ -37,6 +37,17 @@ MUTATIONS = [
     ("gb_radius_not_halved", [("r[i] = (x_hi[i] - x_lo[i]) / 2.0;", "r[i] = (x_hi[i] - x_lo[i]);")]),
     ("gb_ctm_diagonal_negative", [("C[0] = prm[0]; C[1] = 0.0; C[2] = prm[1]; C[3] = 0.0;",
                                    "C[0] = prm[0]; C[1] = -prm[0]; C[2] = prm[1]; C[3] = 0.0;")]),
+    ("heat_open_face_insulated", [("if (d == 0 && s == 1) sum += 0.0 - u;",
+                                   "if (d == 9 && s == 1) sum += 0.0 - u;")]),
+    ("heat_open_face_at_x0", [("if (d == 0 && s == 1) sum += 0.0 - u;",
+                               "if (d == 0 && s == -1) sum += 0.0 - u;")]),
+    ("heat_all_faces_open", [("continue;                                /* insulated face */",
+                              "sum += 0.0 - u; continue;")]),
+    ("heat_z_axis_dropped", [("for (d = 0; d < 3; ++d) {\n        for (s = -1;",
+                              "for (d = 0; d < 2; ++d) {\n        for (s = -1;")]),
+    ("heat_spacing_not_squared", [("alpha / (dx * dx) * sum", "alpha / dx * sum")]),
+    ("heat_axes_transposed", [("{i % wx, (i / wx) % wy, i / (wx * wy)}",
+                               "{i % wy, (i / wy) % wx, i / (wx * wy)}")]),
 ]
 
 PINS = [
@@ -57,6 +68,9 @@ PINS = [
     pins.test_growth_bound_equals_embedding_on_cooperative_linear_chain,
     lambda: pins.test_contraction_matrix_bounds_the_jacobian(pins.oracle.CTM),
     lambda: pins.test_contraction_matrix_bounds_the_jacobian(pins.oracle.RD),
+    lambda: pins.test_heat3d_trajectory_exact_rational((3, 2, 2)),
+    lambda: pins.test_heat3d_cosine_mode_decays_by_stability_polynomial((1, 2, 1)),
+    pins.test_heat3d_heat_leaves_only_through_the_open_face,
 ]
 
 

@@ -529,3 +529,121 @@ def test_growth_bound_window_is_bitwise_whole_chain():
                             nsteps=p.nsteps, n_total=p.n, g0=a - r)
     assert np.array_equal(w[0][r:r + b - a], full[0][a:b])
     assert np.array_equal(w[1][r:r + b - a], full[1][a:b])
+
+
+# ------------------------------------------------------- 3-D heat pins
+
+def _heat_A_by_edges(nx, ny, nz, a):
+    """The heat system's matrix built from its graph: one entry pair per edge
+    between face-adjacent cells, plus the loss of each cell on the open face
+    x = nx - 1 (Sec. 5, heat diffusion: insulated but for one face)."""
+    n = nx * ny * nz
+    A = cf.mat(n)
+    cells = [(i, j, k) for k in range(nz) for j in range(ny) for i in range(nx)]
+    idx = {c: t for t, c in enumerate(cells)}
+    for (i, j, k), p in idx.items():
+        for di, dj, dk in ((1, 0, 0), (0, 1, 0), (0, 0, 1)):
+            q = idx.get((i + di, j + dj, k + dk))
+            if q is not None:      # the edge p -- q: heat flows both ways
+                A[p][q] += a
+                A[q][p] += a
+                A[p][p] -= a
+                A[q][q] -= a
+        if i == nx - 1:
+            A[p][p] -= a
+    return A
+
+
+@pytest.mark.parametrize("dims", [(3, 2, 2), (2, 3, 1), (1, 1, 3), (1, 2, 1)])
+def test_heat3d_trajectory_exact_rational(dims):
+    """RK4 of the heat grid equals R(hA)^N x0 with A built edge by edge."""
+    nx, ny, nz = dims
+    alpha, dx, h, N = 0.375, 0.5, 0.0625, 3
+    a = Fraction(alpha) / (Fraction(dx) ** 2)
+    n = nx * ny * nz
+    x0 = [Fraction(((7 * t) % 11) - 5, 4) for t in range(n)]
+    A = _heat_A_by_edges(nx, ny, nz, a)
+    exact = cf.to_float(cf.rk4_linear_exact(A, [0] * n, x0, h, N))
+    prm = oracle.heat3d_prm(nx, ny, nz, alpha, dx)
+    got = oracle.f_rk4(oracle.HEAT3D, prm, [float(v) for v in x0], None, dt=h, nsteps=N)
+    np.testing.assert_allclose(got, exact, rtol=1e-14, atol=1e-14)
+
+
+@pytest.mark.parametrize("modes", [(0, 0, 0), (1, 2, 1), (2, 0, 3), (4, 3, 0)])
+def test_heat3d_cosine_mode_decays_by_stability_polynomial(modes):
+    """Separable eigenvectors of the grid operator: cos((i + 1/2) t) along x
+    with t = (m + 1/2) pi / (nx + 1/2) (insulated at x = 0, zero outside
+    x = nx - 1), cos((j + 1/2) m pi / ny) along the insulated y and z.  The
+    eigenvalue is alpha / dx^2 times the sum of 2 cos(t) - 2 over the axes,
+    and RK4 multiplies the mode by R(dt lambda) per step."""
+    nx, ny, nz = 9, 7, 5
+    alpha, dx, dt, N = 0.02, 0.1, 0.05, 30
+    mx, my, mz = modes
+    tx = (mx + 0.5) * np.pi / (nx + 0.5)
+    ty, tz = my * np.pi / ny, mz * np.pi / nz
+    i, j, k = np.arange(nx), np.arange(ny), np.arange(nz)
+    u0 = (np.cos((k[:, None, None] + 0.5) * tz) * np.cos((j[None, :, None] + 0.5) * ty)
+          * np.cos((i[None, None, :] + 0.5) * tx)).ravel()
+    lam = alpha / dx ** 2 * ((2 * np.cos(tx) - 2) + (2 * np.cos(ty) - 2) + (2 * np.cos(tz) - 2))
+    prm = oracle.heat3d_prm(nx, ny, nz, alpha, dx)
+    got = oracle.f_rk4(oracle.HEAT3D, prm, u0, None, dt=dt, nsteps=N)
+    np.testing.assert_allclose(got, cf.rk4_stability(lam * dt) ** N * u0, rtol=0,
+                               atol=1e-13 * np.max(np.abs(u0)))
+
+
+def test_heat3d_heat_leaves_only_through_the_open_face():
+    """Summed over the grid, the flows between cells cancel: d/dt of the total
+    heat is alpha / dx^2 times minus the sum of u over the face x = nx - 1."""
+    nx, ny, nz, alpha, dx = 6, 5, 4, 0.3, 0.25
+    rng = np.random.default_rng(21)
+    u = rng.uniform(0.0, 1.0, nx * ny * nz)
+    f = oracle.rhs(oracle.HEAT3D, oracle.heat3d_prm(nx, ny, nz, alpha, dx), u, use_f=True)
+    face = u.reshape(nz, ny, nx)[:, :, nx - 1].sum()
+    assert abs(f.sum() - (-alpha / dx ** 2 * face)) < 1e-11 * alpha / dx ** 2 * u.size
+
+
+def test_heat3d_embedding_is_two_trajectories_and_ordered():
+    """Off-diagonal entries alpha / dx^2 >= 0: cooperative, d = f, so the
+    embedding is RK4 of f from each corner, and stays ordered."""
+    nx, ny, nz = 8, 6, 5
+    prm = oracle.heat3d_prm(nx, ny, nz, 0.01, 0.1)
+    rng = np.random.default_rng(22)
+    lo = rng.uniform(0.0, 1.0, nx * ny * nz)
+    hi = lo + rng.uniform(0.0, 0.2, lo.size)
+    r_lo, r_hi = oracle.embed_rk4(oracle.HEAT3D, prm, lo, hi, dt=0.05, nsteps=40)
+    assert np.array_equal(r_lo, oracle.f_rk4(oracle.HEAT3D, prm, lo, None, dt=0.05, nsteps=40))
+    assert np.array_equal(r_hi, oracle.f_rk4(oracle.HEAT3D, prm, hi, None, dt=0.05, nsteps=40))
+    assert np.all(r_lo <= r_hi)
+
+
+def test_heat3d_growth_bound_equals_embedding():
+    """Linear and Metzler: the growth bound with C = A is the embedding's box."""
+    nx, ny, nz = 7, 4, 6
+    prm = oracle.heat3d_prm(nx, ny, nz, 0.01, 0.1)
+    rng = np.random.default_rng(23)
+    lo = rng.uniform(-1.0, 1.0, nx * ny * nz)
+    hi = lo + rng.uniform(0.0, 0.5, lo.size)
+    g = oracle.growth_bound(oracle.HEAT3D, prm, lo, hi, dt=0.05, nsteps=30)
+    m = oracle.embed_rk4(oracle.HEAT3D, prm, lo, hi, dt=0.05, nsteps=30)
+    np.testing.assert_allclose(g[0], m[0], rtol=1e-12, atol=1e-13)
+    np.testing.assert_allclose(g[1], m[1], rtol=1e-12, atol=1e-13)
+
+
+def test_heat3d_window_is_bitwise_whole_grid():
+    nx, ny, nz, nsteps = 30, 26, 22, 2
+    prm = oracle.heat3d_prm(nx, ny, nz, 0.01, 0.1)
+    rng = np.random.default_rng(24)
+    lo = rng.uniform(0.0, 1.0, nx * ny * nz)
+    hi = lo + 0.1
+    full = oracle.embed_rk4(oracle.HEAT3D, prm, lo, hi, dt=0.05, nsteps=nsteps)
+    L, H = lo.reshape(nz, ny, nx), hi.reshape(nz, ny, nx)
+
+    def box(o, d):
+        s = (slice(o[2], o[2] + d[2]), slice(o[1], o[1] + d[1]), slice(o[0], o[0] + d[0]))
+        return L[s].ravel(), H[s].ravel()
+
+    for a, b in [((0, 0, 0), (5, 4, 3)), ((12, 9, 10), (20, 15, 13)), ((25, 20, 17), (30, 26, 22))]:
+        w_lo, w_hi = oracle.heat3d_window(prm, box, a, b, nsteps, dt=0.05)
+        s = (slice(a[2], b[2]), slice(a[1], b[1]), slice(a[0], b[0]))
+        assert np.array_equal(w_lo, full[0].reshape(nz, ny, nx)[s])
+        assert np.array_equal(w_hi, full[1].reshape(nz, ny, nx)[s])

@@ -1,11 +1,13 @@
-"""Seeded synthetic workloads for interval reachability of the CTM and RD chains.
+"""Seeded synthetic workloads for interval reachability of the CTM and RD chains
+and the 3-D heat grid.
 
 This package only generates inputs (interval boxes, input intervals, query
 streams).  It contains none of the method's arithmetic, so it feeds both the
 FP64 oracle and the GPU library with bitwise-identical data.
 
 The case studies follow the paper's sections on the n-link road traffic model
-(cell transmission chain) and on large sparse systems; the paper publishes no
+(cell transmission chain), on large sparse systems and on heat diffusion in a
+cube; the paper publishes no
 data sets for them, so every box here is synthetic, seeded, and regenerable
 cell by cell (counter-based Philox4x64-10, see ``gen.c``).
 """
@@ -26,10 +28,10 @@ _lib = None
 BASE_SEED = 20010635
 
 # box recipes, same numbering as gen.c
-CTM_RANDW, CTM_FIXEDW, SIN = 0, 1, 2
+CTM_RANDW, CTM_FIXEDW, SIN, HEAT_CORNER = 0, 1, 2, 3
 
 # system kinds, same numbering as the C ABI
-KIND_CTM, KIND_RD, KIND_LIN3 = 1, 2, 3
+KIND_CTM, KIND_RD, KIND_LIN3, KIND_HEAT3D = 1, 2, 3, 4
 
 
 def build(verbose: bool = False) -> str:
@@ -96,7 +98,7 @@ def box(recipe: int, prm, seed: int, n: int, i0: int = 0, count: int | None = No
     if count is None:
         count = n - i0
     dtype = np.dtype(dtype)
-    prm_a = np.zeros(4, dtype=np.float64)
+    prm_a = np.zeros(8, dtype=np.float64)
     prm_a[: len(prm)] = prm
     if out is None:
         lo = np.empty(count, dtype=dtype)
@@ -183,6 +185,31 @@ def serve_mix_f64() -> Problem:
     return Problem("serve_mix_f64", KIND_CTM, 512, CTM_PRM, np.float64, CTM_RANDW,
                    (CTM_BOX_A, CTM_BOX_D), BASE_SEED + 4, 0.01, 1000,
                    extra=dict(nq=100000, rate=5.0e4))
+
+
+# 3-D heat grid (heat diffusion case study): unit cube, l cells per edge,
+# spacing 1/l.  The paper prints no diffusivity; HEAT_ALPHA keeps classical
+# RK4 at dt = 0.02 stable on the 1000^3 grid (spectral radius of the grid
+# operator times dt = 12 alpha l^2 dt = 2.4 < 2.78, RK4's real-axis limit).
+HEAT_ALPHA = 1.0e-5
+HEAT_BOX = (0.5, 1.0, 0.1, 0.01)     # heated corner fraction, T, half-width, cold width
+
+
+def heat3d_problem(nx: int, ny: int, nz: int, seed: int, nsteps: int, dtype=np.float64,
+                   dt: float = 0.02, alpha: float = HEAT_ALPHA, dx: float | None = None) -> Problem:
+    """A 3-D heat grid with the heated-corner box recipe."""
+    dx = 1.0 / max(nx, ny, nz) if dx is None else dx
+    return Problem(f"heat3d_{nx}x{ny}x{nz}", KIND_HEAT3D, nx * ny * nz,
+                   (float(nx), float(ny), float(nz), alpha, dx), dtype, HEAT_CORNER,
+                   (float(nx), float(ny), float(nz)) + HEAT_BOX, seed, dt, nsteps)
+
+
+def heat3d_1000_f64() -> Problem:
+    """The heat diffusion case study at its stated size: l = 1000 (n = 10^9),
+    FP64, [t0, t1] = [0, 20] with dt = 0.02 (1000 RK4 steps)."""
+    p = heat3d_problem(1000, 1000, 1000, BASE_SEED + 5, 1000)
+    p.name = "heat3d_1000^3_f64"
+    return p
 
 
 def small_problem(kind: int, n: int, seed: int, nsteps: int, dtype=np.float64,

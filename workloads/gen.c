@@ -1,6 +1,6 @@
 /*
  * Seeded synthetic workloads: interval boxes for the cell-transmission (CTM)
- * and reaction-diffusion (RD) chains.
+ * and reaction-diffusion (RD) chains and the 3-D heat grid.
  *
  * This module only generates inputs.  It holds none of the reachability
  * arithmetic (no dynamics, no decomposition function, no integrator), so both
@@ -21,6 +21,10 @@
  *   CTM_FIXEDW : lo = a + a*U0(i),          hi = lo + d
  *   SIN        : s  = sin(pi*(i+1)/(n+1)),  w = wmax*U1(i),
  *                lo = s - 0.5*w,            hi = s + 0.5*w
+ *   HEAT_CORNER: a grid of nx * ny * nz cells, cell i = a + nx (b + ny c);
+ *                the corner block a < f nx, b < f ny, c < f nz is heated:
+ *                lo = T - hw*U0(i), hi = T + hw*U1(i); elsewhere
+ *                lo = 0, hi = cw*U1(i).   prm = {nx, ny, nz, f, T, hw, cw}
  * The sine profile is the first Dirichlet eigenmode of the chain; sin is the
  * host libm routine and is only ever evaluated here.
  */
@@ -85,7 +89,7 @@ void wl_uniform(uint64_t seed, uint64_t stream, int64_t i0, int64_t count, doubl
     }
 }
 
-enum { WL_CTM_RANDW = 0, WL_CTM_FIXEDW = 1, WL_SIN = 2 };
+enum { WL_CTM_RANDW = 0, WL_CTM_FIXEDW = 1, WL_SIN = 2, WL_HEAT_CORNER = 3 };
 
 /* One cell of a box recipe; `u0`, `u1` are the stream-0 and stream-1 draws. */
 static inline void wl_cell(int recipe, const double* prm, int64_t n, int64_t i,
@@ -102,6 +106,26 @@ static inline void wl_cell(int recipe, const double* prm, int64_t n, int64_t i,
         if (recipe == WL_CTM_RANDW) { t = d * u1; w = t; } else { w = d; }
         *lo = l;
         *hi = l + w;
+    } else if (recipe == WL_HEAT_CORNER) {
+        const int64_t nx = (int64_t)prm[0], ny = (int64_t)prm[1];
+        const int64_t a = i % nx, b = (i / nx) % ny, c = i / (nx * ny);
+        const double f = prm[3], T = prm[4], hw = prm[5], cw = prm[6];
+        t = f * prm[0];
+        const int in_x = (double)a < t;
+        t = f * prm[1];
+        const int in_y = (double)b < t;
+        t = f * prm[2];
+        const int in_z = (double)c < t;
+        if (in_x && in_y && in_z) {
+            t = hw * u0;
+            *lo = T - t;
+            t = hw * u1;
+            *hi = T + t;
+        } else {
+            *lo = 0.0;
+            t = cw * u1;
+            *hi = t;
+        }
     } else {
         const double wmax = prm[0];
         t = WL_PI * (double)(i + 1);
@@ -124,7 +148,7 @@ static inline void wl_cell(int recipe, const double* prm, int64_t n, int64_t i,
 int wl_box(int recipe, const double* prm, uint64_t seed, int64_t n,
            int64_t i0, int64_t count, int out_f32, void* lo_out, void* hi_out)
 {
-    if (recipe < 0 || recipe > 2 || n < 1 || i0 < 0 || count < 0 || i0 + count > n)
+    if (recipe < 0 || recipe > 3 || n < 1 || i0 < 0 || count < 0 || i0 + count > n)
         return -1;
     if (count == 0) return 0;
     const uint64_t key[2] = {seed, 0};
