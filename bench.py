@@ -37,6 +37,11 @@ RD_FLOPS_PER_STATE_STEP = 45
 # w*(c - y), two minimum operations) and its difference with the neighbour's,
 # 6; plus 13 for the stage inputs and the update.
 CTM_OPS_PER_STATE_STEP = 37
+# 3-D heat: per stage 5 adds, one FMA and one multiply (8); the four RK4
+# updates 2 + 4 + 6 + 2 (the stage-3 level also folds the running sum into
+# y + dt/6 (K1 + 2 K2 + 2 K3)).  One pass = one step: 8 B read + 8 B written.
+HEAT_OPS_PER_CELL_STEP = 46
+HEAT_BYTES_PER_CELL_STEP = 16
 
 
 def log(msg):
@@ -233,6 +238,61 @@ def extra_ctm_2p31_f32(rc, R, torch, workloads, steps=2):
     return out
 
 
+def extra_heat3d_1000(rc, R, torch, workloads, cpu_oracle=True):
+    """The heat diffusion case study at its stated size: 1000^3 grid (n = 10^9),
+    FP64, 1000 RK4 steps of dt = 0.02, embedding of the heated-corner box."""
+    p = workloads.heat3d_1000_f64()
+    lo = np.empty(p.n, dtype=np.float64)
+    hi = np.empty(p.n, dtype=np.float64)
+    t = time.perf_counter()
+    p.box(out=(lo, hi))
+    log(f"heat 1000^3 inputs in {time.perf_counter() - t:.1f} s")
+    x_lo = torch.from_numpy(lo).cuda()
+    x_hi = torch.from_numpy(hi).cuda()
+    del lo, hi
+    r_lo, r_hi = torch.empty_like(x_lo), torch.empty_like(x_hi)
+    sysd = R.make_system(p.kind, p.n, list(p.prm), 0)
+    nb = R.reach_workspace_bytes(rc.ctx, sysd, R.REACH_F64, 0)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device="cuda")
+    plan = R.reach_plan_embed(rc.ctx, sysd, R.REACH_F64, p.nsteps)
+    run = lambda k: R.reach_embed_rk4(rc.ctx, sysd, R.REACH_F64, x_lo, x_hi, None, None, 0.0,
+                                      p.dt, k, r_lo, r_hi, ws, nb, None)
+    run(4)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    run(p.nsteps)
+    e1.record()
+    torch.cuda.synchronize()
+    assert rc.sync() == R.REACH_OK
+    sec = e0.elapsed_time(e1) / 1e3
+    launch = sec / p.nsteps
+    cells = 2.0 * p.n
+    out = {"workload": "3-D heat diffusion 1000^3 (n=1e9) FP64, dt=0.02, 1000 RK4 steps "
+                       "(embedding, 2n states)",
+           "cell_steps_per_s": cells * p.nsteps / sec, "seconds": round(sec, 3),
+           "plan": plan, "launch_ms": round(launch * 1e3, 3),
+           "roofline": {"bound": "hbm",
+                        "achieved": round(cells * HEAT_BYTES_PER_CELL_STEP / launch / 1e9, 1),
+                        "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                        "frac": round(cells * HEAT_BYTES_PER_CELL_STEP / launch / HBM_PEAK, 4)},
+           "alu_frac_fp64": round(cells * HEAT_OPS_PER_CELL_STEP / launch / FP64_PEAK, 4),
+           "paper_cpu_minutes": {"m4.10xlarge": 472, "c5.24xlarge": 350.2}}
+    del x_lo, x_hi, r_lo, r_hi, ws
+    torch.cuda.empty_cache()
+    if cpu_oracle:
+        import oracle
+        q = workloads.heat3d_problem(200, 200, 200, workloads.BASE_SEED + 6, 5)
+        qlo, qhi = q.box()
+        t = time.perf_counter()
+        oracle.embed_rk4(q.kind, list(q.prm), qlo, qhi, dt=q.dt, nsteps=q.nsteps)
+        csec = time.perf_counter() - t
+        out["cpu_oracle"] = {"cell_steps_per_s": 2.0 * q.n * q.nsteps / csec,
+                             "sample": "200^3 grid, 5 steps",
+                             "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
+    return out
+
+
 def extra_mc_ctm4096(rc, R, torch, workloads, cpu_samples):
     """Monte Carlo, CTM n = 4096 FP32, 2^20 samples, 500 RK4 steps."""
     import oracle
@@ -426,6 +486,9 @@ def main():
         extra["mc_ctm4096_f32"] = extra_mc_ctm4096(rc, R, torch, workloads,
                                                    0 if args.no_cpu else args.cpu_mc_samples)
         log(f"mc: {extra['mc_ctm4096_f32']}")
+        extra["embed_heat3d_1000_f64"] = extra_heat3d_1000(rc, R, torch, workloads,
+                                                           not args.no_cpu)
+        log(f"heat 1000^3: {extra['embed_heat3d_1000_f64']}")
 
     cpu = None
     if not args.no_cpu:

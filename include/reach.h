@@ -42,6 +42,19 @@
  *                    + aR- xh_{i+1} + b+ p_i + b- ph_i.
  *              n_in = 0, 1 or n.
  *
+ * Built-in grid system (heat diffusion case study, Sec. 5):
+ *   REACH_HEAT3D prm = {nx, ny, nz, alpha, dx}: the heat equation on an
+ *              nx * ny * nz grid of spacing dx, n = nx ny nz, cell (x, y, z)
+ *              at index x + nx (y + ny z).  f = alpha / dx^2 times the sum
+ *              over the six directions of (neighbour - own).  Every face is
+ *              insulated (a direction leaving the grid adds nothing) except
+ *              x = nx - 1, whose outside is held at temperature 0.  Linear
+ *              with non-negative couplings (alpha >= 0): d = f.  n_in = 0.
+ *              nx, ny, nz are integers >= 1, nx < 2^31, dx > 0.
+ *              Entry points: reach_embed_rk4 (and its tube, plan, autotune
+ *              and workspace queries) and reach_growth_bound; the Monte Carlo,
+ *              batch and serving calls return REACH_E_UNSUPPORTED.
+ *
  * Conventions (all entry points):
  *   - Array pointers are DEVICE pointers (hipMalloc / torch tensors on the
  *     GPU) unless stated otherwise, owned by the caller.  The library never
@@ -88,7 +101,7 @@ enum {
 typedef int32_t reach_dtype;
 enum { REACH_F64 = 0, REACH_F32 = 1 };
 
-enum { REACH_CTM = 1, REACH_RD = 2, REACH_LIN3 = 3 };
+enum { REACH_CTM = 1, REACH_RD = 2, REACH_LIN3 = 3, REACH_HEAT3D = 4 };
 
 /* A system of the list above.  `reserved` must be 0. */
 typedef struct reach_system {
@@ -137,6 +150,8 @@ const char* reach_last_error(const reach_ctx* ctx);
      "embed.E"    cells per lane of the embedding kernel (0 = tuned default)
      "embed.S"    sides per wavefront, 1 or 2 (0 = tuned default)
      "gb.E", "gb.K"  cells per lane / steps per pass of the growth-bound kernel
+     "heat.P"     rows per wavefront of the 3-D heat kernel: 2, 3, 4 or 8
+                  (with 16, 12, 8 or 4 wavefronts per block; 0 = tuned default)
      "mc.waves"   resident waves of the Monte Carlo kernel (0 = default)
      "batch.waves" resident waves of the batch kernel (0 = default)
    Returns REACH_E_INVAL for an unknown key or a value out of range. */
@@ -149,7 +164,10 @@ int64_t reach_get_option(const reach_ctx* ctx, const char* key);
    out[3] = tile stride in cells, out[4] = halo cells per cut edge,
    out[5] = passes (kernel launches), out[6] = S, sides per wavefront (2: lower
    and upper together; 1: one side per wavefront, twice the tiles, for the
-   cooperative CTM and RD chains).  `out` is a host array of 7. */
+   cooperative CTM and RD chains).  `out` is a host array of 7.  For
+   REACH_HEAT3D: out[0] = rows per wavefront, out[1] = 1, out[2] = tiles per
+   side (x-y tiles of 64 by rows x waves cells), out[3] = output cells of a
+   tile along x, out[4] = 4, out[5] = nsteps, out[6] = 1. */
 reach_status reach_plan_embed(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
                               int64_t nsteps, int64_t* out);
 

@@ -32,7 +32,7 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVI
                 -8: "E_BUSY", -9: "E_TIMEOUT"}
 
 REACH_F64, REACH_F32 = 0, 1
-REACH_CTM, REACH_RD, REACH_LIN3 = 1, 2, 3
+REACH_CTM, REACH_RD, REACH_LIN3, REACH_HEAT3D = 1, 2, 3, 4
 
 
 class ReachError(RuntimeError):

@@ -17,7 +17,7 @@ SO = os.path.join(HERE, "libreach.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["embed.hip", "gb.hip", "mc.hip", "batch.hip", "runtime.cpp", "server.cpp"]
+SOURCES = ["embed.hip", "gb.hip", "heat3d.hip", "mc.hip", "batch.hip", "runtime.cpp", "server.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument", "-Wno-unused-value", "-Wno-unused-result"]

@@ -72,6 +72,28 @@ hipError_t launch_gb_combine(int dtype, const void* c, const void* r, int64_t n,
                              void* hi, unsigned int* status, hipStream_t stream);
 bool gb_has_E(int E);
 
+// One RK4 step of the 3-D heat grid for `sides` independent states
+// (lower / upper, or center / half-width).  Tiles are x-y columns of 64 by
+// WV * P cells streaming through z; TX * TY tiles per side, each writing its
+// OX by OY output cells (64 - 8 and WV * P - 8: a 4-cell halo per cut face).
+struct HeatPass {
+    const void* src[2];
+    void* dst[2];
+    int64_t nx, ny, nz;
+    int32_t TX, TY, OX, OY;
+    int32_t sides;
+    int32_t per_xcd;    // tiles per XCD in the blockIdx -> tile map
+    double a;           // alpha / dx^2
+    double h2, dt, dt6;
+    unsigned int* status;
+};
+hipError_t launch_heat3d(int dtype, int P, int WV, const HeatPass& a, int64_t grid,
+                         hipStream_t stream);
+bool heat_has_shape(int dtype, int P, int WV);
+// c = (lo + hi) / 2, r = (hi - lo) / 2 elementwise (growth-bound start).
+hipError_t launch_center_radius(int dtype, const void* lo, const void* hi, int64_t n, void* c,
+                                void* r, hipStream_t stream);
+
 struct McArgs {
     const void* x_lo;
     const void* x_hi;
@@ -115,10 +137,11 @@ struct QDesc {
     int64_t tag;        // caller's index (batch) or ticket slot (serving)
 };
 
-// Persistent batch worker: `grid` waves pull descriptors through *counter.
+// Persistent batch worker: `grid` waves pull work items (2 per query)
+// through *counter; pair[i] counts the finished sides of query i.
 hipError_t launch_batch(const QDesc* d, int64_t nq, unsigned long long* counter,
-                        unsigned int* qflags, unsigned int* status, int64_t grid,
-                        hipStream_t stream);
+                        unsigned int* qflags, unsigned int* pair, unsigned int* status,
+                        int64_t grid, hipStream_t stream);
 // Zero `count` 32-bit words (a kernel, so it can sit in a captured graph).
 hipError_t launch_zero(void* p, int64_t count, hipStream_t stream);
 // One query with a plain launch (the one-launch-per-query baseline).
@@ -127,15 +150,9 @@ hipError_t launch_single(const QDesc& d, unsigned int* status, hipStream_t strea
 // Serving ring (see runtime): slots live in pinned host memory.
 struct ServeSlot {
     QDesc d;
-    unsigned long long seq;      // ticket index published in this slot (+1), 0 = empty
-    unsigned long long done;     // ticket index completed in this slot (+1)
-    unsigned int flags;          // status bits of that query
-    unsigned int pad;
-};
-struct ServeCtl {
-    unsigned long long next;     // device: next ticket index to claim
-    unsigned int stop;           // host-set stop flag (pinned host memory)
-    unsigned int pad;
+    unsigned long long seq;      // sequence published in this slot (+1), 0 = empty
+    unsigned long long done[2];  // sequence whose lower / upper side completed (+1)
+    unsigned int flags[2];       // status bits of each side
 };
 // ctl: device words [claim counter, status, published watermark].
 hipError_t launch_server(ServeSlot* ring, int32_t slots, unsigned long long* ctl,

@@ -106,7 +106,8 @@ int64_t opt_get(const reach_ctx* c, const char* k) {
 reach_status check_system(reach_ctx* c, const reach_system* s, reach_dtype dtype) {
     if (!s) return fail(c, REACH_E_INVAL, "system is NULL");
     if (s->reserved != 0) return fail(c, REACH_E_INVAL, "reserved field must be 0");
-    if (s->kind != REACH_CTM && s->kind != REACH_RD && s->kind != REACH_LIN3)
+    if (s->kind != REACH_CTM && s->kind != REACH_RD && s->kind != REACH_LIN3 &&
+        s->kind != REACH_HEAT3D)
         return fail(c, REACH_E_INVAL, "unknown system kind %d", s->kind);
     if (dtype != REACH_F64 && dtype != REACH_F32) return fail(c, REACH_E_INVAL, "bad dtype %d", dtype);
     if (s->n < 1 || s->n >= kMaxN) return fail(c, REACH_E_INVAL, "n = %lld out of range", (long long)s->n);
@@ -117,6 +118,27 @@ reach_status check_system(reach_ctx* c, const reach_system* s, reach_dtype dtype
     for (int i = 0; i < 8; ++i)
         if (!std::isfinite(s->prm[i])) return fail(c, REACH_E_INVAL, "parameter %d not finite", i);
     if (s->kind == REACH_RD && !(s->prm[0] > 0.0)) return fail(c, REACH_E_INVAL, "RD spacing h must be > 0");
+    if (s->kind == REACH_HEAT3D) {
+        if (s->n_in != 0) return fail(c, REACH_E_UNSUPPORTED, "the 3-D heat grid takes no inputs");
+        int64_t prod = 1;
+        for (int d = 0; d < 3; ++d) {
+            const double g = s->prm[d];
+            if (!(g >= 1.0 && g < 2147483648.0 && g == std::floor(g)))
+                return fail(c, REACH_E_INVAL, "heat grid extent %d must be an integer in [1, 2^31)", d);
+            prod *= (int64_t)g;
+            if (prod > s->n) break;
+        }
+        if (prod != s->n) return fail(c, REACH_E_INVAL, "n must equal nx * ny * nz");
+        if (!(s->prm[3] >= 0.0)) return fail(c, REACH_E_INVAL, "heat diffusivity must be >= 0");
+        if (!(s->prm[4] > 0.0)) return fail(c, REACH_E_INVAL, "heat grid spacing must be > 0");
+    }
+    return REACH_OK;
+}
+
+// Steps of every launch that only the chain kernels implement.
+reach_status chains_only(reach_ctx* c, const reach_system* s, const char* what) {
+    if (s->kind == REACH_HEAT3D)
+        return fail(c, REACH_E_UNSUPPORTED, "%s runs the chain systems only", what);
     return REACH_OK;
 }
 
@@ -144,6 +166,7 @@ struct EmbedPlan {
 // Defaults measured on MI355X for the 2^26-cell chains (overridden by the
 // autotuner or its cache).  Cooperative chains run one side per wave.
 TuneEntry default_tune(int kind, int dtype) {
+    if (kind == REACH_HEAT3D) return TuneEntry{4, 1, 1};   // rows per wave, 8 waves per block
     if (kind == REACH_LIN3) return dtype == REACH_F64 ? TuneEntry{12, 12, 2} : TuneEntry{16, 8, 2};
     return dtype == REACH_F64 ? TuneEntry{24, 20, 1} : TuneEntry{48, 12, 1};
 }
@@ -203,7 +226,193 @@ reach_status plan_embed(reach_ctx* c, const reach_system* s, reach_dtype dtype, 
     return REACH_OK;
 }
 
+// ------------------------------------------------------------ 3-D heat --
+struct HeatPlan {
+    int P = 4, WV = 8;        // rows per wave, waves per block
+    int OX = 0, OY = 0;       // output cells of a tile along x / y
+    int64_t TX = 0, TY = 0;   // tiles per side along x / y
+};
+
+int heat_waves(int P) { return P == 4 ? 8 : P == 2 ? 16 : P == 8 ? 4 : P == 3 ? 12 : 0; }
+
+reach_status plan_heat(reach_ctx* c, const reach_system* s, reach_dtype dtype, HeatPlan* p) {
+    int P = (int)opt_get(c, "heat.P");
+    if (!P) P = tuned(c, REACH_HEAT3D, dtype, s->n).E;
+    const int WV = heat_waves(P);
+    if (!WV || !heat_has_shape(dtype == REACH_F64 ? 0 : 1, P, WV))
+        return fail(c, REACH_E_INVAL, "heat.P = %d not built for this dtype", P);
+    p->P = P;
+    p->WV = WV;
+    p->OX = 64 - 8;
+    p->OY = WV * P - 8;
+    const int64_t nx = (int64_t)s->prm[0], ny = (int64_t)s->prm[1];
+    p->TX = (nx + p->OX - 1) / p->OX;
+    p->TY = (ny + p->OY - 1) / p->OY;
+    return REACH_OK;
+}
+
+// Which buffer each of `passes` passes reads and writes: 0 = x, 1 = r,
+// 2 = workspace.  The last pass writes r unless r aliases x and the pass
+// count makes the ping-pong end in the workspace (then final_copy).
+void plan_io(int64_t passes, bool inplace_ok, bool alias, std::vector<std::pair<int, int>>* io,
+             bool* final_copy) {
+    std::vector<int> dst(passes);
+    *final_copy = false;
+    if (inplace_ok) {
+        for (auto& d : dst) d = 1;
+    } else {
+        for (int64_t p = passes - 1, k = 0; p >= 0; --p, ++k) dst[p] = (k % 2 == 0) ? 1 : 2;
+        if (alias && dst[0] == 1) {
+            for (int64_t p = 0; p < passes; ++p) dst[p] = (p % 2 == 0) ? 2 : 1;
+            *final_copy = (dst[passes - 1] == 2);
+        }
+    }
+    int src = 0;
+    io->clear();
+    for (int64_t p = 0; p < passes; ++p) {
+        io->push_back({src, dst[p]});
+        src = dst[p];
+    }
+}
+
+reach_status embed_heat3d(reach_ctx* c, const reach_system* s, reach_dtype dtype,
+                          const void* x_lo, const void* x_hi, double dt, int64_t nsteps,
+                          void* r_lo, void* r_hi, void* ws, size_t ws_bytes, hipStream_t hs) {
+    HeatPlan hp;
+    reach_status st = plan_heat(c, s, dtype, &hp);
+    if (st != REACH_OK) return st;
+    const size_t bytes = (size_t)s->n * dsize(dtype);
+    const bool alias = (r_lo == x_lo) || (r_hi == x_hi) || (r_lo == x_hi) || (r_hi == x_lo);
+    const int64_t passes = nsteps;   // one RK4 step per pass
+    const bool need_ws = passes >= 2 || alias;
+    void *w_lo = nullptr, *w_hi = nullptr;
+    if (need_ws) {
+        if (!ws || ws_bytes < 2 * bytes)
+            return fail(c, REACH_E_INVAL, "workspace of %zu bytes needed", 2 * bytes);
+        w_lo = ws;
+        w_hi = (char*)ws + bytes;
+    }
+    std::vector<std::pair<int, int>> io;
+    bool final_copy = false;
+    plan_io(passes, false, alias, &io, &final_copy);
+    const void* lo_of[3] = {x_lo, r_lo, w_lo};
+    const void* hi_of[3] = {x_hi, r_hi, w_hi};
+    HeatPass a{};
+    a.nx = (int64_t)s->prm[0]; a.ny = (int64_t)s->prm[1]; a.nz = (int64_t)s->prm[2];
+    a.TX = (int32_t)hp.TX; a.TY = (int32_t)hp.TY; a.OX = hp.OX; a.OY = hp.OY;
+    a.sides = 2;
+    const int64_t tiles = 2 * hp.TX * hp.TY;
+    a.per_xcd = (int32_t)((tiles + 7) / 8);
+    a.a = s->prm[3] / (s->prm[4] * s->prm[4]);
+    a.h2 = dt / 2.0; a.dt = dt; a.dt6 = dt / 6.0;
+    a.status = c->status;
+    const int64_t grid = 8 * (int64_t)a.per_xcd;
+    const int dt_id = dtype == REACH_F64 ? 0 : 1;
+    for (int64_t p = 0; p < passes; ++p) {
+        a.src[0] = lo_of[io[p].first];
+        a.src[1] = hi_of[io[p].first];
+        a.dst[0] = (void*)lo_of[io[p].second];
+        a.dst[1] = (void*)hi_of[io[p].second];
+        hipError_t e = launch_heat3d(dt_id, hp.P, hp.WV, a, grid, hs);
+        if (e != hipSuccess) return hip_fail(c, e, "3-D heat kernel launch");
+    }
+    hipError_t e = launch_order_check(dt_id, lo_of[io.back().second], hi_of[io.back().second],
+                                      s->n, c->status, hs);
+    if (e != hipSuccess) return hip_fail(c, e, "order check launch");
+    if (final_copy) {
+        HIPCHK(c, hipMemcpyAsync(r_lo, w_lo, bytes, hipMemcpyDeviceToDevice, hs));
+        HIPCHK(c, hipMemcpyAsync(r_hi, w_hi, bytes, hipMemcpyDeviceToDevice, hs));
+    }
+    return REACH_OK;
+}
+
+// Growth bound of the heat grid: the system is linear with non-negative
+// couplings, so its own matrix is a contraction matrix and the half-width
+// follows the heat equation too; both runs share each launch.
+reach_status gb_heat3d(reach_ctx* c, const reach_system* s, reach_dtype dtype, const void* x_lo,
+                       const void* x_hi, double dt, int64_t nsteps, void* r_lo, void* r_hi,
+                       void* ws, hipStream_t hs) {
+    HeatPlan hp;
+    reach_status st = plan_heat(c, s, dtype, &hp);
+    if (st != REACH_OK) return st;
+    const size_t bytes = (size_t)s->n * dsize(dtype);
+    const int dt_id = dtype == REACH_F64 ? 0 : 1;
+    char* A = (char*)ws;
+    char* B = (char*)ws + 2 * bytes;
+    hipError_t e = launch_center_radius(dt_id, x_lo, x_hi, s->n, B, B + bytes, hs);
+    if (e != hipSuccess) return hip_fail(c, e, "center / radius launch");
+    HeatPass a{};
+    a.nx = (int64_t)s->prm[0]; a.ny = (int64_t)s->prm[1]; a.nz = (int64_t)s->prm[2];
+    a.TX = (int32_t)hp.TX; a.TY = (int32_t)hp.TY; a.OX = hp.OX; a.OY = hp.OY;
+    a.sides = 2;
+    const int64_t tiles = 2 * hp.TX * hp.TY;
+    a.per_xcd = (int32_t)((tiles + 7) / 8);
+    a.a = s->prm[3] / (s->prm[4] * s->prm[4]);
+    a.h2 = dt / 2.0; a.dt = dt; a.dt6 = dt / 6.0;
+    a.status = c->status;
+    const int64_t grid = 8 * (int64_t)a.per_xcd;
+    char* cur = B;
+    for (int64_t p = 0; p < nsteps; ++p) {
+        char* dst = (cur == A) ? B : A;
+        a.src[0] = cur; a.src[1] = cur + bytes;
+        a.dst[0] = dst; a.dst[1] = dst + bytes;
+        e = launch_heat3d(dt_id, hp.P, hp.WV, a, grid, hs);
+        if (e != hipSuccess) return hip_fail(c, e, "3-D heat kernel launch");
+        cur = dst;
+    }
+    e = launch_gb_combine(dt_id, cur, cur + bytes, s->n, r_lo, r_hi, c->status, hs);
+    if (e != hipSuccess) return hip_fail(c, e, "growth-bound combine launch");
+    return REACH_OK;
+}
+
+void save_tune_entry(const reach_ctx* c, int kind, int dtype, int bucket, TuneEntry t, double ps);
+
+// Times every built (rows, waves) shape of the heat kernel, keeps the fastest.
+reach_status autotune_heat3d(reach_ctx* c, const reach_system* s, reach_dtype dtype,
+                             const void* x_lo, const void* x_hi, double dt, int64_t trial_steps,
+                             void* r_lo, void* r_hi, void* ws, size_t ws_bytes, hipStream_t hs,
+                             int64_t* best) {
+    const int64_t saveP = opt_get(c, "heat.P");
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    double best_ps = 1e300;
+    int bestP = 0;
+    reach_status st = REACH_OK;
+    for (int P : {2, 3, 4, 8}) {
+        if (!heat_has_shape(dtype == REACH_F64 ? 0 : 1, P, heat_waves(P))) continue;
+        c->opt["heat.P"] = P;
+        st = embed_heat3d(c, s, dtype, x_lo, x_hi, dt, trial_steps, r_lo, r_hi, ws, ws_bytes, hs);
+        if (st != REACH_OK) break;
+        hipEventRecord(e0, hs);
+        for (int rep = 0; rep < 2 && st == REACH_OK; ++rep)
+            st = embed_heat3d(c, s, dtype, x_lo, x_hi, dt, trial_steps, r_lo, r_hi, ws, ws_bytes,
+                              hs);
+        hipEventRecord(e1, hs);
+        if (st != REACH_OK) break;
+        if (hipEventSynchronize(e1) != hipSuccess) { st = REACH_E_DEVICE; break; }
+        float ms = 0.f;
+        hipEventElapsedTime(&ms, e0, e1);
+        const double ps = (double)ms * 1e9 / (2.0 * 2.0 * (double)s->n * (double)trial_steps);
+        if (ps < best_ps) { best_ps = ps; bestP = P; }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->opt["heat.P"] = saveP;
+    if (st != REACH_OK) return st;
+    const int bucket = n_bucket(s->n);
+    const TuneEntry bt{bestP, 1, 1};
+    c->tune[{s->kind, dtype, bucket}] = bt;
+    save_tune_entry(c, s->kind, dtype, bucket, bt, best_ps);
+    best[0] = bestP;
+    best[1] = 1;
+    best[2] = (int64_t)std::llround(best_ps * 1000.0);
+    best[3] = 1;
+    return REACH_OK;
+}
+
 size_t embed_ws_bytes(reach_ctx* c, const reach_system* s, reach_dtype dtype) {
+    if (s->kind == REACH_HEAT3D) return (size_t)2 * (size_t)s->n * dsize(dtype);
     EmbedPlan p;
     if (plan_embed(c, s, dtype, 2 * (int64_t)std::max(1, (int)opt_get(c, "embed.K")), &p) != REACH_OK)
         return (size_t)-1;
@@ -241,7 +450,9 @@ void load_tune_cache(reach_ctx* c) {
     double ps;
     while (std::fscanf(f, "%63s %d %d %d %d %d %d %lf", arch, &kind, &dtype, &bucket, &E, &K, &S,
                        &ps) == 8) {
-        if (c->arch == arch && embed_has_shape(kind, dtype, E, S) && K >= 1 && 8 * K < 64 * E)
+        const bool heat_ok = kind == REACH_HEAT3D && heat_waves(E) &&
+                             heat_has_shape(dtype == REACH_F64 ? 0 : 1, E, heat_waves(E));
+        if (c->arch == arch && (heat_ok || (embed_has_shape(kind, dtype, E, S) && K >= 1 && 8 * K < 64 * E)))
             c->tune[{kind, dtype, bucket}] = TuneEntry{E, K, S};
     }
     std::fclose(f);
@@ -309,7 +520,7 @@ const char* reach_last_error(const reach_ctx* c) { return c ? c->err.c_str() : "
 reach_status reach_set_option(reach_ctx* c, const char* key, int64_t value) {
     if (!c || !key) return REACH_E_INVAL;
     static const char* keys[] = {"embed.K", "embed.E", "embed.S", "mc.waves", "batch.waves",
-                                 "serve.mode", "serve.waves", "gb.E", "gb.K"};
+                                 "serve.mode", "serve.waves", "gb.E", "gb.K", "heat.P"};
     bool known = false;
     for (const char* k : keys) known |= (std::strcmp(k, key) == 0);
     if (!known) return fail(c, REACH_E_INVAL, "unknown option %s", key);
@@ -319,6 +530,8 @@ reach_status reach_set_option(reach_ctx* c, const char* key, int64_t value) {
         return fail(c, REACH_E_INVAL, "embed.E = %lld not built", (long long)value);
     if (!std::strcmp(key, "embed.S") && value != 0 && value != 1 && value != 2)
         return fail(c, REACH_E_INVAL, "embed.S must be 0, 1 or 2");
+    if (!std::strcmp(key, "heat.P") && value && !heat_waves((int)value))
+        return fail(c, REACH_E_INVAL, "heat.P must be 0, 2, 3, 4 or 8");
     c->opt[key] = value;
     return REACH_OK;
 }
@@ -333,6 +546,14 @@ reach_status reach_plan_embed(reach_ctx* c, const reach_system* s, reach_dtype d
     reach_status st = check_system(c, s, dtype);
     if (st != REACH_OK) return st;
     if (nsteps < 0) return fail(c, REACH_E_INVAL, "nsteps < 0");
+    if (s->kind == REACH_HEAT3D) {
+        HeatPlan hp;
+        st = plan_heat(c, s, dtype, &hp);
+        if (st != REACH_OK) return st;
+        out[0] = hp.P; out[1] = 1; out[2] = hp.TX * hp.TY; out[3] = hp.OX; out[4] = 4;
+        out[5] = nsteps; out[6] = 1;
+        return REACH_OK;
+    }
     EmbedPlan p;
     st = plan_embed(c, s, dtype, nsteps, &p);
     if (st != REACH_OK) return st;
@@ -378,6 +599,8 @@ reach_status reach_embed_rk4(reach_ctx* c, const reach_system* s, reach_dtype dt
         if (r_hi != x_hi) HIPCHK(c, hipMemcpyAsync(r_hi, x_hi, bytes, hipMemcpyDeviceToDevice, hs));
         return REACH_OK;
     }
+    if (s->kind == REACH_HEAT3D)
+        return embed_heat3d(c, s, dtype, x_lo, x_hi, dt, nsteps, r_lo, r_hi, ws, ws_bytes, hs);
     EmbedPlan pl;
     st = plan_embed(c, s, dtype, nsteps, &pl);
     if (st != REACH_OK) return st;
@@ -395,23 +618,7 @@ reach_status reach_embed_rk4(reach_ctx* c, const reach_system* s, reach_dtype dt
     }
     bool final_copy = false;
     std::vector<std::pair<int, int>> io;  // per pass: (src id, dst id); 0 = x, 1 = r, 2 = ws
-    {
-        std::vector<int> dst(pl.passes);
-        if (inplace_ok) {
-            for (auto& d : dst) d = 1;
-        } else {
-            for (int64_t p = pl.passes - 1, k = 0; p >= 0; --p, ++k) dst[p] = (k % 2 == 0) ? 1 : 2;
-            if (alias && dst[0] == 1) {
-                for (int64_t p = 0; p < pl.passes; ++p) dst[p] = (p % 2 == 0) ? 2 : 1;
-                final_copy = (dst[pl.passes - 1] == 2);
-            }
-        }
-        int src = 0;
-        for (int64_t p = 0; p < pl.passes; ++p) {
-            io.push_back({src, dst[p]});
-            src = dst[p];
-        }
-    }
+    plan_io(pl.passes, inplace_ok, alias, &io, &final_copy);
     const void* lo_of[3] = {x_lo, r_lo, w_lo};
     const void* hi_of[3] = {x_hi, r_hi, w_hi};
 
@@ -494,6 +701,9 @@ reach_status reach_autotune_embed(reach_ctx* c, const reach_system* s, reach_dty
     if (trial_steps < 1) return fail(c, REACH_E_INVAL, "trial_steps must be >= 1");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t hs = (hipStream_t)stream;
+    if (s->kind == REACH_HEAT3D)
+        return autotune_heat3d(c, s, dtype, x_lo, x_hi, dt, trial_steps, r_lo, r_hi, ws, ws_bytes,
+                               hs, best);
     const int64_t saveE = opt_get(c, "embed.E"), saveK = opt_get(c, "embed.K");
     static const int Es[] = {4, 8, 12, 16, 24, 32, 48, 64};
     static const int Ks[] = {2, 4, 6, 8, 10, 12, 16, 20, 24};
@@ -552,6 +762,8 @@ reach_status reach_montecarlo_range(reach_ctx* c, const reach_system* s, reach_d
                                     void* r_max, void* ws, size_t ws_bytes, void* stream) {
     if (!c) return REACH_E_INVAL;
     reach_status st = check_system(c, s, dtype);
+    if (st != REACH_OK) return st;
+    st = chains_only(c, s, "Monte Carlo");
     if (st != REACH_OK) return st;
     if (!x_lo || !x_hi || !r_min || !r_max) return fail(c, REACH_E_INVAL, "NULL pointer");
     if (s->n_in > 0 && (!p_lo || !p_hi)) return fail(c, REACH_E_INVAL, "NULL input pointer");
@@ -647,6 +859,8 @@ reach_status reach_growth_bound(reach_ctx* c, const reach_system* s, reach_dtype
     if (!ws || ws_bytes < 4 * bytes) return fail(c, REACH_E_INVAL, "workspace of %zu bytes needed", 4 * bytes);
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t hs = (hipStream_t)stream;
+    if (s->kind == REACH_HEAT3D)
+        return gb_heat3d(c, s, dtype, x_lo, x_hi, dt, nsteps, r_lo, r_hi, ws, hs);
     // plan: one side per wave, as the one-side embedding tiles
     int E = (int)opt_get(c, "gb.E");
     int K = (int)opt_get(c, "gb.K");
@@ -716,6 +930,8 @@ namespace {
 reach_status make_desc(reach_ctx* c, const reach_query& q, int64_t tag, QDesc* d) {
     reach_status st = check_system(c, &q.sys, q.dtype);
     if (st != REACH_OK) return st;
+    st = chains_only(c, &q.sys, "the batch path");
+    if (st != REACH_OK) return st;
     if (q.dtype != REACH_F64) return fail(c, REACH_E_UNSUPPORTED, "batched queries are FP64");
     if (q.sys.n > kBatchMaxN) return fail(c, REACH_E_UNSUPPORTED, "batched queries need n <= 512");
     if (q.sys.n_in > 1) return fail(c, REACH_E_UNSUPPORTED, "batched queries take n_in 0 or 1");
@@ -747,9 +963,10 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 extern "C" {
 
+// batch workspace: [work counter][per-query flags][per-query side counters][descriptors]
 size_t reach_batch_workspace_bytes(int64_t nq) {
     if (nq < 0) return (size_t)-1;
-    return align256(8) + align256(4 * (size_t)nq) + align256(sizeof(QDesc) * (size_t)nq);
+    return align256(8) + 2 * align256(4 * (size_t)nq) + align256(sizeof(QDesc) * (size_t)nq);
 }
 
 reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t nq, void* ws,
@@ -788,17 +1005,18 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     char* base = (char*)ws;
     auto* counter = (unsigned long long*)base;
     auto* qflags = (unsigned int*)(base + align256(8));
-    auto* ddesc = (QDesc*)(base + align256(8) + align256(4 * (size_t)nq));
+    auto* pair = (unsigned int*)(base + align256(8) + align256(4 * (size_t)nq));
+    auto* ddesc = (QDesc*)(base + align256(8) + 2 * align256(4 * (size_t)nq));
     int64_t grid = opt_get(c, "batch.waves");
     if (grid <= 0) grid = (int64_t)c->cus * 8;
-    grid = std::min<int64_t>(grid, nq);
+    grid = std::min<int64_t>(grid, 2 * nq);
 
     auto enqueue = [&](hipStream_t s) -> hipError_t {
-        hipError_t e = launch_zero(base, (int64_t)(align256(8) + align256(4 * (size_t)nq)) / 4, s);
+        hipError_t e = launch_zero(base, (int64_t)(align256(8) + 2 * align256(4 * (size_t)nq)) / 4, s);
         if (e != hipSuccess) return e;
         e = hipMemcpyAsync(ddesc, c->staging, sizeof(QDesc) * nq, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
-        return launch_batch(ddesc, nq, counter, qflags, c->status, grid, s);
+        return launch_batch(ddesc, nq, counter, qflags, pair, c->status, grid, s);
     };
 
     if (hs == nullptr) {

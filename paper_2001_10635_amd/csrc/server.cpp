@@ -174,12 +174,17 @@ reach_status flags_to_status(unsigned f) {
     return REACH_OK;
 }
 
-// Complete query in slot k (lock held): copy results to the caller.
+// Complete query in slot k (lock held): copy results to the caller.  The two
+// sides ran in different waves, so lower <= upper is checked here.
 void finish(Server* S, int32_t k, unsigned flags) {
     Running& r = S->run[k];
     const int64_t n = r.n;
-    std::memcpy(r.r_lo, S->stage_out + (size_t)k * kOutDoubles, sizeof(double) * n);
-    std::memcpy(r.r_hi, S->stage_out + (size_t)k * kOutDoubles + 512, sizeof(double) * n);
+    const double* lo = S->stage_out + (size_t)k * kOutDoubles;
+    const double* hi = lo + 512;
+    std::memcpy(r.r_lo, lo, sizeof(double) * n);
+    std::memcpy(r.r_hi, hi, sizeof(double) * n);
+    for (int64_t j = 0; j < n; ++j)
+        if (lo[j] > hi[j]) flags |= 2u;
     S->finished[r.ticket] = flags_to_status(flags);
     S->lat.push_back(now_us() - r.t_submit);
     S->alloc.release(r.pool_off, r.pool_len);
@@ -194,8 +199,9 @@ void finish(Server* S, int32_t k, unsigned flags) {
 }
 
 void launch_kernel(Server* S, uint64_t start_seq) {
-    // claim counter and watermark restart at the next sequence to publish
-    unsigned long long init[3] = {start_seq, 0, start_seq};
+    // claim counter (two work items per sequence) and watermark restart at
+    // the next sequence to publish
+    unsigned long long init[3] = {2 * start_seq, 0, start_seq};
     hipMemcpy(S->dctl, init, sizeof init, hipMemcpyHostToDevice);
     *(volatile unsigned int*)S->stop = 0u;
     launch_server(S->ring, S->ring_n, S->dctl, (volatile unsigned int*)S->stop,
@@ -225,8 +231,9 @@ void revive_kernel(Server* S) {
         S->ring_busy[r.seq % S->ring_n] = r.seq + 1;
         ServeSlot* sl = &S->ring[r.seq % S->ring_n];
         sl->d = r.d;
-        sl->flags = 0;
-        __atomic_store_n(&sl->done, (unsigned long long)0, __ATOMIC_RELAXED);
+        sl->flags[0] = sl->flags[1] = 0;
+        __atomic_store_n(&sl->done[0], (unsigned long long)0, __ATOMIC_RELAXED);
+        __atomic_store_n(&sl->done[1], (unsigned long long)0, __ATOMIC_RELAXED);
         __atomic_store_n(&sl->seq, (unsigned long long)(r.seq + 1), __ATOMIC_RELEASE);
     }
     launch_kernel(S, start);
@@ -244,9 +251,11 @@ void service(Server* S) {
             if (!r.used || !r.published) continue;
             if (S->mode == 0) {
                 ServeSlot* sl = &S->ring[r.seq % S->ring_n];
-                uint64_t done = __atomic_load_n(&sl->done, __ATOMIC_ACQUIRE);
-                if (done == r.seq + 1) {
-                    unsigned fl = __atomic_load_n(&sl->flags, __ATOMIC_ACQUIRE);
+                const uint64_t d0 = __atomic_load_n(&sl->done[0], __ATOMIC_ACQUIRE);
+                const uint64_t d1 = __atomic_load_n(&sl->done[1], __ATOMIC_ACQUIRE);
+                if (d0 == r.seq + 1 && d1 == r.seq + 1) {
+                    const unsigned fl = __atomic_load_n(&sl->flags[0], __ATOMIC_ACQUIRE) |
+                                        __atomic_load_n(&sl->flags[1], __ATOMIC_ACQUIRE);
                     finish(S, k, fl);
                     progress = true;
                 }
@@ -335,8 +344,9 @@ void service(Server* S) {
                 Running& r = S->run[k];
                 ServeSlot* sl = &S->ring[r.seq % S->ring_n];
                 sl->d = r.d;
-                sl->flags = 0;
-                __atomic_store_n(&sl->done, (unsigned long long)0, __ATOMIC_RELAXED);
+                sl->flags[0] = sl->flags[1] = 0;
+                __atomic_store_n(&sl->done[0], (unsigned long long)0, __ATOMIC_RELAXED);
+                __atomic_store_n(&sl->done[1], (unsigned long long)0, __ATOMIC_RELAXED);
                 __atomic_store_n(&sl->seq, (unsigned long long)(r.seq + 1), __ATOMIC_RELEASE);
                 r.published = true;
             }
@@ -392,7 +402,7 @@ reach_status reach_server_start(reach_ctx* c, void* pool, size_t pool_bytes, int
     int cus = 256;
     hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     int64_t w = reach_get_option(c, "serve.waves");
-    S->grid = w > 0 ? w : std::min<int64_t>((int64_t)cus * 4, max_slots);
+    S->grid = w > 0 ? w : std::min<int64_t>((int64_t)cus * 4, 2 * (int64_t)max_slots);
     double idle_s = 120.0;
     if (const char* e = std::getenv("REACH_SERVER_IDLE_S")) idle_s = std::max(1.0, std::atof(e));
     int rate_khz = 0;   // wall_clock64 tick rate
@@ -458,6 +468,7 @@ reach_status reach_submit(reach_ctx* c, const reach_query* q, uint64_t* ticket) 
     if (!S) return REACH_E_BUSY;
     if (!q || !ticket) return REACH_E_INVAL;
     const reach_system& s = q->sys;
+    if (s.kind == REACH_HEAT3D) return REACH_E_UNSUPPORTED;   // served queries are chains
     if (s.kind != REACH_CTM && s.kind != REACH_RD && s.kind != REACH_LIN3) return REACH_E_INVAL;
     if (s.reserved != 0) return REACH_E_INVAL;
     if (q->dtype != REACH_F64) return REACH_E_UNSUPPORTED;

@@ -32,7 +32,7 @@ def assert_rel(got, ref, rtol, what=""):
     r = np.asarray(ref, dtype=np.float64)
     assert g.shape == r.shape, f"{what}: shape {g.shape} vs {r.shape}"
     assert np.all(np.isfinite(g)), f"{what}: non-finite GPU values"
-    err = np.abs(g - r) / np.maximum(np.abs(r), 1.0)
+    err = (np.abs(g - r) / np.maximum(np.abs(r), 1.0)).ravel()
     i = int(np.argmax(err)) if err.size else 0
     assert err.size == 0 or err[i] <= rtol, \
         f"{what}: rel err {err[i]:.3e} > {rtol:.0e} at {i} (gpu {g.flat[i]!r}, oracle {r.flat[i]!r})"
