@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-CTM, RD, LIN3, HEAT3D = 1, 2, 3, 4
+CTM, RD, LIN3, HEAT3D, USER = 1, 2, 3, 4, 5
 
 
 def build(verbose: bool = False) -> str:
@@ -56,6 +56,11 @@ def lib():
         L.or_embed_rk4.restype = ctypes.c_int
         L.or_embed_rk4_grid.argtypes = [vp, vp, vp, vp, vp, d, i64, vp, vp]
         L.or_embed_rk4_grid.restype = ctypes.c_int
+        L.or_embed_rk4_user.argtypes = [vp, vp, i64, i64, i64, i64, vp, vp, vp, vp, d, i64,
+                                        vp, vp]
+        L.or_embed_rk4_user.restype = ctypes.c_int
+        L.or_f_rk4_user.argtypes = [vp, vp, i64, i64, vp, vp, d, i64, vp]
+        L.or_f_rk4_user.restype = ctypes.c_int
         L.or_f_rk4.argtypes = [ctypes.c_int, vp, i64, i64, vp, vp, d, d, i64, vp]
         L.or_f_rk4.restype = ctypes.c_int
         L.or_montecarlo.argtypes = [ctypes.c_int, vp, i64, i64, vp, vp, vp, vp, d, d, i64,
@@ -139,6 +144,74 @@ def embed_rk4(kind, prm, x_lo, x_hi, p_lo=None, p_hi=None, t0=0.0, dt=0.01, nste
     if rc != 0:
         raise RuntimeError(f"or_embed_rk4 failed ({rc})")
     return r_lo, r_hi
+
+
+# ------------------------------------------------ user decomposition --
+# A chain system given as C source text defining
+#     REACH_DEVICE real reach_d(real xm, real x, real xp, real hm, real h, real hp,
+#                               real u, real uh, const real* prm, long long i, long long n)
+# (the same text the GPU library compiles with hipRTC).  Here it is compiled by
+# the host C compiler with real = double and called by the oracle's own RK4.
+USER_PRELUDE = "typedef double real;\n#define REACH_DEVICE static\n#include <math.h>\n"
+USER_EXPORT = """
+double or_user_entry(double xm, double x, double xp, double hm, double h, double hp,
+                     double u, double uh, const double* prm, long long i, long long n)
+{
+    return reach_d(xm, x, xp, hm, h, hp, u, uh, prm, i, n);
+}
+"""
+
+
+class UserSystem:
+    """A user decomposition function compiled for the oracle."""
+
+    def __init__(self, source: str):
+        import hashlib
+        import tempfile
+        key = hashlib.sha256(source.encode()).hexdigest()[:16]
+        d = os.path.join(tempfile.gettempdir(), "reach_oracle_user")
+        os.makedirs(d, exist_ok=True)
+        so = os.path.join(d, f"user_{key}.so")
+        if not os.path.exists(so):
+            c = os.path.join(d, f"user_{key}.c")
+            with open(c, "w") as f:
+                f.write(USER_PRELUDE + source + USER_EXPORT)
+            subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-ffp-contract=off",
+                                   "-fno-fast-math", "-std=gnu99", c, "-o", so + ".tmp", "-lm"])
+            os.replace(so + ".tmp", so)
+        self.lib = ctypes.CDLL(so)
+        self.fn = ctypes.cast(self.lib.or_user_entry, ctypes.c_void_p)
+
+
+def embed_rk4_user(user: UserSystem, prm, x_lo, x_hi, p_lo=None, p_hi=None, dt=0.01,
+                   nsteps=1, n_total=None, g0=0):
+    """Algorithm 3 for a chain given by a user decomposition function."""
+    x_lo, x_hi = _f64(x_lo), _f64(x_hi)
+    length = x_lo.size
+    n_in = _nin(p_lo)
+    pl, ph = _f64(p_lo), _f64(p_hi if p_hi is not None else p_lo)
+    r_lo = np.empty(length, dtype=np.float64)
+    r_hi = np.empty(length, dtype=np.float64)
+    pr = _prm(prm)
+    rc = lib().or_embed_rk4_user(user.fn, _p(pr), length if n_total is None else n_total, g0,
+                                 length, n_in, _p(x_lo), _p(x_hi), _p(pl), _p(ph), dt, nsteps,
+                                 _p(r_lo), _p(r_hi))
+    if rc != 0:
+        raise RuntimeError(f"or_embed_rk4_user failed ({rc})")
+    return r_lo, r_hi
+
+
+def f_rk4_user(user: UserSystem, prm, x0, p=None, dt=0.01, nsteps=1):
+    """RK4 of x' = d(x, p, x, p) from x0 (one trajectory)."""
+    x0 = _f64(x0)
+    n_in = _nin(p)
+    pp = _f64(p)
+    out = np.empty(x0.size, dtype=np.float64)
+    pr = _prm(prm)
+    rc = lib().or_f_rk4_user(user.fn, _p(pr), x0.size, n_in, _p(x0), _p(pp), dt, nsteps, _p(out))
+    if rc != 0:
+        raise RuntimeError(f"or_f_rk4_user failed ({rc})")
+    return out
 
 
 def heat3d_prm(nx, ny, nz, alpha, dx):

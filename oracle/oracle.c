@@ -68,7 +68,14 @@
 #include <stdlib.h>
 #include <string.h>
 
-enum { OR_CTM = 1, OR_RD = 2, OR_LIN3 = 3, OR_HEAT3D = 4 };
+enum { OR_CTM = 1, OR_RD = 2, OR_LIN3 = 3, OR_HEAT3D = 4, OR_USER = 5 };
+
+/* A caller-supplied decomposition function of a chain (OR_USER):
+   d_i(x, p, xh, ph) from the cells i-1, i, i+1 of x and of xh, the inputs
+   p_i and ph_i, the system parameters, the global cell index and the chain
+   length. */
+typedef double (*or_user_fn)(double xm, double x, double xp, double hm, double h, double hp,
+                             double u, double uh, const double* prm, long long i, long long n);
 
 /* ------------------------------------------------------------------ RNG --
  * Philox4x64-10 (Salmon et al., SC'11), written from its published
@@ -126,6 +133,7 @@ typedef struct {
     /* HEAT3D only: the window is the box of grid cells [org, org + dim) along
        (x, y, z); left zero, it is the whole grid. */
     int64_t org[3], dim[3];
+    or_user_fn user;   /* OR_USER only */
 } or_sys;
 
 /* Fill in the whole-grid window of a HEAT3D system (no-op for chains). */
@@ -205,10 +213,15 @@ static double or_heat3d_f(const or_sys* S, const double* y, int64_t i)
     return alpha / (dx * dx) * sum;
 }
 
+static double or_d(const or_sys* S, const double* x, const double* p,
+                   const double* xh, const double* ph, int64_t i);
+
 /* f_i(y, p) of the original system at window cell i. */
 static double or_f(const or_sys* S, const double* y, const double* p, int64_t i)
 {
-    if (S->kind == OR_HEAT3D) {
+    if (S->kind == OR_USER) {
+        return or_d(S, y, p, y, p, i);   /* a decomposition function equals f on the diagonal */
+    } else if (S->kind == OR_HEAT3D) {
         return or_heat3d_f(S, y, i);
     } else if (S->kind == OR_CTM) {
         return or_ctm_flux(S, y, i - 1) - or_ctm_flux(S, y, i);
@@ -231,6 +244,13 @@ static double or_neg(double a) { return a < 0.0 ? a : 0.0; }
 static double or_d(const or_sys* S, const double* x, const double* p,
                    const double* xh, const double* ph, int64_t i)
 {
+    if (S->kind == OR_USER) {
+        /* neighbours past the chain's ends read as 0 */
+        double xm = or_nb(S, x, i, -1, 0.0), xp = or_nb(S, x, i, +1, 0.0);
+        double hm = or_nb(S, xh, i, -1, 0.0), hp = or_nb(S, xh, i, +1, 0.0);
+        return S->user(xm, x[i], xp, hm, xh[i], hp, or_input(S, p, i), or_input(S, ph, i),
+                       S->prm, (long long)(S->g0 + i), (long long)S->n_total);
+    }
     if (S->kind == OR_LIN3) {
         const double aL = S->prm[0], aD = S->prm[1], aR = S->prm[2], b = S->prm[3];
         double xm = or_nb(S, x, i, -1, 0.0), xp = or_nb(S, x, i, +1, 0.0);
@@ -331,6 +351,18 @@ int or_embed_rk4(int kind, const double* prm, int64_t n_total, int64_t g0, int64
     return or_embed_core(&S, x_lo, x_hi, p_lo, p_hi, dt, nsteps, r_lo, r_hi);
 }
 
+/* Algorithm 3 for a chain given by a caller-supplied decomposition
+   function `d` (window cells [g0, g0+len) of an n_total-cell chain). */
+int or_embed_rk4_user(or_user_fn d, const double* prm, int64_t n_total, int64_t g0, int64_t len,
+                      int64_t n_in, const double* x_lo, const double* x_hi,
+                      const double* p_lo, const double* p_hi, double dt, int64_t nsteps,
+                      double* r_lo, double* r_hi)
+{
+    if (!d) return -1;
+    or_sys S = {OR_USER, prm, n_total, g0, len, n_in, {0, 0, 0}, {0, 0, 0}, d};
+    return or_embed_core(&S, x_lo, x_hi, p_lo, p_hi, dt, nsteps, r_lo, r_hi);
+}
+
 /* Algorithm 3 on the window box [org, org + dim) of a HEAT3D grid (no
    inputs).  Cells farther than 4 * nsteps cells from every cut face of the
    window are bitwise those of a whole-grid run. */
@@ -385,6 +417,20 @@ int or_f_rk4(int kind, const double* prm, int64_t n, int64_t n_in, const double*
     if (n < 1 || nsteps < 0) return -1;
     or_sys S = {kind, prm, n, 0, n, n_in};
     or_grid_default(&S);
+    double* w = (double*)malloc(sizeof(double) * (size_t)n * 5);
+    if (!w) return -2;
+    memcpy(out, x0, sizeof(double) * (size_t)n);
+    or_traj(&S, out, p, dt, nsteps, w);
+    free(w);
+    return 0;
+}
+
+/* One trajectory of x' = f(x, p) = d(x, p, x, p) for a caller-supplied d. */
+int or_f_rk4_user(or_user_fn d, const double* prm, int64_t n, int64_t n_in, const double* x0,
+                  const double* p, double dt, int64_t nsteps, double* out)
+{
+    if (!d || n < 1 || nsteps < 0) return -1;
+    or_sys S = {OR_USER, prm, n, 0, n, n_in, {0, 0, 0}, {0, 0, 0}, d};
     double* w = (double*)malloc(sizeof(double) * (size_t)n * 5);
     if (!w) return -2;
     memcpy(out, x0, sizeof(double) * (size_t)n);

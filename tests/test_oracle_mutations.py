@@ -10,6 +10,7 @@ import pytest
 
 import oracle
 from tests import test_oracle_pins as pins
+from tests import test_oracle_user as upins
 
 SRC = os.path.join(os.path.dirname(oracle.__file__), "oracle.c")
 
@@ -48,6 +49,12 @@ MUTATIONS = [
     ("heat_spacing_not_squared", [("alpha / (dx * dx) * sum", "alpha / dx * sum")]),
     ("heat_axes_transposed", [("{i % wx, (i / wx) % wy, i / (wx * wy)}",
                                "{i % wy, (i / wy) % wx, i / (wx * wy)}")]),
+    ("user_neighbour_sides_swapped", [("S->user(xm, x[i], xp, hm, xh[i], hp,",
+                                       "S->user(hm, x[i], hp, xm, xh[i], xp,")]),
+    ("user_inputs_swapped", [("or_input(S, p, i), or_input(S, ph, i),\n                       S->prm",
+                              "or_input(S, ph, i), or_input(S, p, i),\n                       S->prm")]),
+    ("user_window_index_local", [("(long long)(S->g0 + i), (long long)S->n_total",
+                                  "(long long)i, (long long)S->n_total")]),
 ]
 
 PINS = [
@@ -71,7 +78,15 @@ PINS = [
     lambda: pins.test_heat3d_trajectory_exact_rational((3, 2, 2)),
     lambda: pins.test_heat3d_cosine_mode_decays_by_stability_polynomial((1, 2, 1)),
     pins.test_heat3d_heat_leaves_only_through_the_open_face,
+    lambda: upins.test_user_lin3_equals_builtin_bitwise(_users(), (-0.5, -1.0, 0.75, -1.5),
+                                                        "cell"),
+    lambda: upins.test_user_ctm_equals_builtin_bitwise_whole_and_window(_users()),
 ]
+
+
+def _users():
+    from tests import user_sources as us
+    return {k: oracle.UserSystem(getattr(us, k)) for k in ("LIN3", "CTM")}
 
 
 def _build_mutant(tmp_path, edits):
