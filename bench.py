@@ -48,18 +48,22 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def source_hash() -> str:
+EMBED_SOURCES = ("dev.hpp", "embed.hip", "kernels.hpp")
+HEAT_SOURCES = ("dev.hpp", "heat3d.hip", "kernels.hpp")
+
+
+def source_hash(files=EMBED_SOURCES) -> str:
     h = hashlib.sha256()
-    for f in ("dev.hpp", "embed.hip", "kernels.hpp"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2001_10635_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile():
-    """HBM bytes per launch from the committed PMC summary of the embedding
-    pass, if it was taken on the current kernel source (else None)."""
-    path = os.path.join(ROOT, "profiles", "embed_tile_kernel_rd2p26_f64_pmc.txt")
+def traffic_from_profile(name="embed_tile_kernel_rd2p26_f64_pmc.txt", files=EMBED_SOURCES):
+    """HBM bytes per launch from a committed PMC summary, if it was taken on
+    the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     vals = {}
@@ -67,7 +71,7 @@ def traffic_from_profile():
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("source_hash") != source_hash():
+    if vals.get("source_hash") != source_hash(files):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -238,10 +242,13 @@ def extra_ctm_2p31_f32(rc, R, torch, workloads, steps=2):
     return out
 
 
-def extra_heat3d_1000(rc, R, torch, workloads, cpu_oracle=True):
+def extra_heat3d_1000(rc, R, torch, workloads, cpu_oracle=True, steps=0):
     """The heat diffusion case study at its stated size: 1000^3 grid (n = 10^9),
-    FP64, 1000 RK4 steps of dt = 0.02, embedding of the heated-corner box."""
+    FP64, 1000 RK4 steps of dt = 0.02, embedding of the heated-corner box
+    (`steps` overrides the step count)."""
     p = workloads.heat3d_1000_f64()
+    if steps:
+        p.nsteps = steps
     lo = np.empty(p.n, dtype=np.float64)
     hi = np.empty(p.n, dtype=np.float64)
     t = time.perf_counter()
@@ -268,14 +275,16 @@ def extra_heat3d_1000(rc, R, torch, workloads, cpu_oracle=True):
     sec = e0.elapsed_time(e1) / 1e3
     launch = sec / p.nsteps
     cells = 2.0 * p.n
-    out = {"workload": "3-D heat diffusion 1000^3 (n=1e9) FP64, dt=0.02, 1000 RK4 steps "
+    out = {"workload": f"3-D heat diffusion 1000^3 (n=1e9) FP64, dt=0.02, {p.nsteps} RK4 steps "
                        "(embedding, 2n states)",
            "cell_steps_per_s": cells * p.nsteps / sec, "seconds": round(sec, 3),
            "plan": plan, "launch_ms": round(launch * 1e3, 3),
            "roofline": {"bound": "hbm",
                         "achieved": round(cells * HEAT_BYTES_PER_CELL_STEP / launch / 1e9, 1),
                         "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                        "frac": round(cells * HEAT_BYTES_PER_CELL_STEP / launch / HBM_PEAK, 4)},
+                        "frac": round(cells * HEAT_BYTES_PER_CELL_STEP / launch / HBM_PEAK, 4),
+                        "traffic": traffic_from_profile("heat3d_kernel_1000cube_f64_pmc.txt",
+                                                        HEAT_SOURCES)},
            "alu_frac_fp64": round(cells * HEAT_OPS_PER_CELL_STEP / launch / FP64_PEAK, 4),
            "paper_cpu_minutes": {"m4.10xlarge": 472, "c5.24xlarge": 350.2}}
     del x_lo, x_hi, r_lo, r_hi, ws
@@ -346,6 +355,9 @@ def main():
                     help="skip the FP32 2^31-cell embedding and the Monte Carlo run")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--heat-only", type=int, default=0, metavar="STEPS",
+                    help="only run the 1000^3 heat grid for STEPS RK4 steps (profiling)")
+    ap.add_argument("--heat-P", type=int, default=0, help="rows per wave of the heat kernel")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of one embedding pass's bytes "
                          "(the reference kernel for HBM counter calibration)")
@@ -359,6 +371,15 @@ def main():
     import torch
     import workloads
     import paper_2001_10635_amd as R
+
+    if args.heat_only:
+        rc = R.Reach(0)
+        if args.heat_P:
+            rc.set_option("heat.P", args.heat_P)
+        out = extra_heat3d_1000(rc, R, torch, workloads, cpu_oracle=False, steps=args.heat_only)
+        print(json.dumps(out), flush=True)
+        rc.close()
+        return
 
     p = workloads.rd_2p26_f64()
     if args.copy_probe:

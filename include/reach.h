@@ -101,7 +101,7 @@ enum {
 typedef int32_t reach_dtype;
 enum { REACH_F64 = 0, REACH_F32 = 1 };
 
-enum { REACH_CTM = 1, REACH_RD = 2, REACH_LIN3 = 3, REACH_HEAT3D = 4 };
+enum { REACH_CTM = 1, REACH_RD = 2, REACH_LIN3 = 3, REACH_HEAT3D = 4, REACH_USER = 5 };
 
 /* A system of the list above.  `reserved` must be 0. */
 typedef struct reach_system {
@@ -345,6 +345,49 @@ reach_status reach_cancel(reach_ctx* ctx, uint64_t ticket);
 reach_status reach_server_stop(reach_ctx* ctx);
 reach_status reach_server_stats(reach_ctx* ctx, double* p50_us, double* p99_us,
                                 double* max_us, int64_t* completed);
+
+/* ---------------------------------------------------- user-defined systems
+ * A chain system given by its decomposition function as C source text (the
+ * embedding of Sec. 2.1 exists for any system with a decomposition function;
+ * PIRK takes the system dynamics as a C function).  The text defines
+ *
+ *   REACH_DEVICE real reach_d(real xm, real x, real xp, real hm, real h, real hp,
+ *                             real u, real uh, const real* prm, long long i,
+ *                             long long n);
+ *
+ * returning d_i(x, p, xh, ph) for cell i of an n-cell chain in which cell i
+ * couples only to cells i-1 and i+1: (xm, x, xp) are x_{i-1}, x_i, x_{i+1},
+ * (hm, h, hp) the same cells of xh, u = p_i and uh = ph_i (0 without inputs,
+ * the shared value for n_in = 1), prm the system's 8 parameters.  Neighbours
+ * past the chain's ends read as 0 (boundary conditions go in d, using i and
+ * n).  d must equal f on the diagonal (d(x, p, x, p) = f(x, p)) and be
+ * nondecreasing in x_j (j != i) and p and nonincreasing in xh and ph; the
+ * library cannot check this, and a d that breaks it gives no guarantee.
+ * `real` is double in FP64 runs and float in FP32 runs; helper functions
+ * must be declared REACH_DEVICE; the device math functions (sin, exp, fmin,
+ * ceil, ...) are available; names starting with reach_ are reserved.
+ *
+ * reach_user_create compiles the text with hipRTC for the context's device
+ * (no floating-point contraction, as the built-in kernels) and loads it;
+ * REACH_E_INVAL with the compiler's log in reach_last_error() when it does
+ * not compile.  The handle is owned by the caller (reach_user_destroy) and
+ * valid on the context's device only.
+ *
+ * reach_embed_rk4_user: Algorithm 3 (embedding RK4) for the user system.
+ * `sys` has kind REACH_USER, n, n_in and prm; the other arguments and the
+ * workspace rule are those of reach_embed_rk4 (2n elements of workspace
+ * when the chain spans several tiles and more than one pass).  Options
+ * "user.E" (cells per lane: 1, 2, 4, 8) and "user.K" (steps per pass). */
+typedef struct reach_user reach_user;
+
+reach_status reach_user_create(reach_ctx* ctx, const char* source, reach_user** out);
+void reach_user_destroy(reach_user* user);
+reach_status reach_embed_rk4_user(reach_ctx* ctx, const reach_user* user,
+                                  const reach_system* sys, reach_dtype dtype,
+                                  const void* x_lo, const void* x_hi, const void* p_lo,
+                                  const void* p_hi, double t0, double dt, int64_t nsteps,
+                                  void* r_lo, void* r_hi, void* workspace,
+                                  size_t workspace_bytes, void* stream);
 
 #ifdef __cplusplus
 }

@@ -32,7 +32,7 @@ STATUS_NAMES = {0: "OK", 1: "PENDING", -1: "E_INVAL", -2: "E_NOMEM", -3: "E_DEVI
                 -8: "E_BUSY", -9: "E_TIMEOUT"}
 
 REACH_F64, REACH_F32 = 0, 1
-REACH_CTM, REACH_RD, REACH_LIN3, REACH_HEAT3D = 1, 2, 3, 4
+REACH_CTM, REACH_RD, REACH_LIN3, REACH_HEAT3D, REACH_USER = 1, 2, 3, 4, 5
 
 
 class ReachError(RuntimeError):
@@ -100,6 +100,10 @@ def lib() -> ctypes.CDLL:
         "reach_cancel": ([vp, u64], i32),
         "reach_server_stop": ([vp], i32),
         "reach_server_stats": ([vp, P(d), P(d), P(d), P(i64)], i32),
+        "reach_user_create": ([vp, ctypes.c_char_p, P(vp)], i32),
+        "reach_user_destroy": ([vp], None),
+        "reach_embed_rk4_user": ([vp, vp, sysp, i32, vp, vp, vp, vp, d, d, i64, vp, vp, vp, sz,
+                                  vp], i32),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -279,6 +283,29 @@ def reach_growth_bound(ctx, sys: reach_system, dtype: int, x_lo, x_hi, p_lo, p_h
     return _chk(ctx, st, "reach_growth_bound")
 
 
+def reach_user_create(ctx, source: str):
+    """Compile a user decomposition function (C source text) for the context's
+    device; returns the handle (free it with reach_user_destroy)."""
+    h = ctypes.c_void_p()
+    st = lib().reach_user_create(ctx, source.encode(), ctypes.byref(h))
+    _chk(ctx, st, "reach_user_create")
+    return h
+
+
+def reach_user_destroy(user) -> None:
+    lib().reach_user_destroy(user)
+
+
+def reach_embed_rk4_user(ctx, user, sys: reach_system, dtype: int, x_lo, x_hi, p_lo, p_hi,
+                         t0: float, dt: float, nsteps: int, r_lo, r_hi, workspace=None,
+                         workspace_bytes: int = 0, stream=None) -> int:
+    st = lib().reach_embed_rk4_user(ctx, user, ctypes.byref(sys), int(dtype), _ptr(x_lo),
+                                    _ptr(x_hi), _ptr(p_lo), _ptr(p_hi), float(t0), float(dt),
+                                    int(nsteps), _ptr(r_lo), _ptr(r_hi), _ptr(workspace),
+                                    int(workspace_bytes), _stream(stream))
+    return _chk(ctx, st, "reach_embed_rk4_user")
+
+
 def reach_mc_samples(n: int, eps: float, delta: float) -> int:
     return int(lib().reach_mc_samples(int(n), float(eps), float(delta)))
 
@@ -430,6 +457,31 @@ class Reach:
         reach_montecarlo_range(self.ctx, sys, dtc, x_lo, x_hi, p_lo, p_hi, t0, dt, nsteps, s0, m,
                                seed, r_min, r_max, ws, nb, stream)
         return r_min, r_max
+
+    def user(self, source: str):
+        """Compile a user decomposition function; returns its handle."""
+        return reach_user_create(self.ctx, source)
+
+    def embed_user(self, user, prm, x_lo, x_hi, dt, nsteps, p_lo=None, p_hi=None, t0=0.0,
+                   r_lo=None, r_hi=None, stream=None):
+        n = x_lo.numel()
+        n_in = 0 if p_lo is None else p_lo.numel()
+        dtc = dtype_code(x_lo.dtype)
+        _check_tensor(x_lo, "x_lo", x_lo.dtype, n, x_lo.device)
+        _check_tensor(x_hi, "x_hi", x_lo.dtype, n, x_lo.device)
+        if p_lo is not None:
+            _check_tensor(p_lo, "p_lo", x_lo.dtype, n_in, x_lo.device)
+            _check_tensor(p_hi, "p_hi", x_lo.dtype, n_in, x_lo.device)
+        if r_lo is None:
+            r_lo = torch.empty_like(x_lo)
+        if r_hi is None:
+            r_hi = torch.empty_like(x_hi)
+        sys = make_system(REACH_USER, n, prm, n_in)
+        nb = 2 * n * x_lo.element_size()
+        ws = self.workspace(nb)
+        reach_embed_rk4_user(self.ctx, user, sys, dtc, x_lo, x_hi, p_lo, p_hi, t0, dt, nsteps,
+                             r_lo, r_hi, ws, nb, stream)
+        return r_lo, r_hi
 
     def growth_bound(self, kind, prm, x_lo, x_hi, dt, nsteps, p_lo=None, p_hi=None, t0=0.0,
                      r_lo=None, r_hi=None, stream=None):

@@ -17,7 +17,8 @@ SO = os.path.join(HERE, "libreach.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["embed.hip", "gb.hip", "heat3d.hip", "mc.hip", "batch.hip", "runtime.cpp", "server.cpp"]
+SOURCES = ["embed.hip", "gb.hip", "heat3d.hip", "mc.hip", "batch.hip", "runtime.cpp", "server.cpp",
+           "user.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument", "-Wno-unused-value", "-Wno-unused-result"]
@@ -46,7 +47,7 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         check_device_asm(BUILD, src, ARCH)
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", SO + ".tmp",
-           "-lpthread"]
+           "-lpthread", "-lhiprtc"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")

@@ -46,9 +46,10 @@ constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
 
 template <class T, int P>
 struct HeatRegs {
-    T t0[6][P];      // loaded planes (stage 1 inputs): z-3 .. z in use, z+1, z+2 in flight
+    T t0[6][P];      // loaded planes (stage 1 inputs): z-2 .. z in use, z+1 .. z+3 in flight
     T t[3][3][P];    // stage 2..4 inputs, three consecutive planes each
     T acc[2][2][P];  // K1 + 2 K2 (+ ...) after stages 1 and 2, by plane parity
+    T y2[2][P];      // step-start state handed to stage 3, by plane parity
     T b3[2][P];      // y + dt/6 (K1 + 2 K2 + 2 K3) handed to stage 4, by plane parity
 };
 
@@ -97,13 +98,28 @@ __device__ __forceinline__ void heat_publish(HeatLds<T, WV>& L, int lvl, int par
     L.e[lvl][par][c.w][1][c.lane] = v[P - 1];
 }
 
+// Rows of the waves above and below, for the stage inputs every level works
+// on in this iteration: read right after the barrier, all at once.
+template <class T>
+struct HeatEdges {
+    T up[4], dn[4];   // last row of the wave above, first row of the wave below
+};
+
+template <int PH, class T, int WV>
+__device__ __forceinline__ void heat_read_edges(HeatEdges<T>& E, const HeatLds<T, WV>& L,
+                                                const HeatCtx<T>& c) {
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const int par = pmod(PH - 1 - l, 2);
+        E.up[l] = L.e[l][par][c.wm][1][c.lane];
+        E.dn[l] = L.e[l][par][c.wp][0][c.lane];
+    }
+}
+
 // One stage of one plane: derivative of every row of this lane.
-template <class T, int P, int WV>
+template <class T, int P>
 __device__ __forceinline__ void heat_k(T (&k)[P], const T (&cur)[P], const T (&zm)[P],
-                                       const T (&zp)[P], const HeatLds<T, WV>& L, int lvl,
-                                       int par, const HeatCtx<T>& c) {
-    const T up = L.e[lvl][par][c.wm][1][c.lane];    // last row of the wave above
-    const T dn = L.e[lvl][par][c.wp][0][c.lane];    // first row of the wave below
+                                       const T (&zp)[P], T up, T dn, const HeatCtx<T>& c) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const T u = cur[p];
@@ -137,22 +153,25 @@ __device__ __forceinline__ void copy_rows(T (&d)[P], const T (&s)[P]) {
 // mirror copy due, so the uniform tests drop out.
 template <int LV, int PH, bool STEADY, bool ZT, class T, int P, int WV>
 __device__ __forceinline__ void heat_level(HeatRegs<T, P>& R, HeatLds<T, WV>& L,
-                                           HeatCtx<T>& c, const HeatRows<T, P>& rows, int z) {
+                                           const HeatEdges<T>& E, HeatCtx<T>& c,
+                                           const HeatRows<T, P>& rows, int z) {
     const int q = z - 1 - LV;
     constexpr int par = pmod(PH - 1 - LV, 2);
     T k[P];
     if constexpr (LV == 0) {
-        heat_k<T, P, WV>(k, R.t0[pmod(PH - 1, 6)], R.t0[pmod(PH - 2, 6)], R.t0[pmod(PH, 6)], L, 0,
-                         par, c);
+        heat_k<T, P>(k, R.t0[pmod(PH - 1, 6)], R.t0[pmod(PH - 2, 6)], R.t0[pmod(PH, 6)], E.up[0],
+                     E.dn[0], c);
     } else {
-        heat_k<T, P, WV>(k, R.t[LV - 1][pmod(PH - 1 - LV, 3)], R.t[LV - 1][pmod(PH - 2 - LV, 3)],
-                         R.t[LV - 1][pmod(PH - LV, 3)], L, LV, par, c);
+        heat_k<T, P>(k, R.t[LV - 1][pmod(PH - 1 - LV, 3)], R.t[LV - 1][pmod(PH - 2 - LV, 3)],
+                     R.t[LV - 1][pmod(PH - LV, 3)], E.up[LV], E.dn[LV], c);
     }
     if constexpr (LV < 3) {
-        // y: the state at the start of the step, plane q (loader ring for
-        // stages 1..3; plane z-4 has already left it, so stage 4 gets b3 =
-        // y + dt/6 (K1 + 2 K2 + 2 K3) and adds dt/6 K4)
-        const T (&y)[P] = R.t0[pmod(PH - 1 - LV, 6)];
+        // y: the state at the start of the step, plane q.  Stages 1 and 2
+        // read it from the loader ring; plane z-3 has left the ring by
+        // stage 3 (its slot holds a plane in flight), so stage 2 hands it on
+        // in y2, and stage 3 hands on b3 = y + dt/6 (K1 + 2 K2 + 2 K3), to
+        // which stage 4 adds dt/6 K4.
+        const T (&y)[P] = (LV == 2) ? R.y2[par] : R.t0[pmod(PH - 1 - LV, 6)];
         T (&nt)[P] = R.t[LV][pmod(PH - 1 - LV, 3)];
 #pragma unroll
         for (int p = 0; p < P; ++p) {
@@ -162,6 +181,7 @@ __device__ __forceinline__ void heat_level(HeatRegs<T, P>& R, HeatLds<T, WV>& L,
             } else if constexpr (LV == 1) {
                 R.acc[1][par][p] = fmaT(T(2), k[p], R.acc[0][par][p]);
                 nt[p] = fmaT(c.h2, k[p], y[p]);
+                R.y2[par][p] = y[p];
             } else {
                 const T acc = fmaT(T(2), k[p], R.acc[1][par][p]);
                 nt[p] = fmaT(c.dt, k[p], y[p]);
@@ -199,15 +219,18 @@ template <int PH, bool STEADY, bool ZT, class T, int P, int WV>
 __device__ __forceinline__ void heat_iter(HeatRegs<T, P>& R, HeatLds<T, WV>& L, HeatCtx<T>& c,
                                           const HeatRows<T, P>& rows, int z) {
     __syncthreads();
+    // plane z + 3 into the slot of plane z - 3, which no level reads any more
+    // (past the last plane this loads plane nz - 1 again: the mirror image the
+    // insulated face needs in the slot of plane nz)
+    const int zl = STEADY ? z + 3 : (z + 3 < c.nz ? z + 3 : c.nz - 1);
+    heat_load<T, P, WV>(R.t0[pmod(PH + 3, 6)], c, rows, zl);
+    HeatEdges<T> E;
+    heat_read_edges<PH, T, WV>(E, L, c);
     heat_publish<T, P, WV>(L, 0, pmod(PH, 2), R.t0[PH], c);
-    heat_level<0, PH, STEADY, ZT>(R, L, c, rows, z);
-    heat_level<1, PH, STEADY, ZT>(R, L, c, rows, z);
-    heat_level<2, PH, STEADY, ZT>(R, L, c, rows, z);
-    heat_level<3, PH, STEADY, ZT>(R, L, c, rows, z);
-    // plane z + 2; past the last plane this loads plane nz - 1 again, which is
-    // the mirror image the insulated face needs in the slot of plane nz
-    const int zl = STEADY ? z + 2 : (z + 2 < c.nz ? z + 2 : c.nz - 1);
-    heat_load<T, P, WV>(R.t0[pmod(PH + 2, 6)], c, rows, zl);
+    heat_level<0, PH, STEADY, ZT>(R, L, E, c, rows, z);
+    heat_level<1, PH, STEADY, ZT>(R, L, E, c, rows, z);
+    heat_level<2, PH, STEADY, ZT>(R, L, E, c, rows, z);
+    heat_level<3, PH, STEADY, ZT>(R, L, E, c, rows, z);
 }
 
 // Six iterations, z0 % 6 == 0 (the ring slots repeat with period 6).
@@ -225,13 +248,13 @@ __device__ __forceinline__ void heat_group(HeatRegs<T, P>& R, HeatLds<T, WV>& L,
 // Whole z sweep, iterations z = 0 .. nz + 3 (rounded up to whole groups:
 // the extra iterations compute nothing that is stored).  A first group with
 // the boundary tests, steady groups while each of their iterations z has
-// 5 <= z and z + 2 < nz, then the rest with the tests again.
+// 5 <= z and z + 3 < nz, then the rest with the tests again.
 template <bool ZT, class T, int P, int WV>
 __device__ __forceinline__ void heat_sweep(HeatRegs<T, P>& R, HeatLds<T, WV>& L, HeatCtx<T>& c,
                                            const HeatRows<T, P>& rows) {
     heat_group<false, ZT>(R, L, c, rows, 0);
     int z = 6;
-    for (; z + 6 <= c.nz - 2; z += 6) heat_group<true, ZT>(R, L, c, rows, z);
+    for (; z + 6 <= c.nz - 3; z += 6) heat_group<true, ZT>(R, L, c, rows, z);
     for (; z < c.nz + 4; z += 6) heat_group<false, ZT>(R, L, c, rows, z);
 }
 
@@ -302,13 +325,14 @@ __global__ __launch_bounds__(WAVE * WV) void heat3d_kernel(HeatPass a) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         R.acc[0][0][p] = R.acc[0][1][p] = R.acc[1][0][p] = R.acc[1][1][p] = T(0);
-        R.b3[0][p] = R.b3[1][p] = T(0);
+        R.y2[0][p] = R.y2[1][p] = R.b3[0][p] = R.b3[1][p] = T(0);
     }
 
-    // prologue: planes 0 and 1 in flight (plane 1 of a one-plane grid is the
-    // mirror of plane 0); plane -1 mirrors plane 0
+    // prologue: planes 0, 1 and 2 in flight (past the last plane, the
+    // mirror plane nz - 1 again); plane -1 mirrors plane 0
     heat_load<T, P, WV>(R.t0[0], c, rows, 0);
-    heat_load<T, P, WV>(R.t0[1], c, rows, c.nz > 1 ? 1 : 0);
+    heat_load<T, P, WV>(R.t0[1], c, rows, c.nz > 1 ? 1 : c.nz - 1);
+    heat_load<T, P, WV>(R.t0[2], c, rows, c.nz > 2 ? 2 : c.nz - 1);
     copy_rows(R.t0[5], R.t0[0]);
 
     if (c.ztile) heat_sweep<true>(R, L, c, rows);

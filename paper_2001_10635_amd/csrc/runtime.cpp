@@ -103,12 +103,17 @@ int64_t opt_get(const reach_ctx* c, const char* k) {
     return it == c->opt.end() ? 0 : it->second;
 }
 
-reach_status check_system(reach_ctx* c, const reach_system* s, reach_dtype dtype) {
+reach_status check_system_kind(reach_ctx* c, const reach_system* s, reach_dtype dtype,
+                               bool user) {
     if (!s) return fail(c, REACH_E_INVAL, "system is NULL");
     if (s->reserved != 0) return fail(c, REACH_E_INVAL, "reserved field must be 0");
+    if (s->kind == REACH_USER && !user)
+        return fail(c, REACH_E_INVAL, "REACH_USER systems run through reach_embed_rk4_user");
     if (s->kind != REACH_CTM && s->kind != REACH_RD && s->kind != REACH_LIN3 &&
-        s->kind != REACH_HEAT3D)
+        s->kind != REACH_HEAT3D && s->kind != REACH_USER)
         return fail(c, REACH_E_INVAL, "unknown system kind %d", s->kind);
+    if (user && s->kind != REACH_USER)
+        return fail(c, REACH_E_INVAL, "reach_embed_rk4_user takes a REACH_USER system");
     if (dtype != REACH_F64 && dtype != REACH_F32) return fail(c, REACH_E_INVAL, "bad dtype %d", dtype);
     if (s->n < 1 || s->n >= kMaxN) return fail(c, REACH_E_INVAL, "n = %lld out of range", (long long)s->n);
     if (s->n_in != 0 && s->n_in != 1 && s->n_in != s->n)
@@ -133,6 +138,10 @@ reach_status check_system(reach_ctx* c, const reach_system* s, reach_dtype dtype
         if (!(s->prm[4] > 0.0)) return fail(c, REACH_E_INVAL, "heat grid spacing must be > 0");
     }
     return REACH_OK;
+}
+
+reach_status check_system(reach_ctx* c, const reach_system* s, reach_dtype dtype) {
+    return check_system_kind(c, s, dtype, false);
 }
 
 // Steps of every launch that only the chain kernels implement.
@@ -520,7 +529,8 @@ const char* reach_last_error(const reach_ctx* c) { return c ? c->err.c_str() : "
 reach_status reach_set_option(reach_ctx* c, const char* key, int64_t value) {
     if (!c || !key) return REACH_E_INVAL;
     static const char* keys[] = {"embed.K", "embed.E", "embed.S", "mc.waves", "batch.waves",
-                                 "serve.mode", "serve.waves", "gb.E", "gb.K", "heat.P"};
+                                 "serve.mode", "serve.waves", "gb.E", "gb.K", "heat.P",
+                                 "user.E", "user.K"};
     bool known = false;
     for (const char* k : keys) known |= (std::strcmp(k, key) == 0);
     if (!known) return fail(c, REACH_E_INVAL, "unknown option %s", key);
@@ -1069,3 +1079,25 @@ reach_status reach_embed_rk4_each(reach_ctx* c, const reach_query* q, int64_t nq
 }
 
 }  // extern "C"
+
+
+// ------------------------------------------------ services for user.cpp --
+namespace reach {
+namespace rt {
+
+int ctx_device(const reach_ctx* c) { return c->device; }
+unsigned int* ctx_status(reach_ctx* c) { return c->status; }
+int64_t option(const reach_ctx* c, const char* key) { return opt_get(c, key); }
+reach_status set_error(reach_ctx* c, reach_status st, const std::string& msg) {
+    return fail(c, st, "%s", msg.c_str());
+}
+reach_status validate_user(reach_ctx* c, const reach_system* s, reach_dtype dtype) {
+    return check_system_kind(c, s, dtype, true);
+}
+void pass_buffers(int64_t passes, bool inplace_ok, bool alias,
+                  std::vector<std::pair<int, int>>* io, bool* final_copy) {
+    plan_io(passes, inplace_ok, alias, io, final_copy);
+}
+
+}  // namespace rt
+}  // namespace reach

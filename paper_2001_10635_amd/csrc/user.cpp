@@ -1,0 +1,366 @@
+// User-defined chain systems: a decomposition function given as source text,
+// compiled at run time with hipRTC for the context's device and run through
+// a temporally blocked embedding kernel like the built-in chains'
+// (Sec. 2.1: the embedding system exists for any system with a decomposition
+// function; PIRK likewise takes the system dynamics as a C function).
+//
+// The program handed to hipRTC is
+//   - the user text twice, inside namespaces reach_user_f64 / reach_user_f32
+//     with `real` = double / float (so one text serves both precisions);
+//   - the tile kernel below, instantiated for FP64 / FP32 and a few tile
+//     widths E, looked up by name expression.
+// The kernel is the chain embedding of Algorithm 3 with the classical RK4 of
+// Algorithm 1: one wavefront owns 64E consecutive cells of both sides in
+// registers, neighbours by DPP lane shifts, K steps per pass with a halo of
+// 4K cells per cut edge, cells past the chain's end held at 0.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/reach.h"
+#include "rt.hpp"
+
+using namespace reach;
+
+namespace {
+
+// Kernel argument block: one field list, stringized for the device program,
+// so host and device agree on the layout by construction.
+#define REACH_USER_PASS_FIELDS                                                        \
+    const void* src_lo; const void* src_hi; void* dst_lo; void* dst_hi;              \
+    const void* p_lo; const void* p_hi;                                              \
+    long long n; long long W; long long OUT; long long ksteps;                       \
+    int H; int in_mode; int check; int per_xcd;                                      \
+    double prm[8]; double h2; double dt; double dt6; unsigned int* status;
+#define REACH_STR2(...) #__VA_ARGS__
+#define REACH_STR(...) REACH_STR2(__VA_ARGS__)
+
+struct UserPass { REACH_USER_PASS_FIELDS };
+
+// tile widths (cells per lane); wider tiles of arbitrary user code spill
+constexpr int kUserE[] = {1, 2, 4, 8};
+constexpr int kNumE = 4;
+
+const char* kPrelude = R"(
+#define REACH_DEVICE __device__ static inline
+)";
+
+const char* kKernel = R"(
+namespace reach_rtc {
+
+template <int D> struct Real;
+template <> struct Real<0> { typedef double T; };
+template <> struct Real<1> { typedef float T; };
+
+// whole-wave lane shifts; lanes past the wave's ends receive 0.  The empty
+// asm keeps each shifted value a plain register move: some run-time compiler
+// versions otherwise fold the shift into the 64-bit arithmetic that uses it,
+// which gfx950 only allows for broadcast patterns.
+template <int CTRL> __device__ inline float dpp(float x) {
+    int v = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xF, 0xF, true);
+    asm volatile("" : "+v"(v));
+    return __int_as_float(v);
+}
+template <int CTRL> __device__ inline double dpp(double x) {
+    const unsigned long long v = (unsigned long long)__double_as_longlong(x);
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, 0xF, 0xF, true);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL, 0xF, 0xF, true);
+    asm volatile("" : "+v"(lo), "+v"(hi));
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+template <class T> __device__ inline T from_left(T x) { return dpp<0x138>(x); }
+template <class T> __device__ inline T from_right(T x) { return dpp<0x130>(x); }
+
+template <int D>
+__device__ inline typename Real<D>::T call_d(typename Real<D>::T xm, typename Real<D>::T x,
+                                            typename Real<D>::T xp, typename Real<D>::T hm,
+                                            typename Real<D>::T h, typename Real<D>::T hp,
+                                            typename Real<D>::T u, typename Real<D>::T uh,
+                                            const typename Real<D>::T* prm, long long i,
+                                            long long n) {
+    if constexpr (D == 0) return reach_user_f64::reach_d(xm, x, xp, hm, h, hp, u, uh, prm, i, n);
+    else return reach_user_f32::reach_d(xm, x, xp, hm, h, hp, u, uh, prm, i, n);
+}
+
+template <int D, int E>
+__global__ __launch_bounds__(64) void user_tile(UserPass a) {
+    typedef typename Real<D>::T T;
+    const int lane = threadIdx.x;
+    const long long b = blockIdx.x;
+    const long long w = (b & 7) * (long long)a.per_xcd + (b >> 3);
+    if (w >= a.W) return;
+    const long long span = 64LL * E;
+    const long long ts = w * a.OUT;
+    const T* src[2] = {(const T*)a.src_lo, (const T*)a.src_hi};
+    const T* pin[2] = {(const T*)a.p_lo, (const T*)a.p_hi};
+    T y[2][E], u[2][E];
+    bool ok[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const long long i = ts + (long long)lane * E + e;
+        ok[e] = i < a.n;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            y[s][e] = ok[e] ? src[s][i] : T(0);
+            u[s][e] = a.in_mode == 0 ? T(0) : a.in_mode == 1 ? pin[s][0] : (ok[e] ? pin[s][i] : T(0));
+        }
+    }
+    T prm[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) prm[j] = (T)a.prm[j];
+    const T h2 = (T)a.h2, dt = (T)a.dt, dt6 = (T)a.dt6;
+    for (long long k = 0; k < a.ksteps; ++k) {
+        T acc[2][E], t[2][E];
+#pragma unroll
+        for (int stage = 1; stage <= 4; ++stage) {
+            T in[2][E];
+#pragma unroll
+            for (int s = 0; s < 2; ++s)
+#pragma unroll
+                for (int e = 0; e < E; ++e) in[s][e] = (stage == 1) ? y[s][e] : t[s][e];
+            const T ln0 = from_left(in[0][E - 1]), ln1 = from_left(in[1][E - 1]);
+            const T rn0 = from_right(in[0][0]), rn1 = from_right(in[1][0]);
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const long long i = ts + (long long)lane * E + e;
+                const T xm = e == 0 ? ln0 : in[0][e - 1], xp = e == E - 1 ? rn0 : in[0][e + 1];
+                const T hm = e == 0 ? ln1 : in[1][e - 1], hp = e == E - 1 ? rn1 : in[1][e + 1];
+                T kk[2];
+                kk[0] = call_d<D>(xm, in[0][e], xp, hm, in[1][e], hp, u[0][e], u[1][e], prm, i, a.n);
+                kk[1] = call_d<D>(hm, in[1][e], hp, xm, in[0][e], xp, u[1][e], u[0][e], prm, i, a.n);
+#pragma unroll
+                for (int s = 0; s < 2; ++s) {
+                    const T kv = kk[s];
+                    if (stage == 1) { acc[s][e] = kv; t[s][e] = __builtin_fma(h2, kv, y[s][e]); }
+                    else if (stage == 2) { acc[s][e] = __builtin_fma(T(2), kv, acc[s][e]); t[s][e] = __builtin_fma(h2, kv, y[s][e]); }
+                    else if (stage == 3) { acc[s][e] = __builtin_fma(T(2), kv, acc[s][e]); t[s][e] = __builtin_fma(dt, kv, y[s][e]); }
+                    else { acc[s][e] = acc[s][e] + kv; y[s][e] = __builtin_fma(dt6, acc[s][e], y[s][e]); }
+                    if (!ok[e]) { t[s][e] = T(0); y[s][e] = T(0); }
+                }
+            }
+        }
+    }
+    const bool reaches_end = ts + span >= a.n;
+    const int olo = (w == 0) ? 0 : a.H;
+    const int ohi = reaches_end ? (int)(a.n - ts) : (int)(span - a.H);
+    T* dst[2] = {(T*)a.dst_lo, (T*)a.dst_hi};
+    unsigned bits = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int el = lane * E + e;
+        if (el >= olo && el < ohi) {
+            dst[0][ts + el] = y[0][e];
+            dst[1][ts + el] = y[1][e];
+            if (!__builtin_isfinite(y[0][e]) || !__builtin_isfinite(y[1][e])) bits |= 1u;
+            if (y[0][e] > y[1][e]) bits |= 2u;
+        }
+    }
+    if (a.check) {
+        const unsigned long long nf = __ballot(bits & 1u), od = __ballot(bits & 2u);
+        if ((nf | od) && lane == 0) atomicOr(a.status, (nf ? 1u : 0u) | (od ? 2u : 0u));
+    }
+}
+
+}  // namespace reach_rtc
+)";
+
+std::string name_expr(int dtype, int E) {
+    return "reach_rtc::user_tile<" + std::to_string(dtype) + ", " + std::to_string(E) + ">";
+}
+
+}  // namespace
+
+struct reach_user {
+    int device = 0;
+    hipModule_t mod = nullptr;
+    hipFunction_t fn[2][kNumE] = {};
+};
+
+extern "C" {
+
+reach_status reach_user_create(reach_ctx* c, const char* source, reach_user** out) {
+    if (!c || !source || !out) return REACH_E_INVAL;
+    *out = nullptr;
+    std::string text = kPrelude;
+    text += "struct UserPass { " REACH_STR(REACH_USER_PASS_FIELDS) " };\n";
+    text += "namespace reach_user_f64 {\ntypedef double real;\n";
+    text += source;
+    text += "\n}\nnamespace reach_user_f32 {\ntypedef float real;\n";
+    text += source;
+    text += "\n}\n";
+    text += kKernel;
+    hiprtcProgram prog;
+    if (hiprtcCreateProgram(&prog, text.c_str(), "reach_user.hip", 0, nullptr, nullptr) !=
+        HIPRTC_SUCCESS)
+        return rt::set_error(c, REACH_E_NOMEM, "hiprtcCreateProgram failed");
+    std::vector<std::string> names;
+    for (int d = 0; d < 2; ++d)
+        for (int e : kUserE) {
+            names.push_back(name_expr(d, e));
+            hiprtcAddNameExpression(prog, names.back().c_str());
+        }
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, rt::ctx_device(c)) != hipSuccess) {
+        hiprtcDestroyProgram(&prog);
+        return rt::set_error(c, REACH_E_DEVICE, "hipGetDeviceProperties failed");
+    }
+    std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
+    arch = arch.substr(0, arch.find(':'));
+    const char* opts[] = {arch.c_str(), "-O3", "-std=c++17", "-ffp-contract=off",
+                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult cr = hiprtcCompileProgram(prog, 8, opts);
+    if (cr != HIPRTC_SUCCESS) {
+        size_t ln = 0;
+        hiprtcGetProgramLogSize(prog, &ln);
+        std::string log(ln, '\0');
+        if (ln) hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        if (log.size() > 400) log = log.substr(0, 400) + " ...";
+        return rt::set_error(c, REACH_E_INVAL, "user source does not compile: " + log);
+    }
+    size_t code_size = 0;
+    hiprtcGetCodeSize(prog, &code_size);
+    std::vector<char> code(code_size);
+    hiprtcGetCode(prog, code.data());
+    std::vector<std::string> lowered;
+    for (const auto& nm : names) {
+        const char* low = nullptr;
+        hiprtcGetLoweredName(prog, nm.c_str(), &low);
+        lowered.push_back(low ? low : "");
+    }
+    hiprtcDestroyProgram(&prog);
+    reach_user* u = new reach_user;
+    u->device = rt::ctx_device(c);
+    if (hipSetDevice(u->device) != hipSuccess ||
+        hipModuleLoadData(&u->mod, code.data()) != hipSuccess) {
+        delete u;
+        return rt::set_error(c, REACH_E_DEVICE, "loading the compiled user module failed");
+    }
+    for (int d = 0, k = 0; d < 2; ++d)
+        for (int e = 0; e < kNumE; ++e, ++k)
+            if (hipModuleGetFunction(&u->fn[d][e], u->mod, lowered[k].c_str()) != hipSuccess) {
+                hipModuleUnload(u->mod);
+                delete u;
+                return rt::set_error(c, REACH_E_DEVICE, "user kernel " + names[k] + " not found");
+            }
+    *out = u;
+    return REACH_OK;
+}
+
+void reach_user_destroy(reach_user* u) {
+    if (!u) return;
+    if (u->mod) {
+        hipSetDevice(u->device);
+        hipModuleUnload(u->mod);
+    }
+    delete u;
+}
+
+reach_status reach_embed_rk4_user(reach_ctx* c, const reach_user* u, const reach_system* s,
+                                  reach_dtype dtype, const void* x_lo, const void* x_hi,
+                                  const void* p_lo, const void* p_hi, double t0, double dt,
+                                  int64_t nsteps, void* r_lo, void* r_hi, void* ws,
+                                  size_t ws_bytes, void* stream) {
+    if (!c) return REACH_E_INVAL;
+    if (!u) return rt::set_error(c, REACH_E_INVAL, "user system is NULL");
+    reach_status st = rt::validate_user(c, s, dtype);
+    if (st != REACH_OK) return st;
+    if (u->device != rt::ctx_device(c))
+        return rt::set_error(c, REACH_E_INVAL, "user system compiled for another device");
+    if (!x_lo || !x_hi || !r_lo || !r_hi) return rt::set_error(c, REACH_E_INVAL, "NULL state pointer");
+    if (s->n_in > 0 && (!p_lo || !p_hi)) return rt::set_error(c, REACH_E_INVAL, "NULL input pointer");
+    if (!(std::isfinite(dt) && dt > 0.0)) return rt::set_error(c, REACH_E_INVAL, "dt must be finite and > 0");
+    if (!std::isfinite(t0)) return rt::set_error(c, REACH_E_INVAL, "t0 must be finite");
+    if (nsteps < 0) return rt::set_error(c, REACH_E_INVAL, "nsteps < 0");
+    if (hipSetDevice(u->device) != hipSuccess) return rt::set_error(c, REACH_E_DEVICE, "hipSetDevice failed");
+    hipStream_t hs = (hipStream_t)stream;
+    const size_t bytes = (size_t)s->n * (dtype == REACH_F64 ? 8 : 4);
+    if (nsteps == 0) {
+        if (r_lo != x_lo && hipMemcpyAsync(r_lo, x_lo, bytes, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+            return rt::set_error(c, REACH_E_DEVICE, "copy failed");
+        if (r_hi != x_hi && hipMemcpyAsync(r_hi, x_hi, bytes, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+            return rt::set_error(c, REACH_E_DEVICE, "copy failed");
+        return REACH_OK;
+    }
+    // plan: the smallest tile that holds the chain, else E = 8 with K steps per pass
+    const int64_t n = s->n;
+    int E = (int)rt::option(c, "user.E");
+    int K = (int)rt::option(c, "user.K");
+    int ei = -1;
+    if (E) {
+        for (int j = 0; j < kNumE; ++j) if (kUserE[j] == E) ei = j;
+        if (ei < 0) return rt::set_error(c, REACH_E_INVAL, "user.E must be 1, 2, 4 or 8");
+    } else {
+        for (int j = 0; j < kNumE && ei < 0; ++j) if ((int64_t)64 * kUserE[j] >= n) ei = j;
+        if (ei < 0) ei = kNumE - 1;
+        E = kUserE[ei];
+    }
+    const int64_t span = (int64_t)64 * E;
+    UserPass a{};
+    int64_t passes;
+    if (n <= span && !K) {
+        K = (int)std::min<int64_t>(nsteps, 1 << 30);
+        a.W = 1; a.OUT = 0; a.H = 0;
+        passes = (nsteps + K - 1) / K;
+    } else {
+        if (!K) K = 8;
+        if ((int64_t)8 * K >= span)
+            return rt::set_error(c, REACH_E_INVAL, "user.K too large for the tile width");
+        a.H = 4 * K;
+        a.OUT = span - 2 * a.H;
+        a.W = (n <= span) ? 1 : 1 + (n - span + a.OUT - 1) / a.OUT;
+        passes = (nsteps + K - 1) / K;
+    }
+    const bool alias = (r_lo == x_lo) || (r_hi == x_hi) || (r_lo == x_hi) || (r_hi == x_lo);
+    const bool inplace_ok = (a.W == 1);
+    const bool need_ws = !inplace_ok && (passes >= 2 || alias);
+    void *w_lo = nullptr, *w_hi = nullptr;
+    if (need_ws) {
+        if (!ws || ws_bytes < 2 * bytes)
+            return rt::set_error(c, REACH_E_INVAL, "workspace of " + std::to_string(2 * bytes) +
+                                                       " bytes needed");
+        w_lo = ws;
+        w_hi = (char*)ws + bytes;
+    }
+    std::vector<std::pair<int, int>> io;
+    bool final_copy = false;
+    rt::pass_buffers(passes, inplace_ok, alias, &io, &final_copy);
+    const void* lo_of[3] = {x_lo, r_lo, w_lo};
+    const void* hi_of[3] = {x_hi, r_hi, w_hi};
+    a.p_lo = s->n_in ? p_lo : nullptr;
+    a.p_hi = s->n_in ? p_hi : nullptr;
+    a.in_mode = s->n_in == 0 ? 0 : (s->n_in == 1 ? 1 : 2);
+    a.n = n;
+    a.per_xcd = (int)((a.W + 7) / 8);
+    for (int j = 0; j < 8; ++j) a.prm[j] = s->prm[j];
+    a.h2 = dt / 2.0; a.dt = dt; a.dt6 = dt / 6.0;
+    a.status = rt::ctx_status(c);
+    hipFunction_t fn = u->fn[dtype == REACH_F64 ? 0 : 1][ei];
+    const unsigned grid = (unsigned)(8 * (int64_t)a.per_xcd);
+    int64_t done = 0;
+    for (int64_t p = 0; p < passes; ++p) {
+        a.src_lo = lo_of[io[p].first];
+        a.src_hi = hi_of[io[p].first];
+        a.dst_lo = (void*)lo_of[io[p].second];
+        a.dst_hi = (void*)hi_of[io[p].second];
+        a.ksteps = std::min<int64_t>(K, nsteps - done);
+        a.check = (p == passes - 1) ? 1 : 0;
+        void* args[] = {&a};
+        if (hipModuleLaunchKernel(fn, grid, 1, 1, 64, 1, 1, 0, hs, args, nullptr) != hipSuccess)
+            return rt::set_error(c, REACH_E_DEVICE, "user kernel launch failed");
+        done += a.ksteps;
+    }
+    if (final_copy) {
+        if (hipMemcpyAsync(r_lo, w_lo, bytes, hipMemcpyDeviceToDevice, hs) != hipSuccess ||
+            hipMemcpyAsync(r_hi, w_hi, bytes, hipMemcpyDeviceToDevice, hs) != hipSuccess)
+            return rt::set_error(c, REACH_E_DEVICE, "copy failed");
+    }
+    return REACH_OK;
+}
+
+}  // extern "C"
