@@ -48,8 +48,10 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-EMBED_SOURCES = ("dev.hpp", "embed.hip", "kernels.hpp")
-HEAT_SOURCES = ("dev.hpp", "heat3d.hip", "kernels.hpp")
+# the kernel sources a PMC summary is tied to (the pass structs in kernels.hpp
+# change with the kernels that read them)
+EMBED_SOURCES = ("dev.hpp", "embed.hip")
+HEAT_SOURCES = ("dev.hpp", "heat3d.hip")
 
 
 def source_hash(files=EMBED_SOURCES) -> str:

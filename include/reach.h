@@ -154,6 +154,8 @@ const char* reach_last_error(const reach_ctx* ctx);
                   (with 16, 12, 8 or 4 wavefronts per block; 0 = tuned default)
      "mc.waves"   resident waves of the Monte Carlo kernel (0 = default)
      "batch.waves" resident waves of the batch kernel (0 = default)
+     "batch.split" 1: one wave per side of each cooperative query (shorter
+                  latency per query); 0 (default): one wave per query
    Returns REACH_E_INVAL for an unknown key or a value out of range. */
 reach_status reach_set_option(reach_ctx* ctx, const char* key, int64_t value);
 int64_t reach_get_option(const reach_ctx* ctx, const char* key);

@@ -6,9 +6,9 @@
 // loop.  The arithmetic per cell is the same code the large-n embedding kernel
 // runs, so a query gives the same box alone, in a batch, or served.
 //
-//   batch_kernel   persistent grid; each wave pops the next work item (a query,
-//                  or one side of a cooperative query) from a device counter
-//                  until the batch is exhausted.
+//   batch_kernel   persistent grid; each wave pops the next work item (a whole
+//                  query, or with `split` one side of a cooperative query) from
+//                  a device counter until the batch is exhausted.
 //   single_kernel  one query per launch (the baseline the batch is compared with).
 //   serve_kernel   persistent grid fed through a ring of descriptors in pinned
 //                  host memory; each wave claims the next work item (sequence
@@ -122,13 +122,24 @@ __device__ __forceinline__ unsigned order_bits(const QDesc& d) {
 __global__ __launch_bounds__(64) void batch_kernel(const QDesc* __restrict__ desc, int64_t nq,
                                                    unsigned long long* counter,
                                                    unsigned int* qflags, unsigned int* pair,
-                                                   unsigned int* status) {
+                                                   unsigned int* status, int split) {
     const int lane = threadIdx.x;
+    const uint64_t items = split ? 2 * (uint64_t)nq : (uint64_t)nq;
     for (;;) {
         uint64_t u = 0;
         if (lane == 0) u = atomicAdd(counter, 1ULL);
         u = wave_bcast(u);
-        if (u >= 2 * (uint64_t)nq) break;
+        if (u >= items) break;
+        if (!split) {
+            // whole queries: both sides in one wave (most work per wave)
+            const QDesc d = desc[u];
+            const unsigned bits = run_query(d);
+            if (lane == 0 && bits) {
+                atomicOr(&qflags[d.tag], bits);
+                atomicOr(status, bits);
+            }
+            continue;
+        }
         const uint64_t i = u >> 1;
         const int side = (int)(u & 1);
         const QDesc d = desc[i];
@@ -222,9 +233,9 @@ __global__ __launch_bounds__(64) void serve_kernel(ServeSlot* ring, int32_t slot
 
 hipError_t launch_batch(const QDesc* d, int64_t nq, unsigned long long* counter,
                         unsigned int* qflags, unsigned int* pair, unsigned int* status,
-                        int64_t grid, hipStream_t s) {
+                        int split, int64_t grid, hipStream_t s) {
     hipLaunchKernelGGL(batch_kernel, dim3((unsigned)grid), dim3(WAVE), 0, s, d, nq, counter,
-                       qflags, pair, status);
+                       qflags, pair, status, split);
     return hipGetLastError();
 }
 

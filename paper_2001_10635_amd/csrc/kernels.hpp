@@ -137,11 +137,12 @@ struct QDesc {
     int64_t tag;        // caller's index (batch) or ticket slot (serving)
 };
 
-// Persistent batch worker: `grid` waves pull work items (2 per query)
-// through *counter; pair[i] counts the finished sides of query i.
+// Persistent batch worker: `grid` waves pull work items through *counter:
+// whole queries, or with `split` two per query (one per side of a
+// cooperative chain), pair[i] counting the finished sides of query i.
 hipError_t launch_batch(const QDesc* d, int64_t nq, unsigned long long* counter,
                         unsigned int* qflags, unsigned int* pair, unsigned int* status,
-                        int64_t grid, hipStream_t stream);
+                        int split, int64_t grid, hipStream_t stream);
 // Zero `count` 32-bit words (a kernel, so it can sit in a captured graph).
 hipError_t launch_zero(void* p, int64_t count, hipStream_t stream);
 // One query with a plain launch (the one-launch-per-query baseline).

@@ -529,6 +529,7 @@ const char* reach_last_error(const reach_ctx* c) { return c ? c->err.c_str() : "
 reach_status reach_set_option(reach_ctx* c, const char* key, int64_t value) {
     if (!c || !key) return REACH_E_INVAL;
     static const char* keys[] = {"embed.K", "embed.E", "embed.S", "mc.waves", "batch.waves",
+                                 "batch.split",
                                  "serve.mode", "serve.waves", "gb.E", "gb.K", "heat.P",
                                  "user.E", "user.K"};
     bool known = false;
@@ -1017,23 +1018,26 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     auto* qflags = (unsigned int*)(base + align256(8));
     auto* pair = (unsigned int*)(base + align256(8) + align256(4 * (size_t)nq));
     auto* ddesc = (QDesc*)(base + align256(8) + 2 * align256(4 * (size_t)nq));
+    // whole queries per wave by default (most work per wave, best throughput);
+    // batch.split = 1 gives each side of a cooperative query its own wave
+    const int split = opt_get(c, "batch.split") ? 1 : 0;
     int64_t grid = opt_get(c, "batch.waves");
     if (grid <= 0) grid = (int64_t)c->cus * 8;
-    grid = std::min<int64_t>(grid, 2 * nq);
+    grid = std::min<int64_t>(grid, split ? 2 * nq : nq);
 
     auto enqueue = [&](hipStream_t s) -> hipError_t {
         hipError_t e = launch_zero(base, (int64_t)(align256(8) + 2 * align256(4 * (size_t)nq)) / 4, s);
         if (e != hipSuccess) return e;
         e = hipMemcpyAsync(ddesc, c->staging, sizeof(QDesc) * nq, hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
-        return launch_batch(ddesc, nq, counter, qflags, pair, c->status, grid, s);
+        return launch_batch(ddesc, nq, counter, qflags, pair, c->status, split, grid, s);
     };
 
     if (hs == nullptr) {
         hipError_t e = enqueue(hs);
         if (e != hipSuccess) return hip_fail(c, e, "batch launch");
     } else {
-        GraphKey key{nq, ws, c->staging, grid, hs};
+        GraphKey key{nq, ws, c->staging, grid * 2 + split, hs};
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             hipGraph_t g = nullptr;

@@ -66,13 +66,19 @@ def mix():
     return Batch(workloads.query_stream(400, 5.0e4, seed=4242))
 
 
-def test_batch_equals_alone_and_oracle(rc, mix):
+@pytest.mark.parametrize("split", [0, 1])
+def test_batch_equals_alone_and_oracle(rc, mix, split):
     qs = mix.queries()
     nb = R.reach_batch_workspace_bytes(len(qs))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
-    say("batch 400 queries")
-    R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
-    assert rc.sync() == R.REACH_OK
+    mix.clear()
+    say(f"batch 400 queries split={split}")
+    rc.set_option("batch.split", split)
+    try:
+        R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
+        assert rc.sync() == R.REACH_OK
+    finally:
+        rc.set_option("batch.split", 0)
     got = mix.results()
     for k, d in enumerate(mix.items):
         a = alone(rc, d)
@@ -129,17 +135,21 @@ def test_each_equals_batch(rc, mix):
         assert np.array_equal(got[k][0], ref[k][0]) and np.array_equal(got[k][1], ref[k][1])
 
 
+@pytest.mark.parametrize("split", [0, 1])
 @pytest.mark.parametrize("waves", [1, 3, 64])
-def test_batch_wave_count_invariance(rc, mix, waves):
+def test_batch_wave_count_invariance(rc, mix, waves, split):
     qs = mix.queries()[:60]
     nb = R.reach_batch_workspace_bytes(len(qs))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    mix.clear()
     rc.set_option("batch.waves", waves)
+    rc.set_option("batch.split", split)
     try:
         R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
         assert rc.sync() == R.REACH_OK
     finally:
         rc.set_option("batch.waves", 0)
+        rc.set_option("batch.split", 0)
     got = mix.results()[:60]
     for k in range(60):
         a = alone(rc, mix.items[k])

@@ -160,7 +160,8 @@ def test_user_errors(rc, users):
     say("user compile error")
     with pytest.raises(R.ReachError) as ei:
         rc.user("REACH_DEVICE real reach_d(real xm) { return undefined_name; }")
-    assert ei.value.args[0] == R.REACH_E_INVAL
+    assert ei.value.status == R.REACH_E_INVAL
+    assert "undefined_name" in str(ei.value)          # the compiler's log is passed on
     g, _ = users["SINE"]
     x = to_dev(np.zeros(16))
     lib = R.lib()
