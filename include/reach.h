@@ -150,8 +150,9 @@ const char* reach_last_error(const reach_ctx* ctx);
      "embed.E"    cells per lane of the embedding kernel (0 = tuned default)
      "embed.S"    sides per wavefront, 1 or 2 (0 = tuned default)
      "gb.E", "gb.K"  cells per lane / steps per pass of the growth-bound kernel
-     "heat.P"     rows per wavefront of the 3-D heat kernel: 2, 3, 4 or 8
-                  (with 16, 12, 8 or 4 wavefronts per block; 0 = tuned default)
+     "heat.P"     rows per wavefront of the 3-D heat kernel: 2, 3, 4, 5 or 8
+                  (with 16, 12, 8, 8 or 4 wavefronts per block; FP64 builds 2, 4
+                  and 5, FP32 2, 3, 4 and 8; 0 = tuned default)
      "mc.waves"   resident waves of the Monte Carlo kernel (0 = default)
      "batch.waves" resident waves of the batch kernel (0 = default)
      "batch.split" 1: one wave per side of each cooperative query (shorter
@@ -180,7 +181,9 @@ reach_status reach_plan_embed(reach_ctx* ctx, const reach_system* sys, reach_dty
    bucket of n in the context; later calls of that bucket use it.  Arguments
    are those of reach_embed_rk4 (r_lo / r_hi receive scratch results).
    best[0] = E, best[1] = K, best[2] = femtoseconds per state-step (2n per
-   step), best[3] = S (sides per wavefront).  `best` is a host array of 4.  With REACH_AUTOTUNE_CACHE set to a file name, results are appended
+   step), best[3] = S (sides per wavefront).  `best` is a host array of 4.
+   For REACH_HEAT3D it times the built heat kernel shapes instead ("heat.P"):
+   best[0] = rows per wavefront, best[1] = 1, best[3] = 1.  With REACH_AUTOTUNE_CACHE set to a file name, results are appended
    there and read back by reach_ctx_create on the same device architecture. */
 reach_status reach_autotune_embed(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
                                   const void* x_lo, const void* x_hi,
