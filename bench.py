@@ -37,10 +37,11 @@ RD_FLOPS_PER_STATE_STEP = 45
 # w*(c - y), two minimum operations) and its difference with the neighbour's,
 # 6; plus 13 for the stage inputs and the update.
 CTM_OPS_PER_STATE_STEP = 37
-# 3-D heat: per stage 5 adds, one FMA and one multiply (8); the four RK4
-# updates 2 + 4 + 6 + 2 (the stage-3 level also folds the running sum into
-# y + dt/6 (K1 + 2 K2 + 2 K3)).  One pass = one step: 8 B read + 8 B written.
-HEAT_OPS_PER_CELL_STEP = 46
+# 3-D heat: per stencil application 5 adds, one FMA and one multiply (8),
+# plus the update FMA (2), four applications per RK4 step (the step's
+# stability polynomial in nested form).  One pass = one step: 8 B read + 8 B
+# written.
+HEAT_OPS_PER_CELL_STEP = 40
 HEAT_BYTES_PER_CELL_STEP = 16
 
 

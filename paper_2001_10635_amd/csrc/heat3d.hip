@@ -8,15 +8,21 @@
 // Faces are insulated (a neighbour past the face equals the cell itself)
 // except x = nx - 1, whose outside neighbour is held at temperature 0.
 //
+// The grid is linear and autonomous, so one classical RK4 step is exactly the
+// stability polynomial R(hA) = I + hA + (hA)^2/2 + (hA)^3/6 + (hA)^4/24 applied
+// to the state.  Each of the four stencil applications of a step evaluates it
+// in nested form, w <- y + (h/j) A w for j = 4, 3, 2, 1 starting from w = y
+// (the same polynomial as the four stages with their running sum, one update
+// per level and no running sum to carry).
+//
 // 2.5-D blocking.  A block owns an x-y tile: 64 lanes along x (DPP shifts give
 // the x neighbours) by WV waves of P rows along y (rows of one lane are
 // registers; the first and last row of each wave go through LDS to the
-// waves above and below).  The block streams through z.  The four RK4 stages
-// of one step form a pipeline of levels: in iteration z the loader brings in
-// plane z, level 0 (stage 1) works on plane z-1, level 1 on z-2, level 2 on
-// z-3, level 3 (stage 4) on z-4 and writes the new state of that plane.
-// Each level keeps its stage input for three consecutive planes (the z
-// neighbours) and hands its running sum K1 + 2 K2 + ... to the next level.
+// waves above and below).  The block streams through z.  The four stencil
+// applications of one step form a pipeline of levels: in iteration z the loader brings in
+// plane z + 3, level 0 works on plane z-1, level 1 on z-2, level 2 on z-3,
+// level 3 on z-4 and writes the new state of that plane.  Each level keeps
+// its input for three consecutive planes (the z neighbours).
 // One step costs one read and one write of the state per cell; the tile's
 // halo (4 cells on each cut face, one per stage) is recomputed, not
 // exchanged.
@@ -46,16 +52,15 @@ constexpr int pmod(int a, int m) { return ((a % m) + m) % m; }
 
 template <class T, int P>
 struct HeatRegs {
-    T t0[6][P];      // loaded planes (stage 1 inputs): z-2 .. z in use, z+1 .. z+3 in flight
-    T t[3][3][P];    // stage 2..4 inputs, three consecutive planes each
-    T acc[2][2][P];  // K1 + 2 K2 (+ ...) after stages 1 and 2, by plane parity
-    T y2[2][P];      // step-start state handed to stage 3, by plane parity
-    T b3[2][P];      // y + dt/6 (K1 + 2 K2 + 2 K3) handed to stage 4, by plane parity
+    T t0[6][P];      // loaded planes (level 0 inputs): z-2 .. z in use, z+1 .. z+3 in flight
+    T t[3][3][P];    // level 1..3 inputs, three consecutive planes each
+    T y2[2][P];      // step-start state handed to level 2, by plane parity
+    T y3[2][P];      // step-start state handed to level 3, by plane parity
 };
 
 template <class T, int WV>
 struct HeatLds {
-    T e[4][2][WV][2][WAVE];   // [stage input][plane parity][wave][first/last row][lane]
+    T e[4][2][WV][2][WAVE];   // [level input][plane parity][wave][first/last row][lane]
 };
 
 template <class T>
@@ -70,7 +75,7 @@ struct HeatCtx {
     bool zlane;          // lane is a zero ghost (outside the open face)
     bool ztile;          // the tile holds a zero ghost lane (uniform)
     bool xout;           // lane's cell is an output of this tile
-    T a, h2, dt, dt6;
+    T a, h4, h3, h2, dt;   // a = alpha / dx^2; dt/4, dt/3, dt/2, dt
     unsigned bits;
 };
 
@@ -98,7 +103,7 @@ __device__ __forceinline__ void heat_publish(HeatLds<T, WV>& L, int lvl, int par
     L.e[lvl][par][c.w][1][c.lane] = v[P - 1];
 }
 
-// Rows of the waves above and below, for the stage inputs every level works
+// Rows of the waves above and below, for the inputs every level works
 // on in this iteration: read right after the barrier, all at once.
 template <class T>
 struct HeatEdges {
@@ -116,7 +121,7 @@ __device__ __forceinline__ void heat_read_edges(HeatEdges<T>& E, const HeatLds<T
     }
 }
 
-// One stage of one plane: derivative of every row of this lane.
+// One stencil application on one plane: A w for every row of this lane.
 template <class T, int P>
 __device__ __forceinline__ void heat_k(T (&k)[P], const T (&cur)[P], const T (&zm)[P],
                                        const T (&zp)[P], T up, T dn, const HeatCtx<T>& c) {
@@ -144,8 +149,8 @@ __device__ __forceinline__ void copy_rows(T (&d)[P], const T (&s)[P]) {
     for (int p = 0; p < P; ++p) d[p] = s[p];
 }
 
-// Level LV (stage LV + 1) in the iteration with z % 6 == PH.
-// Level LV (stage LV + 1) in the iteration with z % 6 == PH, working on plane
+// Level LV (stencil application LV + 1 of the step) in the iteration with
+// z % 6 == PH, working on plane
 // q = z - 1 - LV.  Levels run in every iteration: before their first plane
 // and after their last one they compute values nobody reads (they land in
 // ring slots, pipes and LDS rows that are rewritten before their next use)
@@ -166,27 +171,18 @@ __device__ __forceinline__ void heat_level(HeatRegs<T, P>& R, HeatLds<T, WV>& L,
                      R.t[LV - 1][pmod(PH - LV, 3)], E.up[LV], E.dn[LV], c);
     }
     if constexpr (LV < 3) {
-        // y: the state at the start of the step, plane q.  Stages 1 and 2
-        // read it from the loader ring; plane z-3 has left the ring by
-        // stage 3 (its slot holds a plane in flight), so stage 2 hands it on
-        // in y2, and stage 3 hands on b3 = y + dt/6 (K1 + 2 K2 + 2 K3), to
-        // which stage 4 adds dt/6 K4.
+        // y: the state at the start of the step, plane q.  Levels 0 and 1
+        // read it from the loader ring; plane z-3 has left the ring by level 2
+        // (its slot holds a plane in flight), so level 1 hands it on in y2
+        // and level 2 in y3.
         const T (&y)[P] = (LV == 2) ? R.y2[par] : R.t0[pmod(PH - 1 - LV, 6)];
         T (&nt)[P] = R.t[LV][pmod(PH - 1 - LV, 3)];
+        const T cw = (LV == 0) ? c.h4 : (LV == 1) ? c.h3 : c.h2;
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            if constexpr (LV == 0) {
-                R.acc[0][par][p] = k[p];
-                nt[p] = fmaT(c.h2, k[p], y[p]);
-            } else if constexpr (LV == 1) {
-                R.acc[1][par][p] = fmaT(T(2), k[p], R.acc[0][par][p]);
-                nt[p] = fmaT(c.h2, k[p], y[p]);
-                R.y2[par][p] = y[p];
-            } else {
-                const T acc = fmaT(T(2), k[p], R.acc[1][par][p]);
-                nt[p] = fmaT(c.dt, k[p], y[p]);
-                R.b3[par][p] = fmaT(c.dt6, acc, y[p]);
-            }
+            nt[p] = fmaT(cw, k[p], y[p]);
+            if constexpr (LV == 1) R.y2[par][p] = y[p];
+            if constexpr (LV == 2) R.y3[par][p] = y[p];
         }
         if (ZT) heat_zero_ghost<T, P>(nt, c);
         heat_publish<T, P, WV>(L, LV + 1, par, nt, c);
@@ -206,7 +202,7 @@ __device__ __forceinline__ void heat_level(HeatRegs<T, P>& R, HeatLds<T, WV>& L,
         const bool live = STEADY || (q >= 0 && q < c.nz);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const T v = fmaT(c.dt6, k[p], R.b3[par][p]);
+            const T v = fmaT(c.dt, k[p], R.y3[par][p]);
             if (live && rows.out[p] && c.xout) {
                 out[rows.off[p] + c.xl] = v;
                 if (!finiteT(v)) c.bits |= ST_NONFINITE;
@@ -299,9 +295,10 @@ __global__ __launch_bounds__(WAVE * WV) void heat3d_kernel(HeatPass a) {
     c.ztile = (x0 + WAVE > a.nx) || (x0 <= -1 - a.nx);
     c.xout = c.lane >= HEAT_R && c.lane < WAVE - HEAT_R && gx < a.nx;
     c.a = (T)a.a;
+    c.h4 = (T)(a.dt / 4.0);
+    c.h3 = (T)(a.dt / 3.0);
     c.h2 = (T)a.h2;
     c.dt = (T)a.dt;
-    c.dt6 = (T)a.dt6;
     c.bits = 0;
 
     HeatRows<T, P> rows;
@@ -323,10 +320,7 @@ __global__ __launch_bounds__(WAVE * WV) void heat3d_kernel(HeatPass a) {
 #pragma unroll
         for (int p = 0; p < P; ++p) R.t[l][0][p] = R.t[l][1][p] = R.t[l][2][p] = T(0);
 #pragma unroll
-    for (int p = 0; p < P; ++p) {
-        R.acc[0][0][p] = R.acc[0][1][p] = R.acc[1][0][p] = R.acc[1][1][p] = T(0);
-        R.y2[0][p] = R.y2[1][p] = R.b3[0][p] = R.b3[1][p] = T(0);
-    }
+    for (int p = 0; p < P; ++p) R.y2[0][p] = R.y2[1][p] = R.y3[0][p] = R.y3[1][p] = T(0);
 
     // prologue: planes 0, 1 and 2 in flight (past the last plane, the
     // mirror plane nz - 1 again); plane -1 mirrors plane 0
@@ -371,9 +365,11 @@ static hipError_t go_heat(const HeatPass& a, int64_t grid, hipStream_t s) {
 }
 
 // (P, WV) shapes: rows per wave, waves per block.  FP64 keeps the shapes
-// whose registers fit without spilling (4 x 8) or nearly (2 x 16).
+// whose registers fit in the steady loop (4 x 8, 5 x 8, 3 x 12, 2 x 16).
 bool heat_has_shape(int dtype, int P, int WV) {
-    if (dtype == 0) return (P == 4 && WV == 8) || (P == 2 && WV == 16);
+    if (dtype == 0)
+        return (P == 4 && WV == 8) || (P == 2 && WV == 16) || (P == 5 && WV == 8) ||
+               (P == 3 && WV == 12);
     return (P == 4 && WV == 8) || (P == 2 && WV == 16) || (P == 8 && WV == 4) ||
            (P == 3 && WV == 12);
 }
@@ -383,6 +379,8 @@ hipError_t launch_heat3d(int dtype, int P, int WV, const HeatPass& a, int64_t gr
     if (dtype == 0) {
         if (P == 4 && WV == 8) return go_heat<double, 4, 8>(a, grid, s);
         if (P == 2 && WV == 16) return go_heat<double, 2, 16>(a, grid, s);
+        if (P == 5 && WV == 8) return go_heat<double, 5, 8>(a, grid, s);
+        if (P == 3 && WV == 12) return go_heat<double, 3, 12>(a, grid, s);
     } else {
         if (P == 4 && WV == 8) return go_heat<float, 4, 8>(a, grid, s);
         if (P == 2 && WV == 16) return go_heat<float, 2, 16>(a, grid, s);

@@ -175,7 +175,7 @@ struct EmbedPlan {
 // Defaults measured on MI355X for the 2^26-cell chains (overridden by the
 // autotuner or its cache).  Cooperative chains run one side per wave.
 TuneEntry default_tune(int kind, int dtype) {
-    if (kind == REACH_HEAT3D) return TuneEntry{4, 1, 1};   // rows per wave, 8 waves per block
+    if (kind == REACH_HEAT3D) return TuneEntry{2, 1, 1};   // rows per wave, 16 waves per block
     if (kind == REACH_LIN3) return dtype == REACH_F64 ? TuneEntry{12, 12, 2} : TuneEntry{16, 8, 2};
     return dtype == REACH_F64 ? TuneEntry{24, 20, 1} : TuneEntry{48, 12, 1};
 }
@@ -242,7 +242,9 @@ struct HeatPlan {
     int64_t TX = 0, TY = 0;   // tiles per side along x / y
 };
 
-int heat_waves(int P) { return P == 4 ? 8 : P == 2 ? 16 : P == 8 ? 4 : P == 3 ? 12 : 0; }
+int heat_waves(int P) {
+    return P == 4 ? 8 : P == 5 ? 8 : P == 2 ? 16 : P == 8 ? 4 : P == 3 ? 12 : 0;
+}
 
 reach_status plan_heat(reach_ctx* c, const reach_system* s, reach_dtype dtype, HeatPlan* p) {
     int P = (int)opt_get(c, "heat.P");
@@ -388,7 +390,7 @@ reach_status autotune_heat3d(reach_ctx* c, const reach_system* s, reach_dtype dt
     double best_ps = 1e300;
     int bestP = 0;
     reach_status st = REACH_OK;
-    for (int P : {2, 3, 4, 8}) {
+    for (int P : {2, 3, 4, 5, 8}) {
         if (!heat_has_shape(dtype == REACH_F64 ? 0 : 1, P, heat_waves(P))) continue;
         c->opt["heat.P"] = P;
         st = embed_heat3d(c, s, dtype, x_lo, x_hi, dt, trial_steps, r_lo, r_hi, ws, ws_bytes, hs);
@@ -542,7 +544,7 @@ reach_status reach_set_option(reach_ctx* c, const char* key, int64_t value) {
     if (!std::strcmp(key, "embed.S") && value != 0 && value != 1 && value != 2)
         return fail(c, REACH_E_INVAL, "embed.S must be 0, 1 or 2");
     if (!std::strcmp(key, "heat.P") && value && !heat_waves((int)value))
-        return fail(c, REACH_E_INVAL, "heat.P must be 0, 2, 3, 4 or 8");
+        return fail(c, REACH_E_INVAL, "heat.P must be 0, 2, 3, 4, 5 or 8");
     c->opt[key] = value;
     return REACH_OK;
 }
