@@ -60,6 +60,9 @@ def lib():
                                         vp, vp]
         L.or_embed_rk4_user.restype = ctypes.c_int
         L.or_f_rk4_user.argtypes = [vp, vp, i64, i64, vp, vp, d, i64, vp]
+        L.or_montecarlo_user.argtypes = [vp, vp, i64, i64, vp, vp, vp, vp, d, i64, i64, i64,
+                                         ctypes.c_uint64, ctypes.c_int, vp, vp, vp]
+        L.or_montecarlo_user.restype = ctypes.c_int
         L.or_f_rk4_user.restype = ctypes.c_int
         L.or_f_rk4.argtypes = [ctypes.c_int, vp, i64, i64, vp, vp, d, d, i64, vp]
         L.or_f_rk4.restype = ctypes.c_int
@@ -70,6 +73,8 @@ def lib():
                                       d, d, i64, vp, vp]
         L.or_growth_bound.restype = ctypes.c_int
         L.or_contraction_matrix.argtypes = [ctypes.c_int, vp, vp]
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_get_threads.restype = ctypes.c_int
         L.or_mc_samples.argtypes = [i64, d, d]
         L.or_mc_samples.restype = i64
         _lib = L
@@ -94,6 +99,15 @@ def _prm(prm):
 
 def _nin(p_lo):
     return 0 if p_lo is None else int(np.asarray(p_lo).size)
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads for the oracle's loops started from the calling thread."""
+    lib().or_set_threads(int(n))
+
+
+def get_threads() -> int:
+    return int(lib().or_get_threads())
 
 
 def philox(ctr, key):
@@ -212,6 +226,27 @@ def f_rk4_user(user: UserSystem, prm, x0, p=None, dt=0.01, nsteps=1):
     if rc != 0:
         raise RuntimeError(f"or_f_rk4_user failed ({rc})")
     return out
+
+
+def montecarlo_user(user: UserSystem, prm, x_lo, x_hi, p_lo=None, p_hi=None, dt=0.01,
+                    nsteps=1, m=1, seed=0, s0=0, ubits=53, return_samples=False):
+    """Algorithm 4 for a user system over samples s0 .. s0+m-1."""
+    x_lo, x_hi = _f64(x_lo), _f64(x_hi)
+    n = x_lo.size
+    n_in = _nin(p_lo)
+    pl, ph = _f64(p_lo), _f64(p_hi if p_hi is not None else p_lo)
+    r_min = np.empty(n, dtype=np.float64)
+    r_max = np.empty(n, dtype=np.float64)
+    samples = np.empty((m, n), dtype=np.float64) if return_samples else None
+    pr = _prm(prm)
+    rc = lib().or_montecarlo_user(user.fn, _p(pr), n, n_in, _p(x_lo), _p(x_hi), _p(pl), _p(ph),
+                                  dt, nsteps, s0, m, seed, ubits, _p(r_min), _p(r_max),
+                                  _p(samples))
+    if rc != 0:
+        raise RuntimeError(f"or_montecarlo_user failed ({rc})")
+    if return_samples:
+        return r_min, r_max, samples
+    return r_min, r_max
 
 
 def heat3d_prm(nx, ny, nz, alpha, dx):

@@ -77,6 +77,11 @@ enum { OR_CTM = 1, OR_RD = 2, OR_LIN3 = 3, OR_HEAT3D = 4, OR_USER = 5 };
 typedef double (*or_user_fn)(double xm, double x, double xp, double hm, double h, double hp,
                              double u, double uh, const double* prm, long long i, long long n);
 
+/* Threads of the OpenMP loops started from the calling thread (timing only). */
+#include <omp.h>
+void or_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+int or_get_threads(void) { return omp_get_max_threads(); }
+
 /* ------------------------------------------------------------------ RNG --
  * Philox4x64-10 (Salmon et al., SC'11), written from its published
  * definition: two 64x64->128 multiplications per round, 10 rounds, Weyl key
@@ -462,16 +467,14 @@ static double or_nmax(double a, double b)
     return b > a ? b : a;
 }
 
-int or_montecarlo(int kind, const double* prm, int64_t n, int64_t n_in,
-                  const double* x_lo, const double* x_hi, const double* p_lo,
-                  const double* p_hi, double t0, double dt, int64_t nsteps,
-                  int64_t s0, int64_t m, uint64_t seed, int ubits,
-                  double* r_min, double* r_max, double* samples)
+static int or_montecarlo_core(const or_sys* Sp, const double* x_lo, const double* x_hi,
+                              const double* p_lo, const double* p_hi, double dt,
+                              int64_t nsteps, int64_t s0, int64_t m, uint64_t seed, int ubits,
+                              double* r_min, double* r_max, double* samples)
 {
-    (void)t0;
+    const or_sys S = *Sp;
+    const int64_t n = S.len, n_in = S.n_in;
     if (n < 1 || m < 1 || nsteps < 0 || (n_in != 0 && n_in != 1 && n_in != n)) return -1;
-    or_sys S = {kind, prm, n, 0, n, n_in};
-    or_grid_default(&S);
     int64_t j;
     for (j = 0; j < n; ++j) { r_min[j] = INFINITY; r_max[j] = -INFINITY; }
     int failed = 0;
@@ -517,6 +520,32 @@ int or_montecarlo(int kind, const double* prm, int64_t n, int64_t n_in,
         free(z); free(mn); free(p);
     }
     return failed ? -2 : 0;
+}
+
+int or_montecarlo(int kind, const double* prm, int64_t n, int64_t n_in,
+                  const double* x_lo, const double* x_hi, const double* p_lo,
+                  const double* p_hi, double t0, double dt, int64_t nsteps,
+                  int64_t s0, int64_t m, uint64_t seed, int ubits,
+                  double* r_min, double* r_max, double* samples)
+{
+    (void)t0;
+    or_sys S = {kind, prm, n, 0, n, n_in};
+    or_grid_default(&S);
+    return or_montecarlo_core(&S, x_lo, x_hi, p_lo, p_hi, dt, nsteps, s0, m, seed, ubits,
+                              r_min, r_max, samples);
+}
+
+/* Algorithm 4 for a chain given by a caller-supplied decomposition function
+   (trajectories of f = d on the diagonal). */
+int or_montecarlo_user(or_user_fn d, const double* prm, int64_t n, int64_t n_in,
+                       const double* x_lo, const double* x_hi, const double* p_lo,
+                       const double* p_hi, double dt, int64_t nsteps, int64_t s0, int64_t m,
+                       uint64_t seed, int ubits, double* r_min, double* r_max, double* samples)
+{
+    if (!d) return -1;
+    or_sys S = {OR_USER, prm, n, 0, n, n_in, {0, 0, 0}, {0, 0, 0}, d};
+    return or_montecarlo_core(&S, x_lo, x_hi, p_lo, p_hi, dt, nsteps, s0, m, seed, ubits,
+                              r_min, r_max, samples);
 }
 
 /* ------------------------------------------------------- growth bound --

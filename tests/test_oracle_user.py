@@ -118,3 +118,30 @@ def test_user_sine_box_is_tighter_than_trivially_wide(users):
     # cells below 10 never see the widened cell (coupling runs i-1 -> i only)
     assert np.array_equal(r_lo[:10], r_hi[:10])
     assert np.all(r_hi[10:] - r_lo[10:] > 0)
+
+
+@pytest.mark.parametrize("name,kind", [("CTM", oracle.CTM), ("RD", oracle.RD)])
+def test_user_montecarlo_equals_builtin_bitwise(users, name, kind):
+    p = workloads.small_problem(kind, 40, 39, 25)
+    lo, hi = p.box()
+    pl, ph = p.inputs()
+    u = oracle.montecarlo_user(users[name], p.prm, lo, hi, pl, ph, dt=p.dt, nsteps=p.nsteps,
+                               m=50, seed=9)
+    b = oracle.montecarlo(kind, p.prm, lo, hi, pl, ph, dt=p.dt, nsteps=p.nsteps, m=50, seed=9)
+    assert np.array_equal(u[0], b[0]) and np.array_equal(u[1], b[1])
+
+
+def test_user_sine_montecarlo_samples_are_trajectories_inside_the_box(users):
+    n, dt, N = 24, 0.05, 40
+    lo, hi, pl, ph = _sine_case(n, 40)
+    mn, mx, smp = oracle.montecarlo_user(users["SINE"], us.SINE_PRM, lo, hi, pl, ph, dt=dt,
+                                         nsteps=N, m=64, seed=3, return_samples=True)
+    assert np.array_equal(mn, smp.min(axis=0)) and np.array_equal(mx, smp.max(axis=0))
+    e_lo, e_hi = oracle.embed_rk4_user(users["SINE"], us.SINE_PRM, lo, hi, pl, ph, dt=dt,
+                                       nsteps=N)
+    assert np.all(mn >= e_lo - 1e-12) and np.all(mx <= e_hi + 1e-12)
+    for s in (0, 17, 63):     # each sample is the trajectory from its drawn point
+        x0 = np.array([lo[j] + oracle.uniform(3, s, j) * (hi[j] - lo[j]) for j in range(n)])
+        u = pl + oracle.uniform(3, s, n) * (ph - pl)
+        t = oracle.f_rk4_user(users["SINE"], us.SINE_PRM, x0, u, dt=dt, nsteps=N)
+        assert np.array_equal(t, smp[s])
