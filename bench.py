@@ -82,21 +82,91 @@ def traffic_from_profile(name="embed_tile_kernel_rd2p26_f64_pmc.txt", files=EMBE
         return None
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(p, steps: int):
+    """The oracle on the host: all threads on the full chain for `steps` of
+    the workload's steps, and one thread on its first 2^20 cells."""
     import oracle
     lo, hi = p.box()
     pl, ph = p.inputs()
+    threads = oracle.get_threads()
     t = time.perf_counter()
     oracle.embed_rk4(p.kind, p.prm, lo, hi, pl, ph, dt=p.dt, nsteps=steps)
     el = time.perf_counter() - t
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": 2.0 * p.n * steps / el, "unit": "state-steps/s", "cores": cores,
-            "kind": "oracle", "seconds": round(el, 2),
+    n1, s1 = min(p.n, 1 << 20), 10
+    oracle.set_threads(1)
+    try:
+        t = time.perf_counter()
+        oracle.embed_rk4(p.kind, p.prm, lo[:n1], hi[:n1], pl, ph, dt=p.dt, nsteps=s1)
+        el1 = time.perf_counter() - t
+    finally:
+        oracle.set_threads(threads)
+    return {"value": 2.0 * p.n * steps / el, "unit": "state-steps/s", "cores": threads,
+            "kind": "oracle", "seconds": round(el, 2), "cpu_model": cpu_model(),
             "sample": f"FP64 oracle on the full {p.n}-cell chain for {steps} of the "
-                      f"{p.nsteps} RK4 steps (same box, inputs and dt)"}
+                      f"{p.nsteps} RK4 steps (same box, inputs and dt)",
+            "one_thread": {"value": 2.0 * n1 * s1 / el1, "unit": "state-steps/s",
+                           "sample": f"first {n1} cells, {s1} steps"}}
 
 
-def query_mix(rc, R, torch, workloads, nq):
+def latency_ctm64(rc, R, torch, workloads, reps=1000, cpu=True):
+    """The 64-cell CTM chain (FP64, 100 steps) and its 1000-sample Monte Carlo:
+    microseconds per call, HIP events around `reps` back-to-back calls."""
+    p = workloads.ctm64_f64()
+    lo, hi = p.box()
+    x_lo, x_hi = torch.from_numpy(lo).cuda(), torch.from_numpy(hi).cuda()
+    r_lo, r_hi = torch.empty_like(x_lo), torch.empty_like(x_hi)
+    sysd = R.make_system(p.kind, p.n, p.prm, 0)
+    run = lambda: R.reach_embed_rk4(rc.ctx, sysd, R.REACH_F64, x_lo, x_hi, None, None, 0.0,
+                                    p.dt, p.nsteps, r_lo, r_hi, None, 0, None)
+    for _ in range(10):
+        run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    emb_us = e0.elapsed_time(e1) * 1e3 / reps
+    rc.montecarlo(p.kind, p.prm, x_lo, x_hi, p.dt, p.nsteps, p.m, p.seed)
+    torch.cuda.synchronize()
+    mc_reps = max(10, reps // 10)
+    e0.record()
+    for _ in range(mc_reps):
+        rc.montecarlo(p.kind, p.prm, x_lo, x_hi, p.dt, p.nsteps, p.m, p.seed)
+    e1.record()
+    torch.cuda.synchronize()
+    assert rc.sync() == R.REACH_OK
+    mc_us = e0.elapsed_time(e1) * 1e3 / mc_reps
+    out = {"workload": "CTM chain n=64 FP64, dt=0.01, 100 RK4 steps; Monte Carlo m=1000",
+           "embed_us_per_call": round(emb_us, 2), "mc_us_per_call": round(mc_us, 2),
+           "reps": reps}
+    if cpu:
+        import oracle
+        threads = oracle.get_threads()
+        oracle.set_threads(1)
+        try:
+            k = 200
+            t = time.perf_counter()
+            for _ in range(k):
+                oracle.embed_rk4(p.kind, p.prm, lo, hi, dt=p.dt, nsteps=p.nsteps)
+            out["cpu_oracle_us_per_call_1_thread"] = round((time.perf_counter() - t) * 1e6 / k, 1)
+        finally:
+            oracle.set_threads(threads)
+    return out
+
+
+def query_mix(rc, R, torch, workloads, nq, cpu=True):
     """A Poisson stream of nq CTM / RD queries at 5e4/s, n log-uniform
     in [4, 512], 10-1000 RK4 steps, FP64.  Offline: one persistent-kernel batch
     vs one launch per query.  Online: served with the persistent kernel vs
@@ -200,10 +270,37 @@ def query_mix(rc, R, torch, workloads, nq):
                      "equals_batch": same}
         log(f"{name}: {out[name]}")
     rc.set_option("serve.mode", 0)
+    if cpu:
+        out["cpu_oracle"] = oracle_queries(qs, h_lo, h_hi, offs, u_lo, u_hi, min(nq, 2000))
+        log(f"oracle queries: {out['cpu_oracle']}")
     return out
 
 
-def extra_ctm_2p31_f32(rc, R, torch, workloads, steps=2):
+def oracle_queries(qs, h_lo, h_hi, offs, u_lo, u_hi, k):
+    """The oracle on the first k queries of the mix, one query per host thread
+    (each single-threaded); queries/s."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    workers = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def one(i):
+        pr = qs[i].problem
+        a, b = offs[i], offs[i + 1]
+        pl = np.array([u_lo[i]]) if pr.n_in else None
+        ph = np.array([u_hi[i]]) if pr.n_in else None
+        oracle.embed_rk4(pr.kind, pr.prm, h_lo[a:b], h_hi[a:b], pl, ph, dt=pr.dt,
+                         nsteps=pr.nsteps)
+
+    with ThreadPoolExecutor(workers, initializer=oracle.set_threads, initargs=(1,)) as ex:
+        list(ex.map(lambda i: None, range(workers)))      # start the workers
+        t = time.perf_counter()
+        list(ex.map(one, range(k)))
+        el = time.perf_counter() - t
+    return {"queries_per_s": k / el, "threads": workers, "sample": f"first {k} queries",
+            "kind": "oracle"}
+
+
+def extra_ctm_2p31_f32(rc, R, torch, workloads, steps=2, cpu_oracle=True):
     """CTM chain n = 2^31 FP32, 200 RK4 steps: the largest single-GPU embedding."""
     p = workloads.ctm_2p31_f32()
     lo = np.empty(p.n, dtype=np.float32)
@@ -242,6 +339,17 @@ def extra_ctm_2p31_f32(rc, R, torch, workloads, steps=2):
            "hbm_frac": round(byts / launch / HBM_PEAK, 4)}
     del x_lo, x_hi, r_lo, r_hi, ws
     torch.cuda.empty_cache()
+    if cpu_oracle:
+        import oracle
+        q = workloads.small_problem(workloads.KIND_CTM, 1 << 24, p.seed, 4)
+        qlo, qhi = q.box()
+        t = time.perf_counter()
+        oracle.embed_rk4(q.kind, q.prm, qlo, qhi, dt=q.dt, nsteps=q.nsteps)
+        csec = time.perf_counter() - t
+        out["cpu_oracle"] = {"state_steps_per_s": 2.0 * q.n * q.nsteps / csec,
+                             "sample": "FP64 oracle, CTM n = 2^24, 4 steps; extrapolated per "
+                                       "state-step to the 2^31 chain",
+                             "threads": oracle.get_threads()}
     return out
 
 
@@ -301,7 +409,7 @@ def extra_heat3d_1000(rc, R, torch, workloads, cpu_oracle=True, steps=0):
         csec = time.perf_counter() - t
         out["cpu_oracle"] = {"cell_steps_per_s": 2.0 * q.n * q.nsteps / csec,
                              "sample": "200^3 grid, 5 steps",
-                             "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))}
+                             "cores": oracle.get_threads()}
     return out
 
 
@@ -463,16 +571,19 @@ def main():
     alu_ach = flops_per_launch / launch_s
     hbm_frac, alu_frac = hbm_ach / HBM_PEAK, alu_ach / FP64_PEAK
     traffic = traffic_from_profile()
+    extra_roof = {"kernel": "embed_tile_kernel<RD,double>", "launch_us": round(launch_s * 1e6, 1),
+                  "algorithmic_GBps": round(hbm_ach / 1e9, 1),
+                  # rocprof DRAM bytes (read + write) per launch over this launch time
+                  "hbm_frac_measured": (round(traffic / launch_s / HBM_PEAK, 4)
+                                        if traffic else None)}
     if alu_frac >= hbm_frac:
         roof = {"bound": "alu", "achieved": round(alu_ach / 1e12, 3), "peak": FP64_PEAK / 1e12,
                 "unit": "TFLOP/s", "frac": round(alu_frac, 4), "traffic": traffic,
-                "kernel": "embed_tile_kernel<RD,double>", "launch_us": round(launch_s * 1e6, 1),
-                "hbm_frac_same_launch": round(hbm_frac, 4)}
+                "hbm_frac_same_launch": round(hbm_frac, 4), **extra_roof}
     else:
         roof = {"bound": "hbm", "achieved": round(hbm_ach / 1e9, 1), "peak": HBM_PEAK / 1e9,
                 "unit": "GB/s", "frac": round(hbm_frac, 4), "traffic": traffic,
-                "kernel": "embed_tile_kernel<RD,double>", "launch_us": round(launch_s * 1e6, 1),
-                "alu_frac_same_launch": round(alu_frac, 4)}
+                "alu_frac_same_launch": round(alu_frac, 4), **extra_roof}
 
     # K = 1 streaming pass: the same kernel as a pure HBM stream
     stream_k1 = None
@@ -502,10 +613,13 @@ def main():
 
     queries = None
     if not args.no_queries:
-        queries = query_mix(rc, R, torch, workloads, args.queries)
+        queries = query_mix(rc, R, torch, workloads, args.queries, cpu=not args.no_cpu)
     extra = {}
     if not args.no_extra:
-        extra["embed_ctm_2p31_f32"] = extra_ctm_2p31_f32(rc, R, torch, workloads)
+        extra["latency_ctm64_f64"] = latency_ctm64(rc, R, torch, workloads, cpu=not args.no_cpu)
+        log(f"ctm64 latency: {extra['latency_ctm64_f64']}")
+        extra["embed_ctm_2p31_f32"] = extra_ctm_2p31_f32(rc, R, torch, workloads,
+                                                         cpu_oracle=not args.no_cpu)
         log(f"ctm 2^31 f32: {extra['embed_ctm_2p31_f32']}")
         extra["mc_ctm4096_f32"] = extra_mc_ctm4096(rc, R, torch, workloads,
                                                    0 if args.no_cpu else args.cpu_mc_samples)

@@ -104,6 +104,9 @@ def lib() -> ctypes.CDLL:
         "reach_user_destroy": ([vp], None),
         "reach_embed_rk4_user": ([vp, vp, sysp, i32, vp, vp, vp, vp, d, d, i64, vp, vp, vp, sz,
                                   vp], i32),
+        "reach_user_workspace_bytes": ([vp, sysp, i32, i64], sz),
+        "reach_montecarlo_user": ([vp, vp, sysp, i32, vp, vp, vp, vp, d, d, i64, i64, i64, u64,
+                                   vp, vp, vp, sz, vp], i32),
     }
     for name, (args, res) in sigs.items():
         f = getattr(L, name)
@@ -129,6 +132,29 @@ def _stream(stream):
     if isinstance(stream, torch.cuda.Stream):
         return stream.cuda_stream
     return int(stream)
+
+
+def steps_between(t0: float, t1: float, dt: float) -> int:
+    """RK4 steps from t0 to t1 with step dt: round((t1 - t0) / dt), rejecting a
+    horizon that is not a whole number of steps (mismatch above 1e-9 |t1 - t0|)."""
+    span = float(t1) - float(t0)
+    if not (dt > 0) or span < 0:
+        raise ValueError("need dt > 0 and t1 >= t0")
+    n = int(round(span / dt))
+    if abs(n * dt - span) > 1e-9 * abs(span):
+        raise ValueError(f"[t0, t1] = [{t0}, {t1}] is not a whole number of steps of {dt}")
+    return n
+
+
+def _nsteps(nsteps, t0, t1, dt) -> int:
+    if t1 is None:
+        if nsteps is None:
+            raise ValueError("give nsteps or t1")
+        return int(nsteps)
+    n = steps_between(t0, t1, dt)
+    if nsteps is not None and int(nsteps) != n:
+        raise ValueError(f"nsteps = {nsteps} disagrees with t1 ({n} steps)")
+    return n
 
 
 def make_system(kind: int, n: int, prm, n_in: int = 0) -> reach_system:
@@ -306,6 +332,24 @@ def reach_embed_rk4_user(ctx, user, sys: reach_system, dtype: int, x_lo, x_hi, p
     return _chk(ctx, st, "reach_embed_rk4_user")
 
 
+def reach_user_workspace_bytes(ctx, sys: reach_system, dtype: int, m: int) -> int:
+    v = lib().reach_user_workspace_bytes(ctx, ctypes.byref(sys), int(dtype), int(m))
+    if v == ctypes.c_size_t(-1).value:
+        raise ReachError(REACH_E_INVAL, f"reach_user_workspace_bytes: {reach_last_error(ctx)}")
+    return int(v)
+
+
+def reach_montecarlo_user(ctx, user, sys: reach_system, dtype: int, x_lo, x_hi, p_lo, p_hi,
+                          t0: float, dt: float, nsteps: int, s0: int, m: int, seed: int, r_min,
+                          r_max, workspace=None, workspace_bytes: int = 0, stream=None) -> int:
+    st = lib().reach_montecarlo_user(ctx, user, ctypes.byref(sys), int(dtype), _ptr(x_lo),
+                                     _ptr(x_hi), _ptr(p_lo), _ptr(p_hi), float(t0), float(dt),
+                                     int(nsteps), int(s0), int(m), int(seed), _ptr(r_min),
+                                     _ptr(r_max), _ptr(workspace), int(workspace_bytes),
+                                     _stream(stream))
+    return _chk(ctx, st, "reach_montecarlo_user")
+
+
 def reach_mc_samples(n: int, eps: float, delta: float) -> int:
     return int(lib().reach_mc_samples(int(n), float(eps), float(delta)))
 
@@ -419,8 +463,9 @@ class Reach:
     def set_option(self, key, value):
         reach_set_option(self.ctx, key, value)
 
-    def embed(self, kind, prm, x_lo, x_hi, dt, nsteps, p_lo=None, p_hi=None, t0=0.0,
-              r_lo=None, r_hi=None, stream=None):
+    def embed(self, kind, prm, x_lo, x_hi, dt, nsteps=None, p_lo=None, p_hi=None, t0=0.0,
+              r_lo=None, r_hi=None, stream=None, t1=None):
+        nsteps = _nsteps(nsteps, t0, t1, dt)
         n = x_lo.numel()
         n_in = 0 if p_lo is None else p_lo.numel()
         dtc = dtype_code(x_lo.dtype)
@@ -441,7 +486,8 @@ class Reach:
         return r_lo, r_hi
 
     def montecarlo(self, kind, prm, x_lo, x_hi, dt, nsteps, m, seed, p_lo=None, p_hi=None,
-                   t0=0.0, s0=0, r_min=None, r_max=None, stream=None):
+                   t0=0.0, s0=0, r_min=None, r_max=None, stream=None, t1=None):
+        nsteps = _nsteps(nsteps, t0, t1, dt)
         n = x_lo.numel()
         n_in = 0 if p_lo is None else p_lo.numel()
         dtc = dtype_code(x_lo.dtype)
@@ -462,8 +508,9 @@ class Reach:
         """Compile a user decomposition function; returns its handle."""
         return reach_user_create(self.ctx, source)
 
-    def embed_user(self, user, prm, x_lo, x_hi, dt, nsteps, p_lo=None, p_hi=None, t0=0.0,
-                   r_lo=None, r_hi=None, stream=None):
+    def embed_user(self, user, prm, x_lo, x_hi, dt, nsteps=None, p_lo=None, p_hi=None, t0=0.0,
+                   r_lo=None, r_hi=None, stream=None, t1=None):
+        nsteps = _nsteps(nsteps, t0, t1, dt)
         n = x_lo.numel()
         n_in = 0 if p_lo is None else p_lo.numel()
         dtc = dtype_code(x_lo.dtype)
@@ -483,8 +530,28 @@ class Reach:
                              r_lo, r_hi, ws, nb, stream)
         return r_lo, r_hi
 
-    def growth_bound(self, kind, prm, x_lo, x_hi, dt, nsteps, p_lo=None, p_hi=None, t0=0.0,
-                     r_lo=None, r_hi=None, stream=None):
+    def montecarlo_user(self, user, prm, x_lo, x_hi, dt, nsteps, m, seed, p_lo=None, p_hi=None,
+                        t0=0.0, s0=0, r_min=None, r_max=None, stream=None, t1=None):
+        nsteps = _nsteps(nsteps, t0, t1, dt)
+        n = x_lo.numel()
+        n_in = 0 if p_lo is None else p_lo.numel()
+        dtc = dtype_code(x_lo.dtype)
+        _check_tensor(x_lo, "x_lo", x_lo.dtype, n, x_lo.device)
+        _check_tensor(x_hi, "x_hi", x_lo.dtype, n, x_lo.device)
+        if r_min is None:
+            r_min = torch.empty_like(x_lo)
+        if r_max is None:
+            r_max = torch.empty_like(x_lo)
+        sys = make_system(REACH_USER, n, prm, n_in)
+        nb = reach_user_workspace_bytes(self.ctx, sys, dtc, m)
+        ws = self.workspace(nb)
+        reach_montecarlo_user(self.ctx, user, sys, dtc, x_lo, x_hi, p_lo, p_hi, t0, dt, nsteps,
+                              s0, m, seed, r_min, r_max, ws, nb, stream)
+        return r_min, r_max
+
+    def growth_bound(self, kind, prm, x_lo, x_hi, dt, nsteps=None, p_lo=None, p_hi=None, t0=0.0,
+                     r_lo=None, r_hi=None, stream=None, t1=None):
+        nsteps = _nsteps(nsteps, t0, t1, dt)
         n = x_lo.numel()
         n_in = 0 if p_lo is None else p_lo.numel()
         dtc = dtype_code(x_lo.dtype)

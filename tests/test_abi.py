@@ -76,3 +76,18 @@ def test_null_context_is_rejected(R):
     assert L.reach_set_option(None, b"embed.K", 1) == R.REACH_E_INVAL
     assert L.reach_embed_rk4_batch(None, None, 0, None, 0, None) == R.REACH_E_INVAL
     assert L.reach_submit(None, None, None) == R.REACH_E_BUSY
+
+
+def test_step_count_from_horizon(R):
+    """nsteps = round((t1 - t0) / dt); a horizon that is not a whole number of
+    steps (beyond 1e-9 relative) is rejected."""
+    assert R.steps_between(0.0, 1.0, 0.01) == 100
+    assert R.steps_between(0.0, 20.0, 0.02) == 1000
+    assert R.steps_between(2.5, 2.5, 0.1) == 0
+    with pytest.raises(ValueError):
+        R.steps_between(0.0, 1.0, 0.3)
+    with pytest.raises(ValueError):
+        R.steps_between(1.0, 0.0, 0.1)
+    assert R._nsteps(None, 0.0, 1.0, 0.1) == 10
+    with pytest.raises(ValueError):
+        R._nsteps(9, 0.0, 1.0, 0.1)

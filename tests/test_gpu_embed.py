@@ -259,7 +259,7 @@ def test_rd_2p26_f64_light_cone_windows(rc):
     assert st == R.REACH_OK
     del lo, hi
     say("rd 2^26 oracle windows")
-    _window_check(g_lo, g_hi, p, _windows(p.n, 10, 512, 1), 1e-12, pl, ph)
+    _window_check(g_lo, g_hi, p, _windows(p.n, 64, 4096, 1), 1e-12, pl, ph)
 
 
 def test_ctm_2p31_f32_light_cone_windows(rc):
@@ -279,7 +279,7 @@ def test_ctm_2p31_f32_light_cone_windows(rc):
     r_lo, r_hi = rc.embed(p.kind, p.prm, x_lo, x_hi, p.dt, p.nsteps, r_lo=x_lo, r_hi=x_hi)
     assert rc.sync() == R.REACH_OK
     say("ctm 2^31 oracle windows")
-    wins = _windows(p.n, 8, 256, 2)
+    wins = _windows(p.n, 64, 4096, 2)
     # the last cells sit past 2^31 - 1: exercise 64-bit indexing explicitly
     wins.append((p.n - 4096, p.n - 3840))
     for a, b in wins:
@@ -335,3 +335,17 @@ def test_reach_tube_slots_equal_single_runs(rc, variant, n):
     o_lo, o_hi = run_oracle(kind, prm, lo, hi, pl, ph, dt, 2 * every)
     assert_rel(t_lo[1], o_lo, 1e-12, "slot 1 lower")
     assert_rel(t_hi[1], o_hi, 1e-12, "slot 1 upper")
+
+
+def test_horizon_t1_equals_step_count(rc):
+    """embed(..., t1=...) takes round((t1 - t0) / dt) steps."""
+    kind, prm, lo, hi, pl, ph, dt = make_case("rd", 3000, np.float64, seed=44)
+    say("horizon t1")
+    a = rc.embed(kind, prm, to_dev(lo), to_dev(hi), dt, 30, p_lo=to_dev(pl), p_hi=to_dev(ph))
+    b = rc.embed(kind, prm, to_dev(lo), to_dev(hi), dt, p_lo=to_dev(pl), p_hi=to_dev(ph),
+                 t0=1.0, t1=1.0 + 30 * dt)
+    assert rc.sync() == R.REACH_OK
+    assert np.array_equal(to_host(a[0]), to_host(b[0])) and np.array_equal(to_host(a[1]), to_host(b[1]))
+    with pytest.raises(ValueError):
+        rc.embed(kind, prm, to_dev(lo), to_dev(hi), dt, p_lo=to_dev(pl), p_hi=to_dev(ph),
+                 t0=0.0, t1=0.123 * dt + dt)
