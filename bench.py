@@ -276,6 +276,41 @@ def query_mix(rc, R, torch, workloads, nq, cpu=True):
     return out
 
 
+def batch_only(rc, R, torch, workloads, nq):
+    """One offline batch of the query mix (the batch kernel alone, profiling)."""
+    p4 = workloads.serve_mix_f64()
+    qs = workloads.query_stream(nq, p4.extra["rate"], seed=p4.seed)
+    ns = np.array([q.problem.n for q in qs])
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    h_lo = np.empty(int(offs[-1]))
+    h_hi = np.empty(int(offs[-1]))
+    u = np.zeros(2 * nq)
+    for i, q in enumerate(qs):
+        q.problem.box(out=(h_lo[offs[i]:offs[i + 1]], h_hi[offs[i]:offs[i + 1]]))
+        if q.problem.n_in:
+            u[2 * i], u[2 * i + 1] = q.problem.p_lo[0], q.problem.p_hi[0]
+    d_lo, d_hi, d_u = (torch.from_numpy(a).cuda() for a in (h_lo, h_hi, u))
+    r_lo, r_hi = torch.empty_like(d_lo), torch.empty_like(d_hi)
+    dq = R.query_array([R.make_query(q.problem.kind, q.problem.n, q.problem.prm, R.REACH_F64,
+                                     d_lo.data_ptr() + 8 * offs[i], d_hi.data_ptr() + 8 * offs[i],
+                                     r_lo.data_ptr() + 8 * offs[i], r_hi.data_ptr() + 8 * offs[i],
+                                     q.problem.dt, q.problem.nsteps,
+                                     d_u.data_ptr() + 16 * i if q.problem.n_in else None,
+                                     d_u.data_ptr() + 16 * i + 8 if q.problem.n_in else None,
+                                     n_in=q.problem.n_in) for i, q in enumerate(qs)])
+    nbw = R.reach_batch_workspace_bytes(nq)
+    wsb = torch.empty(nbw, dtype=torch.uint8, device="cuda")
+    R.reach_embed_rk4_batch(rc.ctx, dq, wsb, nbw, None)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    R.reach_embed_rk4_batch(rc.ctx, dq, wsb, nbw, None)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    assert rc.sync() == R.REACH_OK
+    return {"workload": f"{nq} queries of the mix, one batch", "seconds": round(tb, 4),
+            "queries_per_s": nq / tb}
+
+
 def oracle_queries(qs, h_lo, h_hi, offs, u_lo, u_hi, k):
     """The oracle on the first k queries of the mix, one query per host thread
     (each single-threaded); queries/s."""
@@ -413,6 +448,108 @@ def extra_heat3d_1000(rc, R, torch, workloads, cpu_oracle=True, steps=0):
     return out
 
 
+LIN3_OPS_PER_STATE_STEP = 41    # growth-bound half-width: 4 right-hand sides of 7 + 13
+
+
+def next_rows_rd(rc, R, torch, p, x_lo, x_hi, p_lo, p_hi, ref_s, stream):
+    """The growth bound and the reach tube on the benchmark's own RD 2^26
+    workload (inputs resident), against the plain embedding's time ref_s."""
+    out = {}
+    sysd = R.make_system(p.kind, p.n, p.prm, p.n_in)
+    nb = R.reach_growth_bound_workspace_bytes(rc.ctx, sysd, R.REACH_F64)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    g_lo, g_hi = torch.empty_like(x_lo), torch.empty_like(x_hi)
+    run = lambda: R.reach_growth_bound(rc.ctx, sysd, R.REACH_F64, x_lo, x_hi, p_lo, p_hi, 0.0,
+                                       p.dt, p.nsteps, g_lo, g_hi, ws, nb, stream)
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(2):
+        run()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    assert rc.sync(stream) == R.REACH_OK
+    sec = e0.elapsed_time(e1) / 1e3 / 2
+    ss = 2.0 * p.n * p.nsteps
+    ops = p.n * p.nsteps * (RD_FLOPS_PER_STATE_STEP + LIN3_OPS_PER_STATE_STEP)
+    out["growth_bound_rd2p26_f64"] = {
+        "workload": "growth bound (Algorithm 2), RD chain n=2^26 FP64, 1000 RK4 steps "
+                    "(center and half-width runs)",
+        "state_steps_per_s": ss / sec, "seconds": round(sec, 4),
+        "vs_embedding_time": round(sec / ref_s, 3),
+        "roofline": {"bound": "alu", "achieved": round(ops / sec / 1e12, 3),
+                     "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": round(ops / sec / FP64_PEAK, 4)}}
+    del ws, g_lo, g_hi
+    every = 100
+    slots = p.nsteps // every
+    t_lo = torch.empty(slots * p.n, dtype=torch.float64, device="cuda")
+    t_hi = torch.empty_like(t_lo)
+    nbe = R.reach_workspace_bytes(rc.ctx, sysd, R.REACH_F64, 0)
+    wse = torch.empty(max(nbe, 1), dtype=torch.uint8, device="cuda")
+    tube = lambda: R.reach_embed_rk4_tube(rc.ctx, sysd, R.REACH_F64, x_lo, x_hi, p_lo, p_hi, 0.0,
+                                          p.dt, p.nsteps, every, t_lo, t_hi, wse, nbe, stream)
+    tube()
+    torch.cuda.synchronize()
+    e0.record(stream)
+    tube()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    assert rc.sync(stream) == R.REACH_OK
+    sec = e0.elapsed_time(e1) / 1e3
+    out["tube_rd2p26_f64"] = {
+        "workload": "reach tube, RD chain n=2^26 FP64, 1000 RK4 steps, a box every 100 steps "
+                    "(10 boxes, 10 GiB)",
+        "state_steps_per_s": ss / sec, "seconds": round(sec, 4),
+        "vs_embedding_time": round(sec / ref_s, 3)}
+    del t_lo, t_hi, wse
+    torch.cuda.empty_cache()
+    return out
+
+
+def extra_user_sine(rc, R, torch):
+    """A user system compiled at run time: the nonlinear sine chain
+    (f_i = -a x_i + b sin(x_{i-1}) + c u with its tight decomposition), n = 2^22
+    FP64, 200 RK4 steps, and its Monte Carlo at n = 512, 2^16 samples."""
+    from tests import user_sources as us     # the same text the tests use
+    t = time.perf_counter()
+    user = rc.user(us.SINE)
+    compile_s = time.perf_counter() - t
+    n, N = 1 << 22, 200
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    x_lo = torch.rand(n, dtype=torch.float64, device="cuda", generator=g) * 6.0 - 3.0
+    x_hi = x_lo + 0.5
+    pl = torch.tensor([-0.2], dtype=torch.float64, device="cuda")
+    ph = torch.tensor([0.3], dtype=torch.float64, device="cuda")
+    rc.embed_user(user, us.SINE_PRM, x_lo, x_hi, 0.05, 4, p_lo=pl, p_hi=ph)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    rc.embed_user(user, us.SINE_PRM, x_lo, x_hi, 0.05, N, p_lo=pl, p_hi=ph)
+    e1.record()
+    torch.cuda.synchronize()
+    assert rc.sync() == R.REACH_OK
+    sec = e0.elapsed_time(e1) / 1e3
+    m = 1 << 16
+    ml, mh = x_lo[:512].contiguous(), x_hi[:512].contiguous()
+    rc.montecarlo_user(user, us.SINE_PRM, ml, mh, 0.05, N, 1024, 3, p_lo=pl, p_hi=ph)
+    torch.cuda.synchronize()
+    e0.record()
+    rc.montecarlo_user(user, us.SINE_PRM, ml, mh, 0.05, N, m, 3, p_lo=pl, p_hi=ph)
+    e1.record()
+    torch.cuda.synchronize()
+    assert rc.sync() == R.REACH_OK
+    msec = e0.elapsed_time(e1) / 1e3
+    R.reach_user_destroy(user)
+    return {"workload": "user sine chain (hipRTC) n=2^22 FP64, dt=0.05, 200 RK4 steps; Monte "
+                        "Carlo n=512, 2^16 samples",
+            "compile_seconds": round(compile_s, 2),
+            "embed_state_steps_per_s": 2.0 * n * N / sec, "embed_seconds": round(sec, 4),
+            "mc_cell_steps_per_s": 512.0 * m * N / msec, "mc_seconds": round(msec, 4)}
+
+
 def extra_mc_ctm4096(rc, R, torch, workloads, cpu_samples):
     """Monte Carlo, CTM n = 4096 FP32, 2^20 samples, 500 RK4 steps."""
     import oracle
@@ -469,6 +606,9 @@ def main():
     ap.add_argument("--heat-only", type=int, default=0, metavar="STEPS",
                     help="only run the 1000^3 heat grid for STEPS RK4 steps (profiling)")
     ap.add_argument("--heat-P", type=int, default=0, help="rows per wave of the heat kernel")
+    ap.add_argument("--only", choices=("mc", "ctm31", "batch"), default=None,
+                    help="only run one extra row (profiling): the Monte Carlo run, the 2^31 "
+                         "FP32 chain (one call) or one batch of the query mix")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of one embedding pass's bytes "
                          "(the reference kernel for HBM counter calibration)")
@@ -482,6 +622,18 @@ def main():
     import torch
     import workloads
     import paper_2001_10635_amd as R
+
+    if args.only:
+        rc = R.Reach(0)
+        if args.only == "mc":
+            out = extra_mc_ctm4096(rc, R, torch, workloads, 0)
+        elif args.only == "ctm31":
+            out = extra_ctm_2p31_f32(rc, R, torch, workloads, steps=1, cpu_oracle=False)
+        else:
+            out = batch_only(rc, R, torch, workloads, args.queries)
+        print(json.dumps(out), flush=True)
+        rc.close()
+        return
 
     if args.heat_only:
         rc = R.Reach(0)
@@ -607,6 +759,11 @@ def main():
         rc.set_option("embed.K", args.K)
         assert rc.sync(stream) == R.REACH_OK
         log(f"K=1 stream: {stream_k1}")
+    next_rows = {}
+    if not args.no_extra:
+        next_rows = next_rows_rd(rc, R, torch, p, x_lo, x_hi, p_lo, p_hi, ms_per_step / 1e3,
+                                 stream)
+        log(f"growth bound / tube: {next_rows}")
     del x_lo, x_hi, p_lo, p_hi, r_lo, r_hi
     rc._ws = None
     torch.cuda.empty_cache()
@@ -624,6 +781,9 @@ def main():
         extra["mc_ctm4096_f32"] = extra_mc_ctm4096(rc, R, torch, workloads,
                                                    0 if args.no_cpu else args.cpu_mc_samples)
         log(f"mc: {extra['mc_ctm4096_f32']}")
+        extra.update(next_rows)
+        extra["user_sine_f64"] = extra_user_sine(rc, R, torch)
+        log(f"user sine: {extra['user_sine_f64']}")
         extra["embed_heat3d_1000_f64"] = extra_heat3d_1000(rc, R, torch, workloads,
                                                            not args.no_cpu)
         log(f"heat 1000^3: {extra['embed_heat3d_1000_f64']}")

@@ -394,6 +394,22 @@ reach_status reach_embed_rk4_user(reach_ctx* ctx, const reach_user* user,
                                   void* r_lo, void* r_hi, void* workspace,
                                   size_t workspace_bytes, void* stream);
 
+/* reach_montecarlo_user: Algorithm 4 for the user system (samples s0 ..
+ * s0+m-1 integrated with f(x, p) = d(x, p, x, p)); arguments, sampling and
+ * results as reach_montecarlo_range.  n <= 512 (a sample lives in one
+ * wavefront), else REACH_E_UNSUPPORTED.
+ * reach_user_workspace_bytes: workspace of reach_embed_rk4_user (m = 0) or
+ * reach_montecarlo_user with m samples; (size_t)-1 on bad arguments. */
+size_t reach_user_workspace_bytes(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
+                                  int64_t m);
+reach_status reach_montecarlo_user(reach_ctx* ctx, const reach_user* user,
+                                   const reach_system* sys, reach_dtype dtype,
+                                   const void* x_lo, const void* x_hi, const void* p_lo,
+                                   const void* p_hi, double t0, double dt, int64_t nsteps,
+                                   int64_t s0, int64_t m, uint64_t seed, void* r_min,
+                                   void* r_max, void* workspace, size_t workspace_bytes,
+                                   void* stream);
+
 #ifdef __cplusplus
 }
 #endif

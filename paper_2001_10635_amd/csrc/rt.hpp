@@ -13,6 +13,7 @@ namespace reach {
 namespace rt {
 
 int ctx_device(const reach_ctx* c);
+int ctx_cus(const reach_ctx* c);
 unsigned int* ctx_status(reach_ctx* c);
 int64_t option(const reach_ctx* c, const char* key);
 // Records `msg` as the context's last error and returns `st`.

@@ -1092,6 +1092,7 @@ namespace reach {
 namespace rt {
 
 int ctx_device(const reach_ctx* c) { return c->device; }
+int ctx_cus(const reach_ctx* c) { return c->cus; }
 unsigned int* ctx_status(reach_ctx* c) { return c->status; }
 int64_t option(const reach_ctx* c, const char* key) { return opt_get(c, key); }
 reach_status set_error(reach_ctx* c, reach_status st, const std::string& msg) {

@@ -23,6 +23,7 @@
 #include <vector>
 
 #include "../../include/reach.h"
+#include "kernels.hpp"
 #include "rt.hpp"
 
 using namespace reach;
@@ -41,6 +42,15 @@ namespace {
 #define REACH_STR(...) REACH_STR2(__VA_ARGS__)
 
 struct UserPass { REACH_USER_PASS_FIELDS };
+
+#define REACH_USER_MC_FIELDS                                                          \
+    const void* x_lo; const void* x_hi; const void* p_lo; const void* p_hi;          \
+    void* part_min; void* part_max;                                                  \
+    long long n; long long nsteps; long long s0; long long m; long long nw;           \
+    unsigned long long seed; int in_mode; int pad;                                   \
+    double prm[8]; double h2; double dt; double dt6;
+
+struct UserMcPass { REACH_USER_MC_FIELDS };
 
 // tile widths (cells per lane); wider tiles of arbitrary user code spill
 constexpr int kUserE[] = {1, 2, 4, 8};
@@ -166,11 +176,136 @@ __global__ __launch_bounds__(64) void user_tile(UserPass a) {
     }
 }
 
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 64x64 -> 128-bit products with the published multipliers, Weyl key steps.
+struct Philox4 { unsigned long long x[4]; };
+__device__ inline Philox4 philox(unsigned long long c0, unsigned long long c1,
+                                 unsigned long long c2, unsigned long long c3,
+                                 unsigned long long k0, unsigned long long k1) {
+    for (int r = 0; r < 10; ++r) {
+        const unsigned long long lo0 = 0xD2E7470EE14C6C93ULL * c0;
+        const unsigned long long hi0 = __umul64hi(0xD2E7470EE14C6C93ULL, c0);
+        const unsigned long long lo1 = 0xCA5A826395121157ULL * c2;
+        const unsigned long long hi1 = __umul64hi(0xCA5A826395121157ULL, c2);
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B97F4A7C15ULL;
+        k1 += 0xBB67AE8584CAA73BULL;
+    }
+    Philox4 r;
+    r.x[0] = c0; r.x[1] = c1; r.x[2] = c2; r.x[3] = c3;
+    return r;
+}
+__device__ inline unsigned long long pick(const Philox4& r, long long q) {
+    return q == 0 ? r.x[0] : q == 1 ? r.x[1] : q == 2 ? r.x[2] : r.x[3];
+}
+// Uniform on [0, 1): top 53 bits (FP64 runs) or top 24 bits (FP32 runs).
+__device__ inline double unif(unsigned long long r, double) { return (double)(r >> 11) * 0x1.0p-53; }
+__device__ inline float unif(unsigned long long r, float) { return (float)(r >> 40) * 0x1.0p-24f; }
+
+template <class T> __device__ inline T nan_min(T m, T x) {
+    return (m != m) ? m : ((x < m || x != x) ? x : m);
+}
+template <class T> __device__ inline T nan_max(T m, T x) {
+    return (m != m) ? m : ((x > m || x != x) ? x : m);
+}
+
+// Algorithm 4 on the user system: persistent waves, a whole sample per wave
+// (cells lane * E + e, n <= 64 E), f = d on the diagonal, each final state
+// folded into the wave's min / max partials [w][e][lane].  Sample s draws
+// U(s, j) = word j mod 4 of Philox at key (seed, 0), counter
+// (floor(j / 4), s, 2, 0): cells at j < n, inputs at j = n + k.
+template <int D, int E>
+__global__ __launch_bounds__(64) void user_mc(UserMcPass a) {
+    typedef typename Real<D>::T T;
+    const int lane = threadIdx.x;
+    const long long w = blockIdx.x;
+    const long long n = a.n;
+    const T* xlo = (const T*)a.x_lo;
+    const T* xhi = (const T*)a.x_hi;
+    const T* plo = (const T*)a.p_lo;
+    const T* phi = (const T*)a.p_hi;
+    T* pmin = (T*)a.part_min + (size_t)w * E * 64;
+    T* pmax = (T*)a.part_max + (size_t)w * E * 64;
+    T prm[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) prm[j] = (T)a.prm[j];
+    const T h2 = (T)a.h2, dt = (T)a.dt, dt6 = (T)a.dt6;
+    bool ok[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) ok[e] = (long long)lane * E + e < n;
+    bool first = true;
+    for (long long s = a.s0 + w; s < a.s0 + a.m; s += a.nw) {
+        T y[E], u[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const long long j = (long long)lane * E + e;
+            const Philox4 r = philox((unsigned long long)(j >> 2), (unsigned long long)s, 2ULL, 0ULL,
+                                     a.seed, 0ULL);
+            const T uu = unif(pick(r, j & 3), T(0));
+            y[e] = ok[e] ? __builtin_fma(uu, xhi[j] - xlo[j], xlo[j]) : T(0);
+        }
+        if (a.in_mode == 1) {
+            const long long j = n;
+            const Philox4 r = philox((unsigned long long)(j >> 2), (unsigned long long)s, 2ULL, 0ULL,
+                                     a.seed, 0ULL);
+            const T uu = unif(pick(r, j & 3), T(0));
+            const T v = __builtin_fma(uu, phi[0] - plo[0], plo[0]);
+#pragma unroll
+            for (int e = 0; e < E; ++e) u[e] = v;
+        } else if (a.in_mode == 2) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const long long c = (long long)lane * E + e;
+                const long long j = n + c;
+                const Philox4 r = philox((unsigned long long)(j >> 2), (unsigned long long)s, 2ULL,
+                                         0ULL, a.seed, 0ULL);
+                const T uu = unif(pick(r, j & 3), T(0));
+                u[e] = ok[e] ? __builtin_fma(uu, phi[c] - plo[c], plo[c]) : T(0);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < E; ++e) u[e] = T(0);
+        }
+        for (long long k = 0; k < a.nsteps; ++k) {
+            T acc[E], t[E];
+#pragma unroll
+            for (int stage = 1; stage <= 4; ++stage) {
+                T in[E];
+#pragma unroll
+                for (int e = 0; e < E; ++e) in[e] = (stage == 1) ? y[e] : t[e];
+                const T ln = from_left(in[E - 1]), rn = from_right(in[0]);
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const long long i = (long long)lane * E + e;
+                    const T xm = e == 0 ? ln : in[e - 1], xp = e == E - 1 ? rn : in[e + 1];
+                    const T kv = call_d<D>(xm, in[e], xp, xm, in[e], xp, u[e], u[e], prm, i, n);
+                    if (stage == 1) { acc[e] = kv; t[e] = __builtin_fma(h2, kv, y[e]); }
+                    else if (stage == 2) { acc[e] = __builtin_fma(T(2), kv, acc[e]); t[e] = __builtin_fma(h2, kv, y[e]); }
+                    else if (stage == 3) { acc[e] = __builtin_fma(T(2), kv, acc[e]); t[e] = __builtin_fma(dt, kv, y[e]); }
+                    else { acc[e] = acc[e] + kv; y[e] = __builtin_fma(dt6, acc[e], y[e]); }
+                    if (!ok[e]) { t[e] = T(0); y[e] = T(0); }
+                }
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const size_t idx = (size_t)e * 64 + lane;
+            pmin[idx] = first ? y[e] : nan_min(pmin[idx], y[e]);
+            pmax[idx] = first ? y[e] : nan_max(pmax[idx], y[e]);
+        }
+        first = false;
+    }
+}
+
 }  // namespace reach_rtc
 )";
 
-std::string name_expr(int dtype, int E) {
-    return "reach_rtc::user_tile<" + std::to_string(dtype) + ", " + std::to_string(E) + ">";
+std::string name_expr(int dtype, int E, bool mc = false) {
+    return std::string(mc ? "reach_rtc::user_mc<" : "reach_rtc::user_tile<") +
+           std::to_string(dtype) + ", " + std::to_string(E) + ">";
 }
 
 }  // namespace
@@ -178,7 +313,8 @@ std::string name_expr(int dtype, int E) {
 struct reach_user {
     int device = 0;
     hipModule_t mod = nullptr;
-    hipFunction_t fn[2][kNumE] = {};
+    hipFunction_t fn[2][kNumE] = {};   // embedding tiles
+    hipFunction_t mc[2][kNumE] = {};   // Monte Carlo samples
 };
 
 extern "C" {
@@ -188,6 +324,7 @@ reach_status reach_user_create(reach_ctx* c, const char* source, reach_user** ou
     *out = nullptr;
     std::string text = kPrelude;
     text += "struct UserPass { " REACH_STR(REACH_USER_PASS_FIELDS) " };\n";
+    text += "struct UserMcPass { " REACH_STR(REACH_USER_MC_FIELDS) " };\n";
     text += "namespace reach_user_f64 {\ntypedef double real;\n";
     text += source;
     text += "\n}\nnamespace reach_user_f32 {\ntypedef float real;\n";
@@ -199,11 +336,10 @@ reach_status reach_user_create(reach_ctx* c, const char* source, reach_user** ou
         HIPRTC_SUCCESS)
         return rt::set_error(c, REACH_E_NOMEM, "hiprtcCreateProgram failed");
     std::vector<std::string> names;
-    for (int d = 0; d < 2; ++d)
-        for (int e : kUserE) {
-            names.push_back(name_expr(d, e));
-            hiprtcAddNameExpression(prog, names.back().c_str());
-        }
+    for (int mc = 0; mc < 2; ++mc)
+        for (int d = 0; d < 2; ++d)
+            for (int e : kUserE) names.push_back(name_expr(d, e, mc == 1));
+    for (const auto& nm : names) hiprtcAddNameExpression(prog, nm.c_str());
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, rt::ctx_device(c)) != hipSuccess) {
         hiprtcDestroyProgram(&prog);
@@ -241,12 +377,16 @@ reach_status reach_user_create(reach_ctx* c, const char* source, reach_user** ou
         delete u;
         return rt::set_error(c, REACH_E_DEVICE, "loading the compiled user module failed");
     }
-    for (int d = 0, k = 0; d < 2; ++d)
-        for (int e = 0; e < kNumE; ++e, ++k)
-            if (hipModuleGetFunction(&u->fn[d][e], u->mod, lowered[k].c_str()) != hipSuccess) {
-                hipModuleUnload(u->mod);
-                delete u;
-                return rt::set_error(c, REACH_E_DEVICE, "user kernel " + names[k] + " not found");
+    for (int mc = 0, k = 0; mc < 2; ++mc)
+        for (int d = 0; d < 2; ++d)
+            for (int e = 0; e < kNumE; ++e, ++k) {
+                hipFunction_t* f = mc ? &u->mc[d][e] : &u->fn[d][e];
+                if (hipModuleGetFunction(f, u->mod, lowered[k].c_str()) != hipSuccess) {
+                    hipModuleUnload(u->mod);
+                    delete u;
+                    return rt::set_error(c, REACH_E_DEVICE,
+                                         "user kernel " + names[k] + " not found");
+                }
             }
     *out = u;
     return REACH_OK;
@@ -360,6 +500,79 @@ reach_status reach_embed_rk4_user(reach_ctx* c, const reach_user* u, const reach
             hipMemcpyAsync(r_hi, w_hi, bytes, hipMemcpyDeviceToDevice, hs) != hipSuccess)
             return rt::set_error(c, REACH_E_DEVICE, "copy failed");
     }
+    return REACH_OK;
+}
+
+// Monte Carlo plan: tile width holding the whole chain, resident waves.
+static int user_mc_E(int64_t n) {
+    for (int j = 0; j < kNumE; ++j)
+        if ((int64_t)64 * kUserE[j] >= n) return j;
+    return -1;
+}
+
+static int64_t user_mc_waves(const reach_ctx* c, int64_t m) {
+    int64_t w = rt::option(c, "mc.waves");
+    if (w <= 0) w = (int64_t)rt::ctx_cus(c) * 8;
+    return std::max<int64_t>(1, std::min<int64_t>(w, m));
+}
+
+size_t reach_user_workspace_bytes(reach_ctx* c, const reach_system* s, reach_dtype dtype,
+                                  int64_t m) {
+    if (!c || rt::validate_user(c, s, dtype) != REACH_OK || m < 0) return (size_t)-1;
+    const size_t el = dtype == REACH_F64 ? 8 : 4;
+    if (m == 0) return 2 * (size_t)s->n * el;
+    const int ei = user_mc_E(s->n);
+    if (ei < 0) return (size_t)-1;
+    return 2 * (size_t)user_mc_waves(c, m) * 64 * (size_t)kUserE[ei] * el;
+}
+
+reach_status reach_montecarlo_user(reach_ctx* c, const reach_user* u, const reach_system* s,
+                                   reach_dtype dtype, const void* x_lo, const void* x_hi,
+                                   const void* p_lo, const void* p_hi, double t0, double dt,
+                                   int64_t nsteps, int64_t s0, int64_t m, uint64_t seed,
+                                   void* r_min, void* r_max, void* ws, size_t ws_bytes,
+                                   void* stream) {
+    if (!c) return REACH_E_INVAL;
+    if (!u) return rt::set_error(c, REACH_E_INVAL, "user system is NULL");
+    reach_status st = rt::validate_user(c, s, dtype);
+    if (st != REACH_OK) return st;
+    if (u->device != rt::ctx_device(c))
+        return rt::set_error(c, REACH_E_INVAL, "user system compiled for another device");
+    if (!x_lo || !x_hi || !r_min || !r_max) return rt::set_error(c, REACH_E_INVAL, "NULL pointer");
+    if (s->n_in > 0 && (!p_lo || !p_hi)) return rt::set_error(c, REACH_E_INVAL, "NULL input pointer");
+    if (!(std::isfinite(dt) && dt > 0.0)) return rt::set_error(c, REACH_E_INVAL, "dt must be finite and > 0");
+    if (!std::isfinite(t0)) return rt::set_error(c, REACH_E_INVAL, "t0 must be finite");
+    if (nsteps < 0) return rt::set_error(c, REACH_E_INVAL, "nsteps < 0");
+    if (m < 1) return rt::set_error(c, REACH_E_INVAL, "m must be >= 1");
+    if (s0 < 0) return rt::set_error(c, REACH_E_INVAL, "s0 must be >= 0");
+    const int ei = user_mc_E(s->n);
+    if (ei < 0)
+        return rt::set_error(c, REACH_E_UNSUPPORTED, "Monte Carlo holds a sample in one wave: n <= 512");
+    const size_t need = reach_user_workspace_bytes(c, s, dtype, m);
+    if (!ws || ws_bytes < need)
+        return rt::set_error(c, REACH_E_INVAL, "workspace of " + std::to_string(need) + " bytes needed");
+    if (hipSetDevice(u->device) != hipSuccess) return rt::set_error(c, REACH_E_DEVICE, "hipSetDevice failed");
+    hipStream_t hs = (hipStream_t)stream;
+    UserMcPass a{};
+    a.x_lo = x_lo; a.x_hi = x_hi;
+    a.p_lo = s->n_in ? p_lo : nullptr;
+    a.p_hi = s->n_in ? p_hi : nullptr;
+    a.part_min = ws;
+    a.part_max = (char*)ws + need / 2;
+    a.n = s->n; a.nsteps = nsteps; a.s0 = s0; a.m = m;
+    a.nw = user_mc_waves(c, m);
+    a.seed = seed;
+    a.in_mode = s->n_in == 0 ? 0 : (s->n_in == 1 ? 1 : 2);
+    for (int j = 0; j < 8; ++j) a.prm[j] = s->prm[j];
+    a.h2 = dt / 2.0; a.dt = dt; a.dt6 = dt / 6.0;
+    const int d = dtype == REACH_F64 ? 0 : 1;
+    void* args[] = {&a};
+    if (hipModuleLaunchKernel(u->mc[d][ei], (unsigned)a.nw, 1, 1, 64, 1, 1, 0, hs, args,
+                              nullptr) != hipSuccess)
+        return rt::set_error(c, REACH_E_DEVICE, "user Monte Carlo launch failed");
+    if (launch_mc_reduce(d, kUserE[ei], a.part_min, a.part_max, a.nw, s->n, r_min, r_max,
+                         rt::ctx_status(c), hs) != hipSuccess)
+        return rt::set_error(c, REACH_E_DEVICE, "Monte Carlo reduction launch failed");
     return REACH_OK;
 }
 

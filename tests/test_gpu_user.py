@@ -182,3 +182,69 @@ def test_user_errors(rc, users):
     with pytest.raises(R.ReachError):
         rc.set_option("user.E", 16)
         rc.embed_user(g, us.SINE_PRM, to_dev(np.zeros(4000)), to_dev(np.zeros(4000)), 0.05, 3)
+
+
+# ------------------------------------------------------------ Monte Carlo
+
+def oracle_user_mc(o, prm, lo, hi, pl, ph, dt, nsteps, m, seed, s0=0, ubits=53):
+    f = lambda a: None if a is None else np.asarray(a, dtype=np.float64)
+    return oracle.montecarlo_user(o, prm, f(lo), f(hi), f(pl), f(ph), dt=dt, nsteps=nsteps, m=m,
+                                  seed=seed, s0=s0, ubits=ubits)
+
+
+def run_user_mc(rc, g, prm, lo, hi, pl, ph, dt, nsteps, m, seed, s0=0):
+    dev = lambda a: None if a is None else to_dev(a)
+    mn, mx = rc.montecarlo_user(g, prm, dev(lo), dev(hi), dt, nsteps, m, seed, p_lo=dev(pl),
+                                p_hi=dev(ph), s0=s0)
+    return to_host(mn), to_host(mx), rc.sync()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("n", [1, 5, 64, 200, 512])
+@pytest.mark.parametrize("inputs", ["none", "scalar", "cell"])
+def test_user_mc_matches_oracle(rc, users, n, dtype, inputs):
+    g, o = users["SINE"]
+    lo, hi, pl, ph = sine_case(n, dtype, seed=n + 90, inputs=inputs)
+    say(f"user mc sine n={n} {np.dtype(dtype).name} inputs={inputs}")
+    g_mn, g_mx, st = run_user_mc(rc, g, us.SINE_PRM, lo, hi, pl, ph, 0.05, 25, 300, 17)
+    assert st == R.REACH_OK
+    ub = 53 if dtype == np.float64 else 24
+    o_mn, o_mx = oracle_user_mc(o, us.SINE_PRM, lo, hi, pl, ph, 0.05, 25, 300, 17, ubits=ub)
+    rt = RTOL[np.dtype(dtype)]
+    assert_rel(g_mn, o_mn, rt, "min")
+    assert_rel(g_mx, o_mx, rt, "max")
+
+
+def test_user_mc_ranges_compose_and_sit_in_the_box(rc, users):
+    g, _ = users["SINE"]
+    lo, hi, pl, ph = sine_case(300, np.float64, seed=91)
+    say("user mc ranges")
+    a_mn, a_mx, _ = run_user_mc(rc, g, us.SINE_PRM, lo, hi, pl, ph, 0.05, 30, 500, 5)
+    b_mn, b_mx, _ = run_user_mc(rc, g, us.SINE_PRM, lo, hi, pl, ph, 0.05, 30, 180, 5)
+    c_mn, c_mx, _ = run_user_mc(rc, g, us.SINE_PRM, lo, hi, pl, ph, 0.05, 30, 320, 5, s0=180)
+    assert np.array_equal(a_mn, np.minimum(b_mn, c_mn)) and np.array_equal(a_mx, np.maximum(b_mx, c_mx))
+    e_lo, e_hi, _ = run_user(rc, g, us.SINE_PRM, lo, hi, pl, ph, 0.05, 30)
+    assert np.all(a_mn >= e_lo - 1e-12) and np.all(a_mx <= e_hi + 1e-12)
+
+
+def test_user_mc_restated_ctm_matches_builtin(rc, users):
+    g, _ = users["CTM"]
+    p = workloads.ctm64_f64()
+    lo, hi = p.box()
+    say("user mc ctm vs built-in")
+    u_mn, u_mx, st = run_user_mc(rc, g, p.prm, lo, hi, None, None, p.dt, p.nsteps, 1000, p.seed)
+    assert st == R.REACH_OK
+    b_mn, b_mx = rc.montecarlo(p.kind, p.prm, to_dev(lo), to_dev(hi), p.dt, p.nsteps, 1000, p.seed)
+    assert rc.sync() == R.REACH_OK
+    assert_rel(u_mn, to_host(b_mn), 1e-12, "min")
+    assert_rel(u_mx, to_host(b_mx), 1e-12, "max")
+
+
+def test_user_mc_rejects_long_chains(rc, users):
+    g, _ = users["SINE"]
+    x = to_dev(np.zeros(600))
+    sysd = R.make_system(R.REACH_USER, 600, us.SINE_PRM)
+    st = R.lib().reach_montecarlo_user(rc.ctx, g, R.ctypes.byref(sysd), R.REACH_F64, x.data_ptr(),
+                                       x.data_ptr(), None, None, 0.0, 0.05, 1, 0, 16, 1,
+                                       x.data_ptr(), x.data_ptr(), x.data_ptr(), 1 << 20, None)
+    assert st == R.REACH_E_UNSUPPORTED
