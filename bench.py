@@ -606,9 +606,10 @@ def main():
     ap.add_argument("--heat-only", type=int, default=0, metavar="STEPS",
                     help="only run the 1000^3 heat grid for STEPS RK4 steps (profiling)")
     ap.add_argument("--heat-P", type=int, default=0, help="rows per wave of the heat kernel")
-    ap.add_argument("--only", choices=("mc", "ctm31", "batch"), default=None,
+    ap.add_argument("--only", choices=("mc", "ctm31", "batch", "latency"), default=None,
                     help="only run one extra row (profiling): the Monte Carlo run, the 2^31 "
-                         "FP32 chain (one call) or one batch of the query mix")
+                         "FP32 chain (one call), one batch of the query mix or the 64-cell "
+                         "latency calls")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of one embedding pass's bytes "
                          "(the reference kernel for HBM counter calibration)")
@@ -627,6 +628,8 @@ def main():
         rc = R.Reach(0)
         if args.only == "mc":
             out = extra_mc_ctm4096(rc, R, torch, workloads, 0)
+        elif args.only == "latency":
+            out = latency_ctm64(rc, R, torch, workloads, reps=200, cpu=False)
         elif args.only == "ctm31":
             out = extra_ctm_2p31_f32(rc, R, torch, workloads, steps=1, cpu_oracle=False)
         else:

@@ -75,7 +75,7 @@ struct HeatCtx {
     bool zlane;          // lane is a zero ghost (outside the open face)
     bool ztile;          // the tile holds a zero ghost lane (uniform)
     bool xout;           // lane's cell is an output of this tile
-    T a, h4, h3, h2, dt;   // a = alpha / dx^2; dt/4, dt/3, dt/2, dt
+    T cw[4], m6cw[4];      // a dt / (4 - j) for level j and -6 times it (uniform)
     unsigned bits;
 };
 
@@ -121,10 +121,13 @@ __device__ __forceinline__ void heat_read_edges(HeatEdges<T>& E, const HeatLds<T
     }
 }
 
-// One stencil application on one plane: A w for every row of this lane.
+// One stencil application on one plane, folded into the level's update:
+// out = y + (h/j) A w = y + c (s - 6 w) with s the sum of the six neighbours
+// and c = a h / j, evaluated as fma(c, s, fma(-6 c, w, y)).
 template <class T, int P>
-__device__ __forceinline__ void heat_k(T (&k)[P], const T (&cur)[P], const T (&zm)[P],
-                                       const T (&zp)[P], T up, T dn, const HeatCtx<T>& c) {
+__device__ __forceinline__ void heat_apply(T (&out)[P], const T (&cur)[P], const T (&zm)[P],
+                                           const T (&zp)[P], T up, T dn, const T (&y)[P],
+                                           T cj, T m6cj) {
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const T u = cur[p];
@@ -133,7 +136,7 @@ __device__ __forceinline__ void heat_k(T (&k)[P], const T (&cur)[P], const T (&z
         const T yp = (p < P - 1) ? cur[p + 1] : dn;
         T s = (xm + xp) + (ym + yp);
         s = s + (zm[p] + zp[p]);
-        k[p] = c.a * fmaT(T(-6), u, s);
+        out[p] = fmaT(cj, s, fmaT(m6cj, u, y[p]));
     }
 }
 
@@ -162,28 +165,19 @@ __device__ __forceinline__ void heat_level(HeatRegs<T, P>& R, HeatLds<T, WV>& L,
                                            const HeatRows<T, P>& rows, int z) {
     const int q = z - 1 - LV;
     constexpr int par = pmod(PH - 1 - LV, 2);
-    T k[P];
-    if constexpr (LV == 0) {
-        heat_k<T, P>(k, R.t0[pmod(PH - 1, 6)], R.t0[pmod(PH - 2, 6)], R.t0[pmod(PH, 6)], E.up[0],
-                     E.dn[0], c);
-    } else {
-        heat_k<T, P>(k, R.t[LV - 1][pmod(PH - 1 - LV, 3)], R.t[LV - 1][pmod(PH - 2 - LV, 3)],
-                     R.t[LV - 1][pmod(PH - LV, 3)], E.up[LV], E.dn[LV], c);
-    }
+    // the level's input w (three planes), and y: the state at the start of
+    // the step, plane q.  Levels 0 and 1 read y from the loader ring; plane
+    // z-3 has left the ring by level 2 (its slot holds a plane in flight), so
+    // level 1 hands it on in y2 and level 2 in y3.
+    const T (&cur)[P] = (LV == 0) ? R.t0[pmod(PH - 1, 6)] : R.t[LV - 1][pmod(PH - 1 - LV, 3)];
+    const T (&zm)[P] = (LV == 0) ? R.t0[pmod(PH - 2, 6)] : R.t[LV - 1][pmod(PH - 2 - LV, 3)];
+    const T (&zp)[P] = (LV == 0) ? R.t0[pmod(PH, 6)] : R.t[LV - 1][pmod(PH - LV, 3)];
+    const T (&y)[P] = (LV == 3) ? R.y3[par] : (LV == 2) ? R.y2[par] : R.t0[pmod(PH - 1 - LV, 6)];
     if constexpr (LV < 3) {
-        // y: the state at the start of the step, plane q.  Levels 0 and 1
-        // read it from the loader ring; plane z-3 has left the ring by level 2
-        // (its slot holds a plane in flight), so level 1 hands it on in y2
-        // and level 2 in y3.
-        const T (&y)[P] = (LV == 2) ? R.y2[par] : R.t0[pmod(PH - 1 - LV, 6)];
         T (&nt)[P] = R.t[LV][pmod(PH - 1 - LV, 3)];
-        const T cw = (LV == 0) ? c.h4 : (LV == 1) ? c.h3 : c.h2;
-#pragma unroll
-        for (int p = 0; p < P; ++p) {
-            nt[p] = fmaT(cw, k[p], y[p]);
-            if constexpr (LV == 1) R.y2[par][p] = y[p];
-            if constexpr (LV == 2) R.y3[par][p] = y[p];
-        }
+        if constexpr (LV == 1) copy_rows(R.y2[par], y);
+        if constexpr (LV == 2) copy_rows(R.y3[par], y);
+        heat_apply<T, P>(nt, cur, zm, zp, E.up[LV], E.dn[LV], y, c.cw[LV], c.m6cw[LV]);
         if (ZT) heat_zero_ghost<T, P>(nt, c);
         heat_publish<T, P, WV>(L, LV + 1, par, nt, c);
         if constexpr (!STEADY) {
@@ -200,9 +194,11 @@ __device__ __forceinline__ void heat_level(HeatRegs<T, P>& R, HeatLds<T, WV>& L,
     } else {
         T* out = c.dst + (int64_t)q * c.plane;
         const bool live = STEADY || (q >= 0 && q < c.nz);
+        T nv[P];
+        heat_apply<T, P>(nv, cur, zm, zp, E.up[3], E.dn[3], y, c.cw[3], c.m6cw[3]);
 #pragma unroll
         for (int p = 0; p < P; ++p) {
-            const T v = fmaT(c.dt, k[p], R.y3[par][p]);
+            const T v = nv[p];
             if (live && rows.out[p] && c.xout) {
                 out[rows.off[p] + c.xl] = v;
                 if (!finiteT(v)) c.bits |= ST_NONFINITE;
@@ -294,11 +290,18 @@ __global__ __launch_bounds__(WAVE * WV) void heat3d_kernel(HeatPass a) {
     const int64_t x0 = bx * a.OX - HEAT_R;
     c.ztile = (x0 + WAVE > a.nx) || (x0 <= -1 - a.nx);
     c.xout = c.lane >= HEAT_R && c.lane < WAVE - HEAT_R && gx < a.nx;
-    c.a = (T)a.a;
-    c.h4 = (T)(a.dt / 4.0);
-    c.h3 = (T)(a.dt / 3.0);
-    c.h2 = (T)a.h2;
-    c.dt = (T)a.dt;
+    // straight from the kernel arguments (no arithmetic: they stay in scalar
+    // registers)
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        if constexpr (sizeof(T) == 8) {
+            c.cw[l] = a.cw[l];
+            c.m6cw[l] = a.m6cw[l];
+        } else {
+            c.cw[l] = a.cwf[l];
+            c.m6cw[l] = a.m6cwf[l];
+        }
+    }
     c.bits = 0;
 
     HeatRows<T, P> rows;

@@ -85,6 +85,9 @@ struct HeatPass {
     int32_t per_xcd;    // tiles per XCD in the blockIdx -> tile map
     double a;           // alpha / dx^2
     double h2, dt, dt6;
+    // level j of a step updates w <- y + cw[j] (s - 6 w), cw[j] = a dt / (4 - j)
+    double cw[4], m6cw[4];     // cw and -6 cw
+    float cwf[4], m6cwf[4];    // the same in FP32
     unsigned int* status;
 };
 hipError_t launch_heat3d(int dtype, int P, int WV, const HeatPass& a, int64_t grid,

@@ -121,22 +121,59 @@ __global__ __launch_bounds__(64) void mc_kernel(McArgs a) {
     }
 }
 
+// Reduction of the nw per-wave partials.  Block e (one of E) owns the 64
+// partial slots [w][e][0..63], i.e. cells j = lane * E + e.  Its RED_WAVES
+// waves split the w range round-robin, each issuing RED_UNROLL independent
+// loads per round so the latency of one round covers RED_UNROLL partials; the
+// waves then combine through LDS.  Min and max (NaN-propagating) are exact,
+// so the split changes no value (signed zeros aside).
+constexpr int RED_WAVES = 16;
+constexpr int RED_UNROLL = 8;
+
 template <class T, int E>
-__global__ __launch_bounds__(256) void mc_reduce_kernel(const T* __restrict__ pmin,
-                                                        const T* __restrict__ pmax, int64_t nw,
-                                                        int64_t n, T* __restrict__ rmin,
-                                                        T* __restrict__ rmax, unsigned int* status) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(WAVE * RED_WAVES) void mc_reduce_kernel(
+    const T* __restrict__ pmin, const T* __restrict__ pmax, int64_t nw, int64_t n,
+    T* __restrict__ rmin, T* __restrict__ rmax, unsigned int* status) {
+    __shared__ T smin[RED_WAVES][WAVE];
+    __shared__ T smax[RED_WAVES][WAVE];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x / WAVE;
+    const size_t off = (size_t)blockIdx.x * WAVE + (size_t)lane;
+    const size_t stride = (size_t)E * WAVE;
+    // every wave owns at least one partial when nw >= RED_WAVES; otherwise the
+    // waves without one contribute partial 0 again (min/max are idempotent)
+    const int64_t w_first = wv < nw ? wv : 0;
+    T mn = pmin[(size_t)w_first * stride + off];
+    T mx = pmax[(size_t)w_first * stride + off];
+    for (int64_t w0 = w_first + RED_WAVES; w0 < nw; w0 += (int64_t)RED_WAVES * RED_UNROLL) {
+        T a[RED_UNROLL], b[RED_UNROLL];
+#pragma unroll
+        for (int u = 0; u < RED_UNROLL; ++u) {
+            const int64_t w = w0 + (int64_t)u * RED_WAVES;
+            const size_t idx = (size_t)(w < nw ? w : w_first) * stride + off;
+            a[u] = pmin[idx];
+            b[u] = pmax[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < RED_UNROLL; ++u) {
+            mn = nan_min(mn, a[u]);
+            mx = nan_max(mx, b[u]);
+        }
+    }
+    smin[wv][lane] = mn;
+    smax[wv][lane] = mx;
+    __syncthreads();
+    if (wv != 0) return;
+    mn = smin[0][lane];
+    mx = smax[0][lane];
+#pragma unroll
+    for (int k = 1; k < RED_WAVES; ++k) {
+        mn = nan_min(mn, smin[k][lane]);
+        mx = nan_max(mx, smax[k][lane]);
+    }
+    const int64_t j = (int64_t)lane * E + blockIdx.x;
     unsigned bits = 0;
     if (j < n) {
-        // cell j = lane * E + e lives at [w][e][lane]
-        const int64_t lane = j / E, e = j % E;
-        const size_t off = (size_t)e * WAVE + (size_t)lane;
-        T mn = pmin[off], mx = pmax[off];
-        for (int64_t w = 1; w < nw; ++w) {
-            mn = nan_min(mn, pmin[(size_t)w * E * WAVE + off]);
-            mx = nan_max(mx, pmax[(size_t)w * E * WAVE + off]);
-        }
         rmin[j] = mn;
         rmax[j] = mx;
         if (!finiteT(mn) || !finiteT(mx)) bits = ST_NONFINITE;
@@ -191,10 +228,9 @@ hipError_t launch_mc(int kind, int mode, int dtype, int E, const McArgs& a, hipS
 template <class T>
 static hipError_t reduce_T(int E, const void* pmin, const void* pmax, int64_t nw, int64_t n,
                            void* rmin, void* rmax, unsigned int* status, hipStream_t s) {
-    const unsigned grid = (unsigned)((n + 255) / 256);
 #define REACH_RED(EE)                                                                            \
     case EE:                                                                                     \
-        hipLaunchKernelGGL((mc_reduce_kernel<T, EE>), dim3(grid), dim3(256), 0, s,               \
+        hipLaunchKernelGGL((mc_reduce_kernel<T, EE>), dim3(EE), dim3(WAVE * RED_WAVES), 0, s,    \
                            (const T*)pmin, (const T*)pmax, nw, n, (T*)rmin, (T*)rmax, status);  \
         return hipGetLastError();
     switch (E) {

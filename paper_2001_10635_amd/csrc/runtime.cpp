@@ -242,6 +242,18 @@ struct HeatPlan {
     int64_t TX = 0, TY = 0;   // tiles per side along x / y
 };
 
+// Level j of a step: w <- y + cw[j] (s - 6 w), cw[j] = a dt / (4 - j)
+// (the RK4 stability polynomial in nested form, see the heat kernel).
+void heat_level_constants(HeatPass* a) {
+    for (int l = 0; l < 4; ++l) {
+        const double cl = a->a * a->dt / (double)(4 - l);
+        a->cw[l] = cl;
+        a->m6cw[l] = -6.0 * cl;
+        a->cwf[l] = (float)cl;
+        a->m6cwf[l] = (float)(-6.0 * cl);
+    }
+}
+
 int heat_waves(int P) {
     return P == 4 ? 8 : P == 5 ? 8 : P == 2 ? 16 : P == 8 ? 4 : P == 3 ? 12 : 0;
 }
@@ -316,6 +328,7 @@ reach_status embed_heat3d(reach_ctx* c, const reach_system* s, reach_dtype dtype
     a.per_xcd = (int32_t)((tiles + 7) / 8);
     a.a = s->prm[3] / (s->prm[4] * s->prm[4]);
     a.h2 = dt / 2.0; a.dt = dt; a.dt6 = dt / 6.0;
+    heat_level_constants(&a);
     a.status = c->status;
     const int64_t grid = 8 * (int64_t)a.per_xcd;
     const int dt_id = dtype == REACH_F64 ? 0 : 1;
@@ -360,6 +373,7 @@ reach_status gb_heat3d(reach_ctx* c, const reach_system* s, reach_dtype dtype, c
     a.per_xcd = (int32_t)((tiles + 7) / 8);
     a.a = s->prm[3] / (s->prm[4] * s->prm[4]);
     a.h2 = dt / 2.0; a.dt = dt; a.dt6 = dt / 6.0;
+    heat_level_constants(&a);
     a.status = c->status;
     const int64_t grid = 8 * (int64_t)a.per_xcd;
     char* cur = B;
@@ -972,6 +986,24 @@ reach_status make_desc(reach_ctx* c, const reach_query& q, int64_t tag, QDesc* d
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Host threads for preparing a batch of nq queries (1 below 16384 queries).
+int batch_host_threads(int64_t nq) {
+    if (nq < 16384) return 1;
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int64_t by_size = nq / 8192;
+    return (int)std::max<int64_t>(1, std::min<int64_t>({by_size, 8, hw ? (int64_t)hw : 1}));
+}
+
+// fn(t) for t in [0, nth): t = 0 on the calling thread, the rest on their own.
+template <class F>
+void run_threads(int nth, F&& fn) {
+    std::vector<std::thread> th;
+    th.reserve(nth > 1 ? nth - 1 : 0);
+    for (int t = 1; t < nth; ++t) th.emplace_back(fn, t);
+    fn(0);
+    for (auto& x : th) x.join();
+}
+
 }  // namespace
 
 extern "C" {
@@ -991,14 +1023,50 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     if (!ws || ws_bytes < need) return fail(c, REACH_E_NOMEM, "workspace of %zu bytes needed", need);
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t hs = (hipStream_t)stream;
-    // host descriptors, longest query first
-    std::vector<QDesc> d(nq);
-    for (int64_t i = 0; i < nq; ++i) {
-        reach_status st = make_desc(c, q[i], i, &d[i]);
-        if (st != REACH_OK) return st;
-    }
-    std::stable_sort(d.begin(), d.end(), [](const QDesc& a, const QDesc& b) {
-        return a.n * a.nsteps > b.n * b.nsteps;
+    // Longest query first (the workers pull in this order, so the long chains
+    // start early and the short ones fill the tail).  A counting sort on the
+    // cost n * nsteps rounded down to 1/16 of an octave keeps this O(nq): the
+    // order only steers load balance, and ties keep the caller's order.  Large
+    // batches split the host work over a few threads (histogram, scatter and
+    // descriptor building per contiguous chunk of the caller's array).
+    constexpr int kBuckets = 64 * 16;
+    const int nth = batch_host_threads(nq);
+    std::vector<int64_t> order(nq);
+    std::vector<int16_t> bucket(nq);
+    std::vector<int64_t> hist((size_t)nth * kBuckets, 0);
+    auto chunk = [&](int t, int64_t* lo, int64_t* hi) {
+        *lo = nq * t / nth;
+        *hi = nq * (t + 1) / nth;
+    };
+    run_threads(nth, [&](int t) {
+        int64_t lo, hi;
+        chunk(t, &lo, &hi);
+        int64_t* h = &hist[(size_t)t * kBuckets];
+        for (int64_t i = lo; i < hi; ++i) {
+            const uint64_t n = (uint64_t)std::min<int64_t>(std::max<int64_t>(q[i].sys.n, 0), 1ll << 31);
+            const uint64_t k = (uint64_t)std::min<int64_t>(std::max<int64_t>(q[i].nsteps, 0), 1ll << 31);
+            const uint64_t cost = n * k + 1u;   // < 2^62 + 1, never 0
+            const int msb = 63 - __builtin_clzll(cost);
+            const int frac = msb >= 4 ? (int)((cost >> (msb - 4)) & 15u)
+                                      : (int)((cost << (4 - msb)) & 15u);
+            const int b = kBuckets - 1 - (msb * 16 + frac);   // descending cost
+            bucket[i] = (int16_t)b;
+            ++h[b];
+        }
+    });
+    // exclusive offsets: bucket-major, then thread (keeps the caller's order)
+    int64_t run = 0;
+    for (int b = 0; b < kBuckets; ++b)
+        for (int t = 0; t < nth; ++t) {
+            const int64_t v = hist[(size_t)t * kBuckets + b];
+            hist[(size_t)t * kBuckets + b] = run;
+            run += v;
+        }
+    run_threads(nth, [&](int t) {
+        int64_t lo, hi;
+        chunk(t, &lo, &hi);
+        int64_t* h = &hist[(size_t)t * kBuckets];
+        for (int64_t i = lo; i < hi; ++i) order[h[bucket[i]]++] = i;
     });
     // pinned staging (reused; wait for the previous upload from it)
     if (c->staging_cap < nq) {
@@ -1013,7 +1081,23 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     } else {
         HIPCHK(c, hipEventSynchronize(c->staging_ev));
     }
-    std::memcpy(c->staging, d.data(), sizeof(QDesc) * nq);
+    // descriptors straight into the pinned staging buffer, in schedule order;
+    // the threads validate without touching the context, and the first bad
+    // query (lowest index) is then re-checked to set the error message
+    std::vector<int64_t> bad(nth, nq);
+    run_threads(nth, [&](int t) {
+        int64_t lo, hi;
+        chunk(t, &lo, &hi);
+        for (int64_t j = lo; j < hi; ++j) {
+            const int64_t i = order[j];
+            if (make_desc(nullptr, q[i], i, &c->staging[j]) != REACH_OK && i < bad[t]) bad[t] = i;
+        }
+    });
+    const int64_t first_bad = *std::min_element(bad.begin(), bad.end());
+    if (first_bad < nq) {
+        QDesc tmp;
+        return make_desc(c, q[first_bad], first_bad, &tmp);
+    }
 
     char* base = (char*)ws;
     auto* counter = (unsigned long long*)base;

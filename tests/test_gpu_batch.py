@@ -182,3 +182,69 @@ def test_batch_rejections_and_flags(rc):
     R.reach_embed_rk4_batch(rc.ctx, [good, qb], ws, 1 << 20, 0)
     assert rc.sync() == R.REACH_E_NONFINITE
     assert rc.sync() == R.REACH_OK
+
+
+def packed_ctm_batch(nq, seed):
+    """nq CTM queries (n in [4, 512], 1-40 steps) packed in shared device buffers."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(4, 513, nq)
+    ks = rng.integers(1, 41, nq)
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    lo = rng.uniform(12.0, 24.0, offs[-1])
+    hi = lo + rng.uniform(0.0, 2.0, offs[-1])
+    d = dict(ns=ns, ks=ks, offs=offs, lo=lo, hi=hi, x_lo=to_dev(lo), x_hi=to_dev(hi),
+             r_lo=torch.full((int(offs[-1]),), np.nan, dtype=torch.float64, device="cuda"),
+             r_hi=torch.full((int(offs[-1]),), np.nan, dtype=torch.float64, device="cuda"))
+
+    def q(i, dtype=R.REACH_F64, dt=0.01, n=None):
+        o = 8 * int(offs[i])
+        return R.make_query(R.REACH_CTM, int(ns[i]) if n is None else n, workloads.CTM_PRM, dtype,
+                            d["x_lo"].data_ptr() + o, d["x_hi"].data_ptr() + o,
+                            d["r_lo"].data_ptr() + o, d["r_hi"].data_ptr() + o, dt, int(ks[i]))
+    d["q"] = q
+    return d
+
+
+def test_batch_of_20000_queries_equals_one_launch_per_query(rc):
+    """Large batches prepare their descriptors on several host threads: the
+    results still equal one launch per query, bit for bit, and the oracle."""
+    b = packed_ctm_batch(20000, 77)
+    qs = R.query_array([b["q"](i) for i in range(20000)])
+    nb = R.reach_batch_workspace_bytes(20000)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    say("batch 20000 queries")
+    R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
+    assert rc.sync() == R.REACH_OK
+    got_lo, got_hi = to_host(b["r_lo"]), to_host(b["r_hi"])
+    assert not np.isnan(got_lo).any() and not np.isnan(got_hi).any()
+    b["r_lo"].fill_(np.nan)
+    b["r_hi"].fill_(np.nan)
+    say("each 20000 queries")
+    R.reach_embed_rk4_each(rc.ctx, qs, 8)
+    assert rc.sync() == R.REACH_OK
+    assert np.array_equal(to_host(b["r_lo"]), got_lo)
+    assert np.array_equal(to_host(b["r_hi"]), got_hi)
+    offs = b["offs"]
+    for i in (0, 1, 9999, 15001, 19999):
+        a, e = int(offs[i]), int(offs[i + 1])
+        o_lo, o_hi = oracle.embed_rk4(R.REACH_CTM, workloads.CTM_PRM, b["lo"][a:e], b["hi"][a:e],
+                                      dt=0.01, nsteps=int(b["ks"][i]))
+        assert_rel(got_lo[a:e], o_lo, 1e-12, f"query {i} lower")
+        assert_rel(got_hi[a:e], o_hi, 1e-12, f"query {i} upper")
+
+
+def test_batch_of_20000_reports_the_first_bad_query(rc):
+    b = packed_ctm_batch(20000, 78)
+    qs = [b["q"](i) for i in range(20000)]
+    qs[17000] = b["q"](17000, n=600)            # too long for the batch path
+    qs[3000] = b["q"](3000, dt=-1.0)             # the lower index wins
+    nb = R.reach_batch_workspace_bytes(20000)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    with pytest.raises(R.ReachError) as e:
+        R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
+    assert e.value.status == R.REACH_E_INVAL and "dt" in str(e.value)
+    qs[3000] = b["q"](3000)
+    with pytest.raises(R.ReachError) as e:
+        R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
+    assert e.value.status == R.REACH_E_UNSUPPORTED and "512" in str(e.value)
+    assert rc.sync() == R.REACH_OK
