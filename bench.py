@@ -543,11 +543,41 @@ def extra_user_sine(rc, R, torch):
     assert rc.sync() == R.REACH_OK
     msec = e0.elapsed_time(e1) / 1e3
     R.reach_user_destroy(user)
-    return {"workload": "user sine chain (hipRTC) n=2^22 FP64, dt=0.05, 200 RK4 steps; Monte "
-                        "Carlo n=512, 2^16 samples",
-            "compile_seconds": round(compile_s, 2),
-            "embed_state_steps_per_s": 2.0 * n * N / sec, "embed_seconds": round(sec, 4),
-            "mc_cell_steps_per_s": 512.0 * m * N / msec, "mc_seconds": round(msec, 4)}
+    out = {"workload": "user sine chain (hipRTC) n=2^22 FP64, dt=0.05, 200 RK4 steps; Monte "
+                       "Carlo n=512, 2^16 samples",
+           "compile_seconds": round(compile_s, 2),
+           "embed_state_steps_per_s": 2.0 * n * N / sec, "embed_seconds": round(sec, 4),
+           "mc_cell_steps_per_s": 512.0 * m * N / msec, "mc_seconds": round(msec, 4)}
+    # cost of the run-time path itself: the reaction-diffusion chain as user
+    # text in the built-in kernel's operation order against the built-in
+    # kernel, same inputs (n = 2^24, 200 steps)
+    user = rc.user(us.RD_FUSED)
+    n2 = 1 << 24
+    c_lo = torch.rand(n2, dtype=torch.float64, device="cuda", generator=g) * 0.5
+    c_hi = c_lo + 0.02
+    pl2 = torch.tensor([-0.1], dtype=torch.float64, device="cuda")
+    ph2 = torch.tensor([0.1], dtype=torch.float64, device="cuda")
+    runs = {"user": lambda: rc.embed_user(user, (1.0, 2.0), c_lo, c_hi, 0.1, N, p_lo=pl2,
+                                          p_hi=ph2),
+            "builtin": lambda: rc.embed(R.REACH_RD, (1.0,), c_lo, c_hi, 0.1, N, p_lo=pl2,
+                                        p_hi=ph2)}
+    secs = {}
+    for name, f in runs.items():
+        f()
+        torch.cuda.synchronize()
+        e0.record()
+        f()
+        e1.record()
+        torch.cuda.synchronize()
+        assert rc.sync() == R.REACH_OK
+        secs[name] = e0.elapsed_time(e1) / 1e3
+    R.reach_user_destroy(user)
+    out["user_rd_vs_builtin"] = {
+        "workload": "reaction-diffusion chain n=2^24 FP64, dt=0.1, 200 RK4 steps",
+        "user_state_steps_per_s": 2.0 * n2 * N / secs["user"],
+        "builtin_state_steps_per_s": 2.0 * n2 * N / secs["builtin"],
+        "user_over_builtin_time": round(secs["user"] / secs["builtin"], 3)}
+    return out
 
 
 def extra_mc_ctm4096(rc, R, torch, workloads, cpu_samples):
@@ -606,10 +636,10 @@ def main():
     ap.add_argument("--heat-only", type=int, default=0, metavar="STEPS",
                     help="only run the 1000^3 heat grid for STEPS RK4 steps (profiling)")
     ap.add_argument("--heat-P", type=int, default=0, help="rows per wave of the heat kernel")
-    ap.add_argument("--only", choices=("mc", "ctm31", "batch", "latency"), default=None,
+    ap.add_argument("--only", choices=("mc", "ctm31", "batch", "latency", "user"), default=None,
                     help="only run one extra row (profiling): the Monte Carlo run, the 2^31 "
-                         "FP32 chain (one call), one batch of the query mix or the 64-cell "
-                         "latency calls")
+                         "FP32 chain (one call), one batch of the query mix, the 64-cell "
+                         "latency calls or the run-time compiled systems")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of one embedding pass's bytes "
                          "(the reference kernel for HBM counter calibration)")
@@ -628,6 +658,8 @@ def main():
         rc = R.Reach(0)
         if args.only == "mc":
             out = extra_mc_ctm4096(rc, R, torch, workloads, 0)
+        elif args.only == "user":
+            out = extra_user_sine(rc, R, torch)
         elif args.only == "latency":
             out = latency_ctm64(rc, R, torch, workloads, reps=200, cpu=False)
         elif args.only == "ctm31":

@@ -375,8 +375,12 @@ reach_status reach_server_stats(reach_ctx* ctx, double* p50_us, double* p99_us,
  * reach_user_create compiles the text with hipRTC for the context's device
  * (no floating-point contraction, as the built-in kernels) and loads it;
  * REACH_E_INVAL with the compiler's log in reach_last_error() when it does
- * not compile.  The handle is owned by the caller (reach_user_destroy) and
- * valid on the context's device only.
+ * not compile.  Kernels are built per precision and input kind (none or
+ * scalar, per cell): the FP64 scalar set at creation, every other set on
+ * the first call that needs it (that call blocks for the compile and may
+ * fail with REACH_E_INVAL / REACH_E_DEVICE like creation).  The handle is
+ * owned by the caller (reach_user_destroy), valid on the context's device
+ * only, and like the context not safe for concurrent calls.
  *
  * reach_embed_rk4_user: Algorithm 3 (embedding RK4) for the user system.
  * `sys` has kind REACH_USER, n, n_in and prm; the other arguments and the
@@ -387,7 +391,7 @@ typedef struct reach_user reach_user;
 
 reach_status reach_user_create(reach_ctx* ctx, const char* source, reach_user** out);
 void reach_user_destroy(reach_user* user);
-reach_status reach_embed_rk4_user(reach_ctx* ctx, const reach_user* user,
+reach_status reach_embed_rk4_user(reach_ctx* ctx, reach_user* user,
                                   const reach_system* sys, reach_dtype dtype,
                                   const void* x_lo, const void* x_hi, const void* p_lo,
                                   const void* p_hi, double t0, double dt, int64_t nsteps,
@@ -402,7 +406,7 @@ reach_status reach_embed_rk4_user(reach_ctx* ctx, const reach_user* user,
  * reach_montecarlo_user with m samples; (size_t)-1 on bad arguments. */
 size_t reach_user_workspace_bytes(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
                                   int64_t m);
-reach_status reach_montecarlo_user(reach_ctx* ctx, const reach_user* user,
+reach_status reach_montecarlo_user(reach_ctx* ctx, reach_user* user,
                                    const reach_system* sys, reach_dtype dtype,
                                    const void* x_lo, const void* x_hi, const void* p_lo,
                                    const void* p_hi, double t0, double dt, int64_t nsteps,

@@ -52,9 +52,10 @@ struct UserPass { REACH_USER_PASS_FIELDS };
 
 struct UserMcPass { REACH_USER_MC_FIELDS };
 
-// tile widths (cells per lane); wider tiles of arbitrary user code spill
+// Tile widths (cells per lane); wider tiles of arbitrary user code spill.
 constexpr int kUserE[] = {1, 2, 4, 8};
 constexpr int kNumE = 4;
+constexpr int kNumMcE = 4;
 
 const char* kPrelude = R"(
 #define REACH_DEVICE __device__ static inline
@@ -97,18 +98,34 @@ __device__ inline typename Real<D>::T call_d(typename Real<D>::T xm, typename Re
     else return reach_user_f32::reach_d(xm, x, xp, hm, h, hp, u, uh, prm, i, n);
 }
 
-template <int D, int E>
-__global__ __launch_bounds__(64) void user_tile(UserPass a) {
+// Inputs seen by a lane: M = 0 one value per side (no input, or a scalar
+// input interval), M = 1 one value per cell and side.
+template <int D, int E, int M> struct UIn;
+template <int D, int E> struct UIn<D, E, 0> {
+    typename Real<D>::T v[2];
+    __device__ inline typename Real<D>::T at(int s, int) const { return v[s]; }
+};
+template <int D, int E> struct UIn<D, E, 1> {
+    typename Real<D>::T v[2][E];
+    __device__ inline typename Real<D>::T at(int s, int e) const { return v[s][e]; }
+};
+
+// One tile: load, ksteps classical RK4 steps of both sides of the lane's
+// cells, store.  MASKED: the tile runs past cell n-1 and cells past it (ok[e]
+// false) are held at the zero ghost (the stage input t after stages 1-3, the
+// state y after stage 4); a tile inside the chain skips those selects.  The
+// whole tile is one function body per variant: splitting the step loop off
+// behind reference parameters costs the compiler ~100 extra registers.
+template <int D, int E, int M, bool MASKED>
+__device__ inline void tile_run(const UserPass& a, long long w) {
     typedef typename Real<D>::T T;
     const int lane = threadIdx.x;
-    const long long b = blockIdx.x;
-    const long long w = (b & 7) * (long long)a.per_xcd + (b >> 3);
-    if (w >= a.W) return;
     const long long span = 64LL * E;
     const long long ts = w * a.OUT;
     const T* src[2] = {(const T*)a.src_lo, (const T*)a.src_hi};
     const T* pin[2] = {(const T*)a.p_lo, (const T*)a.p_hi};
-    T y[2][E], u[2][E];
+    T y[2][E];
+    UIn<D, E, M> u;
     bool ok[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -117,8 +134,12 @@ __global__ __launch_bounds__(64) void user_tile(UserPass a) {
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             y[s][e] = ok[e] ? src[s][i] : T(0);
-            u[s][e] = a.in_mode == 0 ? T(0) : a.in_mode == 1 ? pin[s][0] : (ok[e] ? pin[s][i] : T(0));
+            if constexpr (M == 1) u.v[s][e] = ok[e] ? pin[s][i] : T(0);
         }
+    }
+    if constexpr (M == 0) {
+#pragma unroll
+        for (int s = 0; s < 2; ++s) u.v[s] = a.in_mode == 0 ? T(0) : pin[s][0];
     }
     T prm[8];
 #pragma unroll
@@ -141,8 +162,8 @@ __global__ __launch_bounds__(64) void user_tile(UserPass a) {
                 const T xm = e == 0 ? ln0 : in[0][e - 1], xp = e == E - 1 ? rn0 : in[0][e + 1];
                 const T hm = e == 0 ? ln1 : in[1][e - 1], hp = e == E - 1 ? rn1 : in[1][e + 1];
                 T kk[2];
-                kk[0] = call_d<D>(xm, in[0][e], xp, hm, in[1][e], hp, u[0][e], u[1][e], prm, i, a.n);
-                kk[1] = call_d<D>(hm, in[1][e], hp, xm, in[0][e], xp, u[1][e], u[0][e], prm, i, a.n);
+                kk[0] = call_d<D>(xm, in[0][e], xp, hm, in[1][e], hp, u.at(0, e), u.at(1, e), prm, i, a.n);
+                kk[1] = call_d<D>(hm, in[1][e], hp, xm, in[0][e], xp, u.at(1, e), u.at(0, e), prm, i, a.n);
 #pragma unroll
                 for (int s = 0; s < 2; ++s) {
                     const T kv = kk[s];
@@ -150,7 +171,10 @@ __global__ __launch_bounds__(64) void user_tile(UserPass a) {
                     else if (stage == 2) { acc[s][e] = __builtin_fma(T(2), kv, acc[s][e]); t[s][e] = __builtin_fma(h2, kv, y[s][e]); }
                     else if (stage == 3) { acc[s][e] = __builtin_fma(T(2), kv, acc[s][e]); t[s][e] = __builtin_fma(dt, kv, y[s][e]); }
                     else { acc[s][e] = acc[s][e] + kv; y[s][e] = __builtin_fma(dt6, acc[s][e], y[s][e]); }
-                    if (!ok[e]) { t[s][e] = T(0); y[s][e] = T(0); }
+                    if (MASKED && !ok[e]) {
+                        if (stage == 4) y[s][e] = T(0);
+                        else t[s][e] = T(0);
+                    }
                 }
             }
         }
@@ -174,6 +198,15 @@ __global__ __launch_bounds__(64) void user_tile(UserPass a) {
         const unsigned long long nf = __ballot(bits & 1u), od = __ballot(bits & 2u);
         if ((nf | od) && lane == 0) atomicOr(a.status, (nf ? 1u : 0u) | (od ? 2u : 0u));
     }
+}
+
+template <int D, int E, int M>
+__global__ __launch_bounds__(64) void user_tile(UserPass a) {
+    const long long b = blockIdx.x;
+    const long long w = (b & 7) * (long long)a.per_xcd + (b >> 3);
+    if (w >= a.W) return;
+    if (w * a.OUT + 64LL * E <= a.n) tile_run<D, E, M, false>(a, w);
+    else tile_run<D, E, M, true>(a, w);
 }
 
 // Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
@@ -216,12 +249,12 @@ template <class T> __device__ inline T nan_max(T m, T x) {
 // (cells lane * E + e, n <= 64 E), f = d on the diagonal, each final state
 // folded into the wave's min / max partials [w][e][lane].  Sample s draws
 // U(s, j) = word j mod 4 of Philox at key (seed, 0), counter
-// (floor(j / 4), s, 2, 0): cells at j < n, inputs at j = n + k.
-template <int D, int E>
-__global__ __launch_bounds__(64) void user_mc(UserMcPass a) {
+// (floor(j / 4), s, 2, 0): cells at j < n, inputs at j = n + k.  MASKED as
+// for the tiles (n < 64 E).
+template <int D, int E, int M, bool MASKED>
+__device__ inline void mc_run(const UserMcPass& a, long long w) {
     typedef typename Real<D>::T T;
     const int lane = threadIdx.x;
-    const long long w = blockIdx.x;
     const long long n = a.n;
     const T* xlo = (const T*)a.x_lo;
     const T* xhi = (const T*)a.x_hi;
@@ -238,7 +271,8 @@ __global__ __launch_bounds__(64) void user_mc(UserMcPass a) {
     for (int e = 0; e < E; ++e) ok[e] = (long long)lane * E + e < n;
     bool first = true;
     for (long long s = a.s0 + w; s < a.s0 + a.m; s += a.nw) {
-        T y[E], u[E];
+        T y[E];
+        UIn<D, E, M> u;
 #pragma unroll
         for (int e = 0; e < E; ++e) {
             const long long j = (long long)lane * E + e;
@@ -247,15 +281,17 @@ __global__ __launch_bounds__(64) void user_mc(UserMcPass a) {
             const T uu = unif(pick(r, j & 3), T(0));
             y[e] = ok[e] ? __builtin_fma(uu, xhi[j] - xlo[j], xlo[j]) : T(0);
         }
-        if (a.in_mode == 1) {
-            const long long j = n;
-            const Philox4 r = philox((unsigned long long)(j >> 2), (unsigned long long)s, 2ULL, 0ULL,
-                                     a.seed, 0ULL);
-            const T uu = unif(pick(r, j & 3), T(0));
-            const T v = __builtin_fma(uu, phi[0] - plo[0], plo[0]);
-#pragma unroll
-            for (int e = 0; e < E; ++e) u[e] = v;
-        } else if (a.in_mode == 2) {
+        if constexpr (M == 0) {
+            if (a.in_mode == 1) {
+                const long long j = n;
+                const Philox4 r = philox((unsigned long long)(j >> 2), (unsigned long long)s, 2ULL,
+                                         0ULL, a.seed, 0ULL);
+                const T uu = unif(pick(r, j & 3), T(0));
+                u.v[0] = __builtin_fma(uu, phi[0] - plo[0], plo[0]);
+            } else {
+                u.v[0] = T(0);
+            }
+        } else {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const long long c = (long long)lane * E + e;
@@ -263,11 +299,8 @@ __global__ __launch_bounds__(64) void user_mc(UserMcPass a) {
                 const Philox4 r = philox((unsigned long long)(j >> 2), (unsigned long long)s, 2ULL,
                                          0ULL, a.seed, 0ULL);
                 const T uu = unif(pick(r, j & 3), T(0));
-                u[e] = ok[e] ? __builtin_fma(uu, phi[c] - plo[c], plo[c]) : T(0);
+                u.v[0][e] = ok[e] ? __builtin_fma(uu, phi[c] - plo[c], plo[c]) : T(0);
             }
-        } else {
-#pragma unroll
-            for (int e = 0; e < E; ++e) u[e] = T(0);
         }
         for (long long k = 0; k < a.nsteps; ++k) {
             T acc[E], t[E];
@@ -281,12 +314,16 @@ __global__ __launch_bounds__(64) void user_mc(UserMcPass a) {
                 for (int e = 0; e < E; ++e) {
                     const long long i = (long long)lane * E + e;
                     const T xm = e == 0 ? ln : in[e - 1], xp = e == E - 1 ? rn : in[e + 1];
-                    const T kv = call_d<D>(xm, in[e], xp, xm, in[e], xp, u[e], u[e], prm, i, n);
+                    const T uu = u.at(0, e);
+                    const T kv = call_d<D>(xm, in[e], xp, xm, in[e], xp, uu, uu, prm, i, n);
                     if (stage == 1) { acc[e] = kv; t[e] = __builtin_fma(h2, kv, y[e]); }
                     else if (stage == 2) { acc[e] = __builtin_fma(T(2), kv, acc[e]); t[e] = __builtin_fma(h2, kv, y[e]); }
                     else if (stage == 3) { acc[e] = __builtin_fma(T(2), kv, acc[e]); t[e] = __builtin_fma(dt, kv, y[e]); }
                     else { acc[e] = acc[e] + kv; y[e] = __builtin_fma(dt6, acc[e], y[e]); }
-                    if (!ok[e]) { t[e] = T(0); y[e] = T(0); }
+                    if (MASKED && !ok[e]) {
+                        if (stage == 4) y[e] = T(0);
+                        else t[e] = T(0);
+                    }
                 }
             }
         }
@@ -300,54 +337,46 @@ __global__ __launch_bounds__(64) void user_mc(UserMcPass a) {
     }
 }
 
+template <int D, int E, int M>
+__global__ __launch_bounds__(64) void user_mc(UserMcPass a) {
+    if (a.n < 64LL * E) mc_run<D, E, M, true>(a, blockIdx.x);
+    else mc_run<D, E, M, false>(a, blockIdx.x);
+}
+
 }  // namespace reach_rtc
 )";
 
-std::string name_expr(int dtype, int E, bool mc = false) {
+std::string name_expr(int dtype, int E, int M, bool mc) {
     return std::string(mc ? "reach_rtc::user_mc<" : "reach_rtc::user_tile<") +
-           std::to_string(dtype) + ", " + std::to_string(E) + ">";
+           std::to_string(dtype) + ", " + std::to_string(E) + ", " + std::to_string(M) + ">";
 }
 
 }  // namespace
 
 struct reach_user {
     int device = 0;
-    hipModule_t mod = nullptr;
-    hipFunction_t fn[2][kNumE] = {};   // embedding tiles
-    hipFunction_t mc[2][kNumE] = {};   // Monte Carlo samples
+    std::string text;                       // the whole program handed to hipRTC
+    std::string arch;                       // --offload-arch=... of the device
+    // one module per (precision, input mode), compiled on first use
+    hipModule_t mod[2][2] = {};
+    hipFunction_t fn[2][2][kNumE] = {};     // embedding tiles [dtype][mode][E]
+    hipFunction_t mc[2][2][kNumMcE] = {};   // Monte Carlo samples
 };
 
-extern "C" {
+namespace {
 
-reach_status reach_user_create(reach_ctx* c, const char* source, reach_user** out) {
-    if (!c || !source || !out) return REACH_E_INVAL;
-    *out = nullptr;
-    std::string text = kPrelude;
-    text += "struct UserPass { " REACH_STR(REACH_USER_PASS_FIELDS) " };\n";
-    text += "struct UserMcPass { " REACH_STR(REACH_USER_MC_FIELDS) " };\n";
-    text += "namespace reach_user_f64 {\ntypedef double real;\n";
-    text += source;
-    text += "\n}\nnamespace reach_user_f32 {\ntypedef float real;\n";
-    text += source;
-    text += "\n}\n";
-    text += kKernel;
+// Compile and load the kernels of one precision d and input mode m.
+reach_status compile_set(reach_ctx* c, reach_user* u, int d, int m) {
+    if (u->mod[d][m]) return REACH_OK;
     hiprtcProgram prog;
-    if (hiprtcCreateProgram(&prog, text.c_str(), "reach_user.hip", 0, nullptr, nullptr) !=
+    if (hiprtcCreateProgram(&prog, u->text.c_str(), "reach_user.hip", 0, nullptr, nullptr) !=
         HIPRTC_SUCCESS)
         return rt::set_error(c, REACH_E_NOMEM, "hiprtcCreateProgram failed");
     std::vector<std::string> names;
-    for (int mc = 0; mc < 2; ++mc)
-        for (int d = 0; d < 2; ++d)
-            for (int e : kUserE) names.push_back(name_expr(d, e, mc == 1));
+    for (int e = 0; e < kNumE; ++e) names.push_back(name_expr(d, kUserE[e], m, false));
+    for (int e = 0; e < kNumMcE; ++e) names.push_back(name_expr(d, kUserE[e], m, true));
     for (const auto& nm : names) hiprtcAddNameExpression(prog, nm.c_str());
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, rt::ctx_device(c)) != hipSuccess) {
-        hiprtcDestroyProgram(&prog);
-        return rt::set_error(c, REACH_E_DEVICE, "hipGetDeviceProperties failed");
-    }
-    std::string arch = std::string("--offload-arch=") + prop.gcnArchName;
-    arch = arch.substr(0, arch.find(':'));
-    const char* opts[] = {arch.c_str(), "-O3", "-std=c++17", "-ffp-contract=off",
+    const char* opts[] = {u->arch.c_str(), "-O3", "-std=c++17", "-ffp-contract=off",
                           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
     const hiprtcResult cr = hiprtcCompileProgram(prog, 8, opts);
     if (cr != HIPRTC_SUCCESS) {
@@ -370,38 +399,66 @@ reach_status reach_user_create(reach_ctx* c, const char* source, reach_user** ou
         lowered.push_back(low ? low : "");
     }
     hiprtcDestroyProgram(&prog);
+    hipModule_t mod = nullptr;
+    if (hipSetDevice(u->device) != hipSuccess || hipModuleLoadData(&mod, code.data()) != hipSuccess)
+        return rt::set_error(c, REACH_E_DEVICE, "loading the compiled user module failed");
+    hipFunction_t f[kNumE + kNumMcE];
+    for (size_t q = 0; q < names.size(); ++q) {
+        if (hipModuleGetFunction(&f[q], mod, lowered[q].c_str()) != hipSuccess) {
+            hipModuleUnload(mod);
+            return rt::set_error(c, REACH_E_DEVICE, "user kernel " + names[q] + " not found");
+        }
+    }
+    for (int e = 0; e < kNumE; ++e) u->fn[d][m][e] = f[e];
+    for (int e = 0; e < kNumMcE; ++e) u->mc[d][m][e] = f[kNumE + e];
+    u->mod[d][m] = mod;
+    return REACH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+reach_status reach_user_create(reach_ctx* c, const char* source, reach_user** out) {
+    if (!c || !source || !out) return REACH_E_INVAL;
+    *out = nullptr;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, rt::ctx_device(c)) != hipSuccess)
+        return rt::set_error(c, REACH_E_DEVICE, "hipGetDeviceProperties failed");
     reach_user* u = new reach_user;
     u->device = rt::ctx_device(c);
-    if (hipSetDevice(u->device) != hipSuccess ||
-        hipModuleLoadData(&u->mod, code.data()) != hipSuccess) {
+    u->arch = std::string("--offload-arch=") + prop.gcnArchName;
+    u->arch = u->arch.substr(0, u->arch.find(':'));
+    u->text = kPrelude;
+    u->text += "struct UserPass { " REACH_STR(REACH_USER_PASS_FIELDS) " };\n";
+    u->text += "struct UserMcPass { " REACH_STR(REACH_USER_MC_FIELDS) " };\n";
+    u->text += "namespace reach_user_f64 {\ntypedef double real;\n";
+    u->text += source;
+    u->text += "\n}\nnamespace reach_user_f32 {\ntypedef float real;\n";
+    u->text += source;
+    u->text += "\n}\n";
+    u->text += kKernel;
+    // FP64 with no or scalar inputs now (this also rejects text that does not
+    // compile); the other precision and per-cell inputs on first use
+    const reach_status st = compile_set(c, u, 0, 0);
+    if (st != REACH_OK) {
         delete u;
-        return rt::set_error(c, REACH_E_DEVICE, "loading the compiled user module failed");
+        return st;
     }
-    for (int mc = 0, k = 0; mc < 2; ++mc)
-        for (int d = 0; d < 2; ++d)
-            for (int e = 0; e < kNumE; ++e, ++k) {
-                hipFunction_t* f = mc ? &u->mc[d][e] : &u->fn[d][e];
-                if (hipModuleGetFunction(f, u->mod, lowered[k].c_str()) != hipSuccess) {
-                    hipModuleUnload(u->mod);
-                    delete u;
-                    return rt::set_error(c, REACH_E_DEVICE,
-                                         "user kernel " + names[k] + " not found");
-                }
-            }
     *out = u;
     return REACH_OK;
 }
 
 void reach_user_destroy(reach_user* u) {
     if (!u) return;
-    if (u->mod) {
-        hipSetDevice(u->device);
-        hipModuleUnload(u->mod);
-    }
+    hipSetDevice(u->device);
+    for (int d = 0; d < 2; ++d)
+        for (int m = 0; m < 2; ++m)
+            if (u->mod[d][m]) hipModuleUnload(u->mod[d][m]);
     delete u;
 }
 
-reach_status reach_embed_rk4_user(reach_ctx* c, const reach_user* u, const reach_system* s,
+reach_status reach_embed_rk4_user(reach_ctx* c, reach_user* u, const reach_system* s,
                                   reach_dtype dtype, const void* x_lo, const void* x_hi,
                                   const void* p_lo, const void* p_hi, double t0, double dt,
                                   int64_t nsteps, void* r_lo, void* r_hi, void* ws,
@@ -427,8 +484,11 @@ reach_status reach_embed_rk4_user(reach_ctx* c, const reach_user* u, const reach
             return rt::set_error(c, REACH_E_DEVICE, "copy failed");
         return REACH_OK;
     }
-    // plan: the smallest tile that holds the chain, else E = 8 with K steps per pass
+    // plan: the smallest tile that holds the chain, else E = 8 with K steps per
+    // pass (K = 12 by default: within a few per cent of the best K for a cheap
+    // d, whose passes are bandwidth-heavy, and for a transcendental one)
     const int64_t n = s->n;
+    const int di = dtype == REACH_F64 ? 0 : 1;
     int E = (int)rt::option(c, "user.E");
     int K = (int)rt::option(c, "user.K");
     int ei = -1;
@@ -448,7 +508,7 @@ reach_status reach_embed_rk4_user(reach_ctx* c, const reach_user* u, const reach
         a.W = 1; a.OUT = 0; a.H = 0;
         passes = (nsteps + K - 1) / K;
     } else {
-        if (!K) K = 8;
+        if (!K) K = (int)std::max<int64_t>(1, std::min<int64_t>(12, (span - 1) / 8));
         if ((int64_t)8 * K >= span)
             return rt::set_error(c, REACH_E_INVAL, "user.K too large for the tile width");
         a.H = 4 * K;
@@ -480,7 +540,10 @@ reach_status reach_embed_rk4_user(reach_ctx* c, const reach_user* u, const reach
     for (int j = 0; j < 8; ++j) a.prm[j] = s->prm[j];
     a.h2 = dt / 2.0; a.dt = dt; a.dt6 = dt / 6.0;
     a.status = rt::ctx_status(c);
-    hipFunction_t fn = u->fn[dtype == REACH_F64 ? 0 : 1][ei];
+    const int mode = a.in_mode == 2 ? 1 : 0;
+    st = compile_set(c, u, di, mode);
+    if (st != REACH_OK) return st;
+    hipFunction_t fn = u->fn[di][mode][ei];
     const unsigned grid = (unsigned)(8 * (int64_t)a.per_xcd);
     int64_t done = 0;
     for (int64_t p = 0; p < passes; ++p) {
@@ -505,7 +568,7 @@ reach_status reach_embed_rk4_user(reach_ctx* c, const reach_user* u, const reach
 
 // Monte Carlo plan: tile width holding the whole chain, resident waves.
 static int user_mc_E(int64_t n) {
-    for (int j = 0; j < kNumE; ++j)
+    for (int j = 0; j < kNumMcE; ++j)
         if ((int64_t)64 * kUserE[j] >= n) return j;
     return -1;
 }
@@ -526,7 +589,7 @@ size_t reach_user_workspace_bytes(reach_ctx* c, const reach_system* s, reach_dty
     return 2 * (size_t)user_mc_waves(c, m) * 64 * (size_t)kUserE[ei] * el;
 }
 
-reach_status reach_montecarlo_user(reach_ctx* c, const reach_user* u, const reach_system* s,
+reach_status reach_montecarlo_user(reach_ctx* c, reach_user* u, const reach_system* s,
                                    reach_dtype dtype, const void* x_lo, const void* x_hi,
                                    const void* p_lo, const void* p_hi, double t0, double dt,
                                    int64_t nsteps, int64_t s0, int64_t m, uint64_t seed,
@@ -567,7 +630,10 @@ reach_status reach_montecarlo_user(reach_ctx* c, const reach_user* u, const reac
     a.h2 = dt / 2.0; a.dt = dt; a.dt6 = dt / 6.0;
     const int d = dtype == REACH_F64 ? 0 : 1;
     void* args[] = {&a};
-    if (hipModuleLaunchKernel(u->mc[d][ei], (unsigned)a.nw, 1, 1, 64, 1, 1, 0, hs, args,
+    const int mode = a.in_mode == 2 ? 1 : 0;
+    const reach_status cs = compile_set(c, u, d, mode);
+    if (cs != REACH_OK) return cs;
+    if (hipModuleLaunchKernel(u->mc[d][mode][ei], (unsigned)a.nw, 1, 1, 64, 1, 1, 0, hs, args,
                               nullptr) != hipSuccess)
         return rt::set_error(c, REACH_E_DEVICE, "user Monte Carlo launch failed");
     if (launch_mc_reduce(d, kUserE[ei], a.part_min, a.part_max, a.nw, s->n, r_min, r_max,

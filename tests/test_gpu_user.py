@@ -184,6 +184,33 @@ def test_user_errors(rc, users):
         rc.embed_user(g, us.SINE_PRM, to_dev(np.zeros(4000)), to_dev(np.zeros(4000)), 0.05, 3)
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("inputs", ["scalar", "cell"])
+@pytest.mark.parametrize("n", [300, 5000])
+def test_user_rd_in_builtin_order_equals_builtin_bitwise(rc, n, dtype, inputs):
+    """Same per-cell arithmetic as the built-in RD kernel (and different tile
+    shapes, halos and pass counts): identical results."""
+    g = rc.user(us.RD_FUSED)
+    try:
+        rng = np.random.default_rng(n + 7)
+        lo = rng.uniform(-1.0, 1.0, n).astype(dtype)
+        hi = (lo + rng.uniform(0.0, 0.2, n)).astype(dtype)
+        if inputs == "scalar":
+            pl, ph = np.array([-0.1], dtype), np.array([0.1], dtype)
+        else:
+            pl = rng.uniform(-0.1, 0.0, n).astype(dtype)
+            ph = (pl + rng.uniform(0.0, 0.2, n)).astype(dtype)
+        say(f"user RD in built-in order n={n} {np.dtype(dtype).name} {inputs}")
+        u_lo, u_hi, st = run_user(rc, g, (1.0, 2.0), lo, hi, pl, ph, 0.05, 41)
+        assert st == R.REACH_OK
+        b_lo, b_hi = rc.embed(R.REACH_RD, (1.0,), to_dev(lo), to_dev(hi), 0.05, 41,
+                              p_lo=to_dev(pl), p_hi=to_dev(ph))
+        assert rc.sync() == R.REACH_OK
+        assert np.array_equal(u_lo, to_host(b_lo)) and np.array_equal(u_hi, to_host(b_hi))
+    finally:
+        R.reach_user_destroy(g)
+
+
 # ------------------------------------------------------------ Monte Carlo
 
 def oracle_user_mc(o, prm, lo, hi, pl, ph, dt, nsteps, m, seed, s0=0, ubits=53):

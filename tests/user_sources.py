@@ -50,6 +50,17 @@ REACH_DEVICE real reach_d(real xm, real x, real xp, real hm, real h, real hp, re
 }
 """
 
+# RD in the built-in kernel's fused operation order, with prm[0] = 1/h^2 and
+# prm[1] = 2/h^2: the user kernel then runs the same arithmetic per cell as
+# the built-in one, so the two agree bit for bit.
+RD_FUSED = r"""
+REACH_DEVICE real reach_d(real xm, real x, real xp, real hm, real h, real hp, real u, real uh,
+                          const real* prm, long long i, long long n)
+{
+    return fma(xm + xp, prm[0], fma(-x, fma(x, x, prm[1]), u));
+}
+"""
+
 SINE = r"""
 /* extremes of sin over [lo, hi]: -1 / +1 when a trough / crest lies inside */
 REACH_DEVICE real sine_min(real lo, real hi)
