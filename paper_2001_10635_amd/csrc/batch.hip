@@ -1,9 +1,9 @@
 // Many small embedding queries on gfx950: offline batches and online serving.
 //
 // Every query (FP64, n <= 512 cells, scalar input) is run by one wavefront
-// with its whole lower/upper state in registers (E = 1, 2, 4 or 8 cells per
-// lane), all N RK4 steps in one go: no halo, no HBM traffic inside the step
-// loop.  The arithmetic per cell is the same code the large-n embedding kernel
+// with its whole lower/upper state in registers (E = ceil(n / 64) cells per
+// lane, 1..8, spread so that every lane is busy), all N RK4 steps in one go:
+// no halo, no HBM traffic inside the step loop.  The arithmetic per cell is the same code the large-n embedding kernel
 // runs, so a query gives the same box alone, in a batch, or served.
 //
 //   batch_kernel   persistent grid; each wave pops the next work item (a whole
@@ -26,13 +26,146 @@ __device__ __forceinline__ uint64_t wave_bcast(uint64_t v) {
     return ((uint64_t)hi << 32) | lo;
 }
 
+// Balanced layout of a query's n cells over the 64 lanes: E = ceil(n / 64)
+// (1..8), the first F = n - 64 (E - 1) lanes hold E consecutive cells and the
+// others ("short" lanes) E - 1.  For E >= 2 every lane holds cells and the
+// chain's last cell sits in lane 63, so no cell of the window is a ghost and
+// no stage needs a per-cell select: a short lane's last cell is slot E - 2,
+// whose right neighbour (and the value its left neighbour lane reads) is
+// picked once per stage; slot E - 1 of a short lane computes a value nobody
+// reads.  For E = 1 the lanes past cell n-1 are empty and the right neighbour
+// of cell n-1 is set to the ghost.  The arithmetic per cell is the
+// large-chain kernel's, operation for operation, so a query's box is the
+// same alone, batched or served.
+struct Lanes {
+    bool shortl;   // this lane holds E - 1 cells
+    bool end;      // this lane holds cell n-1
+    int cnt;       // cells held
+    int64_t first; // index of the first cell held
+};
+
+template <int E>
+__device__ __forceinline__ Lanes lanes_of(int64_t n) {
+    const int lane = threadIdx.x;
+    const int64_t F = n - (int64_t)WAVE * (E - 1);   // lanes holding E cells
+    Lanes L;
+    L.shortl = lane >= F;
+    L.cnt = L.shortl ? E - 1 : E;
+    L.first = (int64_t)lane * E - (L.shortl ? (int64_t)lane - F : 0);
+    L.end = (E == 1) ? (lane == n - 1) : (lane == WAVE - 1);
+    return L;
+}
+
+// Right neighbour of slot e, given the value shifted in from the next lane.
+template <int E, class T>
+__device__ __forceinline__ T right_of(const T (&in)[E], int e, T rn, bool shortl) {
+    if (e == E - 1) return rn;
+    if (e == E - 2) return shortl ? rn : in[E - 1];
+    return in[e + 1];
+}
+// The value lane l + 1 needs from this lane: its last held cell.
+template <int E, class T>
+__device__ __forceinline__ T last_of(const T (&in)[E], bool shortl) {
+    if constexpr (E == 1) return in[0];
+    else return shortl ? in[E - 2] : in[E - 1];
+}
+
+template <int KIND, int STAGE, int E, int S>
+__device__ __forceinline__ void bal_stage(double (&y)[S][E], double (&acc)[S][E],
+                                          double (&t)[S][E], const SysPrm<double>& P,
+                                          const Inputs<double, E, S, IN_SCALAR>& U,
+                                          const Steps<double>& st, const Lanes& L) {
+    using T = double;
+    T (&in)[S][E] = (STAGE == 1) ? y : t;
+    if constexpr (KIND == K_CTM) {
+        // F_e = min(v y_e, wc - w y_{e+1}, q), k_e = F_{e-1} - F_e; ghost -inf
+        // right of cell n-1 (free outflow), zero flux into cell 0 (lane 0
+        // receives 0 from the shift)
+        const T v = P.a0, w = P.a1, wc = P.a2, q = P.a3;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            T rn = from_right(in[s][0]);
+            rn = L.end ? neg_inf<T>() : rn;
+            T F[E];
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+                F[e] = minT(minT(v * in[s][e], fmaT(-w, right_of<E>(in[s], e, rn, L.shortl), wc)), q);
+            T Fprev = from_left(last_of<E>(F, L.shortl));
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const T k = Fprev - F[e];
+                Fprev = F[e];
+                rk_update<STAGE>(k, y[s][e], acc[s][e], t[s][e], st);
+            }
+        }
+    } else if constexpr (KIND == K_RD) {
+        // k = (y_{e-1} + y_{e+1}) / h^2 + (u - y_e (y_e^2 + 2 / h^2)), ghosts 0
+        const T ih2 = P.a0, two_ih2 = P.a1;
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const T ln = from_left(last_of<E>(in[s], L.shortl));
+            T rn = from_right(in[s][0]);
+            if (E == 1) rn = L.end ? T(0) : rn;
+            T left = ln;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const T mid = in[s][e];
+                const T right = right_of<E>(in[s], e, rn, L.shortl);
+                const T loc = fmaT(-mid, fmaT(mid, mid, two_ih2), U.at(s, e));
+                const T k = fmaT(left + right, ih2, loc);
+                left = mid;
+                rk_update<STAGE>(k, y[s][e], acc[s][e], t[s][e], st);
+            }
+        }
+    } else {
+        // LIN3, both sides (S == 2): the sign split of aL, aR, b
+        const T aL = P.a0, aD = P.a1, aR = P.a2, b = P.a3;
+        const T aLp = aL > T(0) ? aL : T(0), aLn = aL < T(0) ? aL : T(0);
+        const T aRp = aR > T(0) ? aR : T(0), aRn = aR < T(0) ? aR : T(0);
+        const T bp = b > T(0) ? b : T(0), bn = b < T(0) ? b : T(0);
+        T ln[2], rn[2], left[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            ln[s] = from_left(last_of<E>(in[s], L.shortl));
+            rn[s] = from_right(in[s][0]);
+            if (E == 1) rn[s] = L.end ? T(0) : rn[s];
+            left[s] = ln[s];
+        }
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            T mid[2], right[2], k[2];
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                mid[s] = in[s][e];
+                right[s] = right_of<E>(in[s], e, rn[s], L.shortl);
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int o = 1 - s;
+                T acc0 = aD * mid[s];
+                acc0 = fmaT(aLp, left[s], acc0);
+                acc0 = fmaT(aLn, left[o], acc0);
+                acc0 = fmaT(aRp, right[s], acc0);
+                acc0 = fmaT(aRn, right[o], acc0);
+                acc0 = fmaT(bp, U.at(s, e), acc0);
+                k[s] = fmaT(bn, U.at(o, e), acc0);
+            }
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                left[s] = mid[s];
+                rk_update<STAGE>(k[s], y[s][e], acc[s][e], t[s][e], st);
+            }
+        }
+    }
+}
+
 // One query, or one side of it: S = 2 runs both sides in this wave, S = 1
 // only side `side` (cooperative systems, whose sides do not interact).
-template <int KIND, int E, bool MASKED, int S>
+template <int KIND, int E, int S>
 __device__ __noinline__ unsigned run_query_E(const QDesc& d, int side) {
     using T = double;
-    const int lane = threadIdx.x;
     const int64_t n = d.n;
+    const Lanes L = lanes_of<E>(n);
     const double* src[2] = {d.x_lo, d.x_hi};
     double* dst[2] = {d.r_lo, d.r_hi};
     const double* pin[2] = {d.p_lo, d.p_hi};
@@ -42,23 +175,25 @@ __device__ __noinline__ unsigned run_query_E(const QDesc& d, int side) {
     for (int s = 0; s < S; ++s) {
         const int sd = S == 1 ? side : s;
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            const int64_t j = (int64_t)lane * E + e;
-            y[s][e] = (j < n) ? src[sd][j] : ghost<KIND, T>();
-        }
+        for (int e = 0; e < E; ++e)
+            y[s][e] = (e < L.cnt) ? src[sd][L.first + e] : ghost<KIND, T>();
         U.u[s] = pin[sd] ? *pin[sd] : T(0);
     }
     SysPrm<T> P;
     P.a0 = d.prm[0]; P.a1 = d.prm[1]; P.a2 = d.prm[2]; P.a3 = d.prm[3]; P.a4 = d.prm[4];
     const Steps<T> st = {d.h2, d.dt, d.dt6};
-    const int64_t left = n - (int64_t)lane * E;
-    Mask<E, MASKED, true> M{(int)(left < 0 ? 0 : (left > E ? E : left))};
-    rk4_steps<KIND, T, E, S, IN_SCALAR>(y, d.nsteps, P, U, st, M);
+    T acc[S][E], t[S][E];
+    for (int64_t k = 0; k < d.nsteps; ++k) {
+        bal_stage<KIND, 1, E, S>(y, acc, t, P, U, st, L);
+        bal_stage<KIND, 2, E, S>(y, acc, t, P, U, st, L);
+        bal_stage<KIND, 3, E, S>(y, acc, t, P, U, st, L);
+        bal_stage<KIND, 4, E, S>(y, acc, t, P, U, st, L);
+    }
     unsigned bits = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-        const int64_t j = (int64_t)lane * E + e;
-        if (j < n) {
+        if (e < L.cnt) {
+            const int64_t j = L.first + e;
 #pragma unroll
             for (int s = 0; s < S; ++s) {
                 dst[S == 1 ? side : s][j] = y[s][e];
@@ -74,19 +209,17 @@ __device__ __noinline__ unsigned run_query_E(const QDesc& d, int side) {
     return (nf ? (unsigned)ST_NONFINITE : 0u) | (od ? (unsigned)ST_ORDER : 0u);
 }
 
-template <int KIND, int E, int S>
-__device__ __forceinline__ unsigned run_query_k(const QDesc& d, int side) {
-    if (d.n == (int64_t)WAVE * E) return run_query_E<KIND, E, false, S>(d, side);
-    return run_query_E<KIND, E, true, S>(d, side);
-}
-
 template <int KIND, int S>
 __device__ __forceinline__ unsigned run_query_kind(const QDesc& d, int side) {
     switch (d.E) {
-        case 1: return run_query_k<KIND, 1, S>(d, side);
-        case 2: return run_query_k<KIND, 2, S>(d, side);
-        case 4: return run_query_k<KIND, 4, S>(d, side);
-        default: return run_query_k<KIND, 8, S>(d, side);
+        case 1: return run_query_E<KIND, 1, S>(d, side);
+        case 2: return run_query_E<KIND, 2, S>(d, side);
+        case 3: return run_query_E<KIND, 3, S>(d, side);
+        case 4: return run_query_E<KIND, 4, S>(d, side);
+        case 5: return run_query_E<KIND, 5, S>(d, side);
+        case 6: return run_query_E<KIND, 6, S>(d, side);
+        case 7: return run_query_E<KIND, 7, S>(d, side);
+        default: return run_query_E<KIND, 8, S>(d, side);
     }
 }
 

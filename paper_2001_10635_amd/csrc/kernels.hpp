@@ -126,7 +126,7 @@ int mc_max_E(int dtype);
 // Batch / serving descriptor of one FP64 query (n <= 512).
 struct QDesc {
     int32_t kind;
-    int32_t E;          // cells per lane: 1, 2, 4 or 8
+    int32_t E;          // cells per lane: batch_cells_per_lane(n), 1..8
     int64_t n;
     int64_t nsteps;
     double prm[5];
@@ -139,6 +139,9 @@ struct QDesc {
     double* r_hi;
     int64_t tag;        // caller's index (batch) or ticket slot (serving)
 };
+
+// Cells per lane of a batched query: ceil(n / 64) (lanes hold E or E - 1).
+inline int batch_cells_per_lane(int64_t n) { return (int)((n + 63) / 64); }
 
 // Persistent batch worker: `grid` waves pull work items through *counter:
 // whole queries, or with `split` two per query (one per side of a

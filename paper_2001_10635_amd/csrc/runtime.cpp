@@ -969,7 +969,7 @@ reach_status make_desc(reach_ctx* c, const reach_query& q, int64_t tag, QDesc* d
     if (q.sys.n_in == 1 && (!q.p_lo || !q.p_hi)) return fail(c, REACH_E_INVAL, "NULL input pointer");
     std::memset(d, 0, sizeof *d);
     d->kind = q.sys.kind;
-    d->E = ceil_pow2_E(q.sys.n);
+    d->E = batch_cells_per_lane(q.sys.n);
     d->n = q.sys.n;
     d->nsteps = q.nsteps;
     kernel_prm(&q.sys, d->prm);

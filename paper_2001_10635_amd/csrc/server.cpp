@@ -308,9 +308,7 @@ void service(Server* S) {
             QDesc& d = r.d;
             std::memset(&d, 0, sizeof d);
             d.kind = w.q.sys.kind;
-            int E = 1;
-            while (64 * E < n) E *= 2;
-            d.E = E;
+            d.E = batch_cells_per_lane(n);
             d.n = n;
             d.nsteps = w.q.nsteps;
             kernel_params(w.q.sys.kind, w.q.sys.prm, d.prm);
