@@ -2,7 +2,8 @@
 //
 // Each wavefront integrates whole samples: the full n-cell state of one sample
 // lives in the wave's registers (E cells per lane, n <= 64E), so a sample's
-// N RK4 steps touch no memory at all.  Waves are persistent: wave w takes
+// N RK4 steps touch no memory at all.  Waves (four per workgroup, each on its
+// own) are persistent: wave w takes
 // samples s0 + w, s0 + w + nw, ... and folds each final state into its own
 // running min / max kept in the workspace (read-modify-write once per sample,
 // interleaved [w][e][lane] so those accesses are coalesced).  A second kernel
@@ -27,10 +28,16 @@ __device__ __forceinline__ T nan_max(T m, T x) {
     return (m != m) ? m : ((x > m || x != x) ? x : m);
 }
 
+// Waves per workgroup.  Each wave is independent; grouping four makes the
+// dispatcher give a small launch (a few hundred samples) one wave per SIMD
+// instead of stacking single-wave groups on the same SIMDs.
+constexpr int MC_WPB = 4;
+
 template <int KIND, class T, int E, int MODE>
-__global__ __launch_bounds__(64) void mc_kernel(McArgs a) {
-    const int lane = threadIdx.x;
-    const int64_t w = blockIdx.x;
+__global__ __launch_bounds__(WAVE * MC_WPB) void mc_kernel(McArgs a) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t w = (int64_t)blockIdx.x * MC_WPB + (int64_t)(threadIdx.x / WAVE);
+    if (w >= a.nw) return;
     const int64_t n = a.n;
     const bool masked = (int64_t)WAVE * E > n;
     const int64_t left = n - (int64_t)lane * E;
@@ -128,7 +135,7 @@ __global__ __launch_bounds__(64) void mc_kernel(McArgs a) {
 // waves then combine through LDS.  Min and max (NaN-propagating) are exact,
 // so the split changes no value (signed zeros aside).
 constexpr int RED_WAVES = 16;
-constexpr int RED_UNROLL = 8;
+constexpr int RED_UNROLL = 16;
 
 template <class T, int E>
 __global__ __launch_bounds__(WAVE * RED_WAVES) void mc_reduce_kernel(
@@ -140,12 +147,12 @@ __global__ __launch_bounds__(WAVE * RED_WAVES) void mc_reduce_kernel(
     const int wv = threadIdx.x / WAVE;
     const size_t off = (size_t)blockIdx.x * WAVE + (size_t)lane;
     const size_t stride = (size_t)E * WAVE;
-    // every wave owns at least one partial when nw >= RED_WAVES; otherwise the
-    // waves without one contribute partial 0 again (min/max are idempotent)
+    // Partial indices past nw are replaced by the wave's first one (min and
+    // max are idempotent), which exists for every wave when nw >= RED_WAVES
+    // and is partial 0 otherwise.
     const int64_t w_first = wv < nw ? wv : 0;
-    T mn = pmin[(size_t)w_first * stride + off];
-    T mx = pmax[(size_t)w_first * stride + off];
-    for (int64_t w0 = w_first + RED_WAVES; w0 < nw; w0 += (int64_t)RED_WAVES * RED_UNROLL) {
+    T mn, mx;
+    for (int64_t w0 = wv; w0 < nw || w0 == wv; w0 += (int64_t)RED_WAVES * RED_UNROLL) {
         T a[RED_UNROLL], b[RED_UNROLL];
 #pragma unroll
         for (int u = 0; u < RED_UNROLL; ++u) {
@@ -153,6 +160,10 @@ __global__ __launch_bounds__(WAVE * RED_WAVES) void mc_reduce_kernel(
             const size_t idx = (size_t)(w < nw ? w : w_first) * stride + off;
             a[u] = pmin[idx];
             b[u] = pmax[idx];
+        }
+        if (w0 == wv) {
+            mn = a[0];
+            mx = b[0];
         }
 #pragma unroll
         for (int u = 0; u < RED_UNROLL; ++u) {
@@ -183,7 +194,8 @@ __global__ __launch_bounds__(WAVE * RED_WAVES) void mc_reduce_kernel(
 
 template <int KIND, class T, int E, int MODE>
 static hipError_t go(const McArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((mc_kernel<KIND, T, E, MODE>), dim3((unsigned)a.nw), dim3(WAVE), 0, s, a);
+    const unsigned grid = (unsigned)((a.nw + MC_WPB - 1) / MC_WPB);
+    hipLaunchKernelGGL((mc_kernel<KIND, T, E, MODE>), dim3(grid), dim3(WAVE * MC_WPB), 0, s, a);
     return hipGetLastError();
 }
 
