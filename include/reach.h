@@ -153,7 +153,7 @@ const char* reach_last_error(const reach_ctx* ctx);
      "heat.P"     rows per wavefront of the 3-D heat kernel: 2, 3, 4, 5 or 8
                   (with 16, 12, 8, 8 or 4 wavefronts per block; FP64 builds 2, 3,
                   4 and 5, FP32 2, 3, 4 and 8; 0 = tuned default)
-     "mc.waves"   resident waves of the Monte Carlo kernel (0 = default)
+     "mc.waves"   resident waves of the Monte Carlo kernel (0 = default, at most 4096)
      "batch.waves" resident waves of the batch kernel (0 = default)
      "batch.split" 1: one wave per side of each cooperative query (shorter
                   latency per query); 0 (default): one wave per query

@@ -116,8 +116,11 @@ struct McArgs {
     double h2, dt, dt6;
 };
 hipError_t launch_mc(int kind, int mode, int dtype, int E, const McArgs& a, hipStream_t stream);
-// r_min / r_max [n] from the partials of `nw` waves; reports non-finite.
-hipError_t launch_mc_reduce(int dtype, int E, const void* part_min, const void* part_max,
+// r_min / r_max [n] from the partials of `nw` <= kMcMaxWaves waves (the
+// partials are overwritten: chunk results are written in place); reports
+// non-finite values.
+constexpr int64_t kMcMaxWaves = 4096;
+hipError_t launch_mc_reduce(int dtype, int E, void* part_min, void* part_max,
                             int64_t nw, int64_t n, void* r_min, void* r_max,
                             unsigned int* status, hipStream_t stream);
 bool mc_has_E(int dtype, int E);

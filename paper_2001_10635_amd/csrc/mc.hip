@@ -128,48 +128,45 @@ __global__ __launch_bounds__(WAVE * MC_WPB) void mc_kernel(McArgs a) {
     }
 }
 
-// Reduction of the nw per-wave partials.  Block e (one of E) owns the 64
-// partial slots [w][e][0..63], i.e. cells j = lane * E + e.  Its RED_WAVES
-// waves split the w range round-robin, each issuing RED_UNROLL independent
-// loads per round so the latency of one round covers RED_UNROLL partials; the
-// waves then combine through LDS.  Min and max (NaN-propagating) are exact,
-// so the split changes no value (signed zeros aside).
+// Reduction of the nw per-wave partials, in two launches when nw > RED_CHUNK.
+// Block (e, g) owns the 64 partial slots [w][e][0..63] (cells j = lane * E + e)
+// of partials w in [g RED_CHUNK, (g + 1) RED_CHUNK): its RED_WAVES waves issue
+// RED_CHUNK / RED_WAVES independent loads each, then combine through LDS.  The
+// first launch writes each chunk's result over the chunk's first partial; the
+// second (wstep = RED_CHUNK) reduces those and writes the box.  Min and max
+// (NaN-propagating) are exact, so the split changes no value (signed zeros
+// aside), and every block reads only its own chunk.
 constexpr int RED_WAVES = 16;
-constexpr int RED_UNROLL = 16;
+constexpr int RED_CHUNK = 64;
+constexpr int RED_PER_WAVE = RED_CHUNK / RED_WAVES;
 
 template <class T, int E>
 __global__ __launch_bounds__(WAVE * RED_WAVES) void mc_reduce_kernel(
-    const T* __restrict__ pmin, const T* __restrict__ pmax, int64_t nw, int64_t n,
-    T* __restrict__ rmin, T* __restrict__ rmax, unsigned int* status) {
+    T* __restrict__ pmin, T* __restrict__ pmax, int64_t nw, int64_t wstep, int64_t n,
+    T* __restrict__ rmin, T* __restrict__ rmax, unsigned int* status, int final_pass) {
     __shared__ T smin[RED_WAVES][WAVE];
     __shared__ T smax[RED_WAVES][WAVE];
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
     const size_t off = (size_t)blockIdx.x * WAVE + (size_t)lane;
     const size_t stride = (size_t)E * WAVE;
-    // Partial indices past nw are replaced by the wave's first one (min and
-    // max are idempotent), which exists for every wave when nw >= RED_WAVES
-    // and is partial 0 otherwise.
-    const int64_t w_first = wv < nw ? wv : 0;
-    T mn, mx;
-    for (int64_t w0 = wv; w0 < nw || w0 == wv; w0 += (int64_t)RED_WAVES * RED_UNROLL) {
-        T a[RED_UNROLL], b[RED_UNROLL];
+    const int64_t w0 = (int64_t)blockIdx.y * RED_CHUNK;
+    const int64_t w1 = w0 + RED_CHUNK < nw ? w0 + RED_CHUNK : nw;
+    // indices past the chunk read the chunk's first partial again (min and
+    // max are idempotent)
+    T a[RED_PER_WAVE], b[RED_PER_WAVE];
 #pragma unroll
-        for (int u = 0; u < RED_UNROLL; ++u) {
-            const int64_t w = w0 + (int64_t)u * RED_WAVES;
-            const size_t idx = (size_t)(w < nw ? w : w_first) * stride + off;
-            a[u] = pmin[idx];
-            b[u] = pmax[idx];
-        }
-        if (w0 == wv) {
-            mn = a[0];
-            mx = b[0];
-        }
+    for (int u = 0; u < RED_PER_WAVE; ++u) {
+        const int64_t w = w0 + wv + (int64_t)u * RED_WAVES;
+        const size_t idx = (size_t)((w < w1 ? w : w0) * wstep) * stride + off;
+        a[u] = pmin[idx];
+        b[u] = pmax[idx];
+    }
+    T mn = a[0], mx = b[0];
 #pragma unroll
-        for (int u = 0; u < RED_UNROLL; ++u) {
-            mn = nan_min(mn, a[u]);
-            mx = nan_max(mx, b[u]);
-        }
+    for (int u = 1; u < RED_PER_WAVE; ++u) {
+        mn = nan_min(mn, a[u]);
+        mx = nan_max(mx, b[u]);
     }
     smin[wv][lane] = mn;
     smax[wv][lane] = mx;
@@ -181,6 +178,12 @@ __global__ __launch_bounds__(WAVE * RED_WAVES) void mc_reduce_kernel(
     for (int k = 1; k < RED_WAVES; ++k) {
         mn = nan_min(mn, smin[k][lane]);
         mx = nan_max(mx, smax[k][lane]);
+    }
+    if (!final_pass) {
+        const size_t idx = (size_t)(w0 * wstep) * stride + off;
+        pmin[idx] = mn;
+        pmax[idx] = mx;
+        return;
     }
     const int64_t j = (int64_t)lane * E + blockIdx.x;
     unsigned bits = 0;
@@ -237,23 +240,42 @@ hipError_t launch_mc(int kind, int mode, int dtype, int E, const McArgs& a, hipS
     return hipErrorInvalidValue;
 }
 
-template <class T>
-static hipError_t reduce_T(int E, const void* pmin, const void* pmax, int64_t nw, int64_t n,
-                           void* rmin, void* rmax, unsigned int* status, hipStream_t s) {
-#define REACH_RED(EE)                                                                            \
-    case EE:                                                                                     \
-        hipLaunchKernelGGL((mc_reduce_kernel<T, EE>), dim3(EE), dim3(WAVE * RED_WAVES), 0, s,    \
-                           (const T*)pmin, (const T*)pmax, nw, n, (T*)rmin, (T*)rmax, status);  \
-        return hipGetLastError();
-    switch (E) {
-        REACH_RED(1) REACH_RED(2) REACH_RED(4) REACH_RED(8) REACH_RED(16) REACH_RED(32)
-        REACH_RED(64)
-        default: return hipErrorInvalidValue;
+template <class T, int E>
+static hipError_t reduce_E(void* pmin, void* pmax, int64_t nw, int64_t n, void* rmin, void* rmax,
+                           unsigned int* status, hipStream_t s) {
+    const dim3 block(WAVE * RED_WAVES);
+    const int64_t chunks = (nw + RED_CHUNK - 1) / RED_CHUNK;
+    if (chunks > 1) {
+        hipLaunchKernelGGL((mc_reduce_kernel<T, E>), dim3(E, (unsigned)chunks), block, 0, s,
+                           (T*)pmin, (T*)pmax, nw, (int64_t)1, n, (T*)rmin, (T*)rmax, status, 0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        static_assert(RED_CHUNK * RED_CHUNK >= kMcMaxWaves, "two passes cover every wave count");
+        hipLaunchKernelGGL((mc_reduce_kernel<T, E>), dim3(E, 1), block, 0, s, (T*)pmin, (T*)pmax,
+                           chunks, (int64_t)RED_CHUNK, n, (T*)rmin, (T*)rmax, status, 1);
+    } else {
+        hipLaunchKernelGGL((mc_reduce_kernel<T, E>), dim3(E, 1), block, 0, s, (T*)pmin, (T*)pmax,
+                           nw, (int64_t)1, n, (T*)rmin, (T*)rmax, status, 1);
     }
-#undef REACH_RED
+    return hipGetLastError();
 }
 
-hipError_t launch_mc_reduce(int dtype, int E, const void* pmin, const void* pmax, int64_t nw,
+template <class T>
+static hipError_t reduce_T(int E, void* pmin, void* pmax, int64_t nw, int64_t n, void* rmin,
+                           void* rmax, unsigned int* status, hipStream_t s) {
+    switch (E) {
+        case 1: return reduce_E<T, 1>(pmin, pmax, nw, n, rmin, rmax, status, s);
+        case 2: return reduce_E<T, 2>(pmin, pmax, nw, n, rmin, rmax, status, s);
+        case 4: return reduce_E<T, 4>(pmin, pmax, nw, n, rmin, rmax, status, s);
+        case 8: return reduce_E<T, 8>(pmin, pmax, nw, n, rmin, rmax, status, s);
+        case 16: return reduce_E<T, 16>(pmin, pmax, nw, n, rmin, rmax, status, s);
+        case 32: return reduce_E<T, 32>(pmin, pmax, nw, n, rmin, rmax, status, s);
+        case 64: return reduce_E<T, 64>(pmin, pmax, nw, n, rmin, rmax, status, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_mc_reduce(int dtype, int E, void* pmin, void* pmax, int64_t nw,
                             int64_t n, void* rmin, void* rmax, unsigned int* status,
                             hipStream_t s) {
     return dtype == 0 ? reduce_T<double>(E, pmin, pmax, nw, n, rmin, rmax, status, s)

@@ -454,7 +454,7 @@ int mc_E(int dtype, int64_t n) {
 int64_t mc_waves(const reach_ctx* c, int64_t m) {
     int64_t w = opt_get(c, "mc.waves");
     if (w <= 0) w = (int64_t)c->cus * 8;
-    return std::max<int64_t>(1, std::min<int64_t>(w, m));
+    return std::max<int64_t>(1, std::min<int64_t>(std::min(w, kMcMaxWaves), m));
 }
 
 size_t mc_ws_bytes(const reach_ctx* c, const reach_system* s, reach_dtype dtype, int64_t m) {

@@ -576,7 +576,7 @@ static int user_mc_E(int64_t n) {
 static int64_t user_mc_waves(const reach_ctx* c, int64_t m) {
     int64_t w = rt::option(c, "mc.waves");
     if (w <= 0) w = (int64_t)rt::ctx_cus(c) * 8;
-    return std::max<int64_t>(1, std::min<int64_t>(w, m));
+    return std::max<int64_t>(1, std::min<int64_t>(std::min(w, kMcMaxWaves), m));
 }
 
 size_t reach_user_workspace_bytes(reach_ctx* c, const reach_system* s, reach_dtype dtype,

@@ -88,10 +88,24 @@ def test_mc_sample_ranges_compose_bitwise(rc):
 def test_mc_wave_count_invariance_bitwise(rc):
     case = make_case("ctm", 200, np.float32, seed=8)
     outs = []
-    for waves in (1, 7, 64, 0):
+    for waves in (1, 7, 64, 65, 0):
         rc.set_option("mc.waves", waves)
         say(f"mc waves={waves}")
         outs.append(run_mc(rc, *case, 25, 300, 9)[:2])
+    rc.set_option("mc.waves", 0)
+    for o in outs[1:]:
+        assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
+
+
+def test_mc_two_pass_reduction_at_the_wave_cap_bitwise(rc):
+    """4096 waves (64 chunks of 64 partials, reduced in two passes) and 100
+    waves give the same box; a wave count above the cap is clamped."""
+    case = make_case("rd", 130, np.float64, seed=12)
+    outs = []
+    for waves in (100, 4096, 10000):
+        rc.set_option("mc.waves", waves)
+        say(f"mc waves={waves} m=5000")
+        outs.append(run_mc(rc, *case, 10, 5000, 13)[:2])
     rc.set_option("mc.waves", 0)
     for o in outs[1:]:
         assert np.array_equal(o[0], outs[0][0]) and np.array_equal(o[1], outs[0][1])
