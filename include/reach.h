@@ -136,7 +136,11 @@ typedef struct reach_ctx reach_ctx;
 /* ------------------------------------------------------------ context -- */
 
 /* Create a context on HIP device `device` (made current for the call).
-   Allocates the context's status words on that device. */
+   Allocates the context's status words on that device.  With the environment
+   variable REACH_LOG set (and not "0") when the context is created, every
+   embedding, Monte Carlo, growth-bound and batch call on it writes one line
+   "reach: {...}" to stderr: a JSON object with the call, system kind, dtype,
+   sizes and the launch plan (tile shape, tiles, passes, waves). */
 reach_status reach_ctx_create(int device, reach_ctx** out);
 
 /* Destroy a context (stops a running server first).  NULL is a no-op. */

@@ -72,6 +72,7 @@ struct reach_ctx {
     hipEvent_t staging_ev = nullptr;
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::vector<hipStream_t> each_streams;
+    bool log = false;                    // REACH_LOG: one JSON line per call on stderr
 };
 
 namespace {
@@ -85,6 +86,19 @@ reach_status fail(reach_ctx* c, reach_status st, const char* fmt, ...) {
     if (c) c->err = buf;
     return st;
 }
+
+// One "reach: {...}" line on stderr when the context logs (REACH_LOG).
+void log_call(const reach_ctx* c, const char* fmt, ...) {
+    if (!c || !c->log) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "reach: {%s}\n", buf);
+}
+
+const char* dtype_name(reach_dtype d) { return d == REACH_F64 ? "f64" : "f32"; }
 
 reach_status hip_fail(reach_ctx* c, hipError_t e, const char* what) {
     return fail(c, REACH_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
@@ -304,6 +318,10 @@ reach_status embed_heat3d(reach_ctx* c, const reach_system* s, reach_dtype dtype
     HeatPlan hp;
     reach_status st = plan_heat(c, s, dtype, &hp);
     if (st != REACH_OK) return st;
+    log_call(c, "\"call\": \"embed\", \"kind\": %d, \"dtype\": \"%s\", \"n\": %lld, "
+                "\"nsteps\": %lld, \"rows_per_wave\": %d, \"tiles\": %lld, \"passes\": %lld",
+             s->kind, dtype_name(dtype), (long long)s->n, (long long)nsteps, hp.P,
+             (long long)(2 * hp.TX * hp.TY), (long long)nsteps);
     const size_t bytes = (size_t)s->n * dsize(dtype);
     const bool alias = (r_lo == x_lo) || (r_hi == x_hi) || (r_lo == x_hi) || (r_hi == x_lo);
     const int64_t passes = nsteps;   // one RK4 step per pass
@@ -359,6 +377,10 @@ reach_status gb_heat3d(reach_ctx* c, const reach_system* s, reach_dtype dtype, c
     HeatPlan hp;
     reach_status st = plan_heat(c, s, dtype, &hp);
     if (st != REACH_OK) return st;
+    log_call(c, "\"call\": \"growth_bound\", \"kind\": %d, \"dtype\": \"%s\", \"n\": %lld, "
+                "\"nsteps\": %lld, \"rows_per_wave\": %d, \"tiles\": %lld, \"passes\": %lld",
+             s->kind, dtype_name(dtype), (long long)s->n, (long long)nsteps, hp.P,
+             (long long)(2 * hp.TX * hp.TY), (long long)nsteps);
     const size_t bytes = (size_t)s->n * dsize(dtype);
     const int dt_id = dtype == REACH_F64 ? 0 : 1;
     char* A = (char*)ws;
@@ -516,6 +538,7 @@ reach_status reach_ctx_create(int device, reach_ctx** out) {
         if (colon != std::string::npos) c->arch.resize(colon);
     }
     load_tune_cache(c);
+    if (const char* e = std::getenv("REACH_LOG")) c->log = e[0] && std::strcmp(e, "0") != 0;
     if (hipMalloc((void**)&c->status, 256) != hipSuccess) { delete c; return REACH_E_DEVICE; }
     if (hipMemset(c->status, 0, 256) != hipSuccess) { hipFree(c->status); delete c; return REACH_E_DEVICE; }
     if (hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming) != hipSuccess) {
@@ -631,6 +654,11 @@ reach_status reach_embed_rk4(reach_ctx* c, const reach_system* s, reach_dtype dt
     EmbedPlan pl;
     st = plan_embed(c, s, dtype, nsteps, &pl);
     if (st != REACH_OK) return st;
+    log_call(c, "\"call\": \"embed\", \"kind\": %d, \"dtype\": \"%s\", \"n\": %lld, "
+                "\"nsteps\": %lld, \"E\": %d, \"K\": %d, \"S\": %d, \"tiles\": %lld, "
+                "\"passes\": %lld",
+             s->kind, dtype_name(dtype), (long long)s->n, (long long)nsteps, pl.E, pl.K, pl.S,
+             (long long)(pl.S == 1 ? 2 * pl.W : pl.W), (long long)pl.passes);
 
     // buffers: the last pass writes r; multi-tile passes never run in place
     const bool alias = (r_lo == x_lo) || (r_hi == x_hi) || (r_lo == x_hi) || (r_hi == x_lo);
@@ -852,6 +880,10 @@ reach_status reach_montecarlo_range(reach_ctx* c, const reach_system* s, reach_d
     const int mode = s->n_in > 1 ? 1 : 0;
     const int dt_id = dtype == REACH_F64 ? 0 : 1;
     hipStream_t hs = (hipStream_t)stream;
+    log_call(c, "\"call\": \"montecarlo\", \"kind\": %d, \"dtype\": \"%s\", \"n\": %lld, "
+                "\"nsteps\": %lld, \"s0\": %lld, \"m\": %lld, \"E\": %d, \"waves\": %lld",
+             s->kind, dtype_name(dtype), (long long)s->n, (long long)nsteps, (long long)s0,
+             (long long)m, E, (long long)a.nw);
     hipError_t e = launch_mc(s->kind, mode, dt_id, E, a, hs);
     if (e != hipSuccess) return hip_fail(c, e, "Monte Carlo kernel launch");
     e = launch_mc_reduce(dt_id, E, a.part_min, a.part_max, a.nw, s->n, r_min, r_max, c->status, hs);
@@ -960,6 +992,10 @@ reach_status reach_growth_bound(reach_ctx* c, const reach_system* s, reach_dtype
     }
     a.per_xcd = (int32_t)((2 * a.W + 7) / 8);
     const int64_t grid = 8 * (int64_t)a.per_xcd;
+    log_call(c, "\"call\": \"growth_bound\", \"kind\": %d, \"dtype\": \"%s\", \"n\": %lld, "
+                "\"nsteps\": %lld, \"E\": %d, \"K\": %d, \"tiles\": %lld, \"passes\": %lld",
+             s->kind, dtype_name(dtype), (long long)n, (long long)nsteps, E, K,
+             (long long)(2 * a.W), (long long)passes);
     // (c, r) ping-pong in the workspace; the last pass writes buffer A
     char* A = (char*)ws;
     char* B = (char*)ws + 2 * bytes;
@@ -1145,6 +1181,9 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     if (grid <= 0) grid = (int64_t)c->cus * 8;
     grid = std::min<int64_t>(grid, split ? 2 * nq : nq);
 
+    log_call(c, "\"call\": \"batch\", \"queries\": %lld, \"waves\": %lld, \"split\": %d, "
+                "\"host_threads\": %d",
+             (long long)nq, (long long)grid, split, nth);
     auto enqueue = [&](hipStream_t s) -> hipError_t {
         hipError_t e = launch_zero(base, (int64_t)(align256(8) + 2 * align256(4 * (size_t)nq)) / 4, s);
         if (e != hipSuccess) return e;

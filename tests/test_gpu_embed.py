@@ -349,3 +349,29 @@ def test_horizon_t1_equals_step_count(rc):
     with pytest.raises(ValueError):
         rc.embed(kind, prm, to_dev(lo), to_dev(hi), dt, p_lo=to_dev(pl), p_hi=to_dev(ph),
                  t0=0.0, t1=0.123 * dt + dt)
+
+
+def test_reach_log_writes_one_json_record_per_call(capfd, monkeypatch):
+    """REACH_LOG: a context created with it set writes the call and its launch
+    plan as one JSON line on stderr per call."""
+    import json
+    monkeypatch.setenv("REACH_LOG", "1")
+    r = R.Reach(0)
+    try:
+        kind, prm, lo, hi, pl, ph, dt = make_case("rd", 5000, np.float64, seed=31)
+        say("REACH_LOG embed + montecarlo")
+        capfd.readouterr()
+        r.embed(kind, prm, to_dev(lo), to_dev(hi), dt, 30, p_lo=to_dev(pl), p_hi=to_dev(ph))
+        r.montecarlo(kind, prm, to_dev(lo[:300]), to_dev(hi[:300]), dt, 5, 40, 3,
+                     p_lo=to_dev(pl[:300]), p_hi=to_dev(ph[:300]))
+        assert r.sync() == R.REACH_OK
+        err = capfd.readouterr().err
+        plan = R.reach_plan_embed(r.ctx, R.make_system(kind, 5000, prm, pl.size), R.REACH_F64, 30)
+    finally:
+        r.close()
+    recs = [json.loads(l[len("reach: "):]) for l in err.splitlines() if l.startswith("reach: {")]
+    assert [x["call"] for x in recs] == ["embed", "montecarlo"]
+    e, m = recs
+    assert (e["n"], e["nsteps"], e["dtype"], e["kind"]) == (5000, 30, "f64", kind)
+    assert (e["E"], e["K"], e["S"], e["passes"]) == (plan["E"], plan["K"], plan["S"], plan["passes"])
+    assert (m["n"], m["m"], m["nsteps"]) == (300, 40, 5) and m["waves"] == 40
