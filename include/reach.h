@@ -303,8 +303,10 @@ int64_t reach_mc_samples(int64_t n, double eps, double delta);
 
 /* --------------------------------------------------------------- batch --
  * Many small embeddings (n <= 512, FP64, n_in 0 or 1) in one persistent
- * kernel: each wave takes the next query from a device work counter
- * (longest first) and integrates it with its whole state in registers.
+ * kernel: each wave takes the next work item from a device work counter
+ * (longest first; the schedule is reach_plan_batch's) and integrates it with
+ * its whole state in registers.  A work item is one query, or a pack of
+ * short cooperative queries sharing a wave (one cell per lane).
  * `q` is a HOST array of nq queries whose pointers are device pointers; it is
  * read during the call only.  workspace: reach_batch_workspace_bytes(nq)
  * bytes of device memory.  Results are identical to nq separate
@@ -315,6 +317,24 @@ int64_t reach_mc_samples(int64_t n, double eps, double delta);
  * REACH_F32 or per-cell inputs, REACH_E_NOMEM for a short workspace.
  */
 size_t reach_batch_workspace_bytes(int64_t nq);
+
+/* The schedule reach_embed_rk4_batch launches for these queries, computed on
+ * the host only (no device call; the query pointers are not dereferenced).
+ * Short cooperative queries (CTM or RD, n <= 32) with the same parameters, dt
+ * and step count are packed up to 16 to a wavefront, at most 64 cells in all,
+ * one cell per lane; every other query runs alone.  Items come longest first
+ * (wave time E * nsteps with E = ceil(n / 64), a pack counting as E = 1).
+ * On return *n_items holds the item count and item k runs the queries
+ * member[item_start[k] .. item_start[k] + item_count[k]) (indices into q);
+ * item_start, item_count and member are host arrays of nq entries.  ctx may
+ * be NULL (then packing is on, as with the default options, and errors carry
+ * no message); with a context its "batch.split" option turns packing off as
+ * it does for the batch.
+ * Errors: those of reach_embed_rk4_batch's query checks, REACH_E_INVAL for
+ * NULL arrays. */
+reach_status reach_plan_batch(reach_ctx* ctx, const reach_query* q, int64_t nq,
+                              int64_t* item_start, int32_t* item_count, int64_t* member,
+                              int64_t* n_items);
 reach_status reach_embed_rk4_batch(reach_ctx* ctx, const reach_query* q, int64_t nq,
                                    void* workspace, size_t workspace_bytes, void* stream);
 

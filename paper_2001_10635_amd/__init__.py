@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
         "reach_growth_bound": ([vp, sysp, i32, vp, vp, vp, vp, d, d, i64, vp, vp, vp, sz, vp], i32),
         "reach_batch_workspace_bytes": ([i64], sz),
         "reach_embed_rk4_batch": ([vp, qp, i64, vp, sz, vp], i32),
+        "reach_plan_batch": ([vp, qp, i64, P(i64), P(i32), P(i64), P(i64)], i32),
         "reach_embed_rk4_each": ([vp, qp, i64, i32], i32),
         "reach_server_start": ([vp, vp, sz, i32, vp], i32),
         "reach_submit": ([vp, qp, P(u64)], i32),
@@ -356,6 +357,24 @@ def reach_mc_samples(n: int, eps: float, delta: float) -> int:
 
 def reach_batch_workspace_bytes(nq: int) -> int:
     return int(lib().reach_batch_workspace_bytes(int(nq)))
+
+
+def reach_plan_batch(ctx, queries) -> list:
+    """The batch's work items in launch order, each a list of query indices
+    (more than one: a pack sharing a wavefront).  Host only; ctx may be None."""
+    arr = query_array(queries)
+    nq = len(queries)
+    start = (ctypes.c_int64 * max(nq, 1))()
+    count = (ctypes.c_int32 * max(nq, 1))()
+    member = (ctypes.c_int64 * max(nq, 1))()
+    ni = ctypes.c_int64(0)
+    st = lib().reach_plan_batch(ctx, arr, nq, start, count, member, ctypes.byref(ni))
+    if ctx is None:
+        if st != REACH_OK:
+            raise ReachError(st, "reach_plan_batch")
+    else:
+        _chk(ctx, st, "reach_plan_batch")
+    return [[int(member[start[k] + m]) for m in range(count[k])] for k in range(ni.value)]
 
 
 def query_array(queries):

@@ -223,6 +223,110 @@ __device__ __forceinline__ unsigned run_query_kind(const QDesc& d, int side) {
     }
 }
 
+// Packed short queries: up to kPackMax cooperative queries (CTM or RD) of at
+// most kPackMaxN cells with the same system constants and dt share one wave,
+// query m on a contiguous segment of n_m lanes (one cell per lane, both
+// sides).  A segment's first lane takes the left boundary value (ghost 0;
+// zero inflow for the CTM) and its last lane the right ghost (0; -inf, free
+// outflow, for the CTM) instead of the neighbouring segment's values; the
+// wave runs the longest member's step count and a member's lanes keep their
+// state once its own steps are done.  Per cell this is the arithmetic of the
+// single-query path, so the results are bitwise those of the query run alone.
+template <int KIND, int STAGE>
+__device__ __forceinline__ void pack_stage(double (&y)[2], double (&acc)[2], double (&t)[2],
+                                           const SysPrm<double>& P, const double (&u)[2],
+                                           const Steps<double>& st, bool first, bool last,
+                                           bool live) {
+    using T = double;
+    T (&in)[2] = (STAGE == 1) ? y : t;
+    if constexpr (KIND == K_CTM) {
+        const T v = P.a0, w = P.a1, wc = P.a2, q = P.a3;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            T rn = from_right(in[s]);
+            rn = last ? neg_inf<T>() : rn;
+            const T F = minT(minT(v * in[s], fmaT(-w, rn, wc)), q);
+            T Fprev = from_left(F);
+            Fprev = first ? T(0) : Fprev;
+            const T y0 = y[s];
+            rk_update<STAGE>(Fprev - F, y[s], acc[s], t[s], st);
+            if (STAGE == 4) y[s] = live ? y[s] : y0;
+        }
+    } else {
+        const T ih2 = P.a0, two_ih2 = P.a1;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            T ln = from_left(in[s]);
+            ln = first ? T(0) : ln;
+            T rn = from_right(in[s]);
+            rn = last ? T(0) : rn;
+            const T mid = in[s];
+            const T loc = fmaT(-mid, fmaT(mid, mid, two_ih2), u[s]);
+            const T y0 = y[s];
+            rk_update<STAGE>(fmaT(ln + rn, ih2, loc), y[s], acc[s], t[s], st);
+            if (STAGE == 4) y[s] = live ? y[s] : y0;
+        }
+    }
+}
+
+template <int KIND>
+__device__ __noinline__ void run_pack(const QDesc* __restrict__ desc,
+                                      const uint32_t* __restrict__ mem_idx, int count,
+                                      unsigned int* qflags, unsigned int* status) {
+    using T = double;
+    const int lane = threadIdx.x;
+    const QDesc* d = desc + mem_idx[0];
+    int mem = -1;
+    int64_t c = 0;
+    int off = 0;
+    int64_t steps = 0;   // the longest member's
+    for (int m = 0; m < count; ++m) {
+        const QDesc* dm = desc + mem_idx[m];
+        const int nm = (int)dm->n;
+        if (lane >= off && lane < off + nm) {
+            mem = m;
+            c = lane - off;
+        }
+        off += nm;
+        steps = dm->nsteps > steps ? dm->nsteps : steps;
+    }
+    const bool valid = mem >= 0;
+    const QDesc* me = desc + mem_idx[valid ? mem : 0];
+    const int64_t n = me->n;
+    const bool first = valid && c == 0;
+    const bool last = valid && c == n - 1;
+    T y[2], u[2], acc[2], t[2];
+    const double* src[2] = {me->x_lo, me->x_hi};
+    const double* pin[2] = {me->p_lo, me->p_hi};
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+        y[s] = valid ? src[s][c] : ghost<KIND, T>();
+        u[s] = (valid && pin[s]) ? *pin[s] : T(0);
+    }
+    SysPrm<T> P;
+    P.a0 = d->prm[0]; P.a1 = d->prm[1]; P.a2 = d->prm[2]; P.a3 = d->prm[3]; P.a4 = d->prm[4];
+    const Steps<T> st = {d->h2, d->dt, d->dt6};
+    const int64_t my_steps = me->nsteps;
+    for (int64_t k = 0; k < steps; ++k) {
+        const bool live = k < my_steps;
+        pack_stage<KIND, 1>(y, acc, t, P, u, st, first, last, live);
+        pack_stage<KIND, 2>(y, acc, t, P, u, st, first, last, live);
+        pack_stage<KIND, 3>(y, acc, t, P, u, st, first, last, live);
+        pack_stage<KIND, 4>(y, acc, t, P, u, st, first, last, live);
+    }
+    if (valid) {
+        me->r_lo[c] = y[0];
+        me->r_hi[c] = y[1];
+        unsigned bits = 0;
+        if (!finiteT(y[0]) || !finiteT(y[1])) bits |= ST_NONFINITE;
+        if (y[0] > y[1]) bits |= ST_ORDER;
+        if (bits) {
+            atomicOr(&qflags[me->tag], bits);
+            atomicOr(status, bits);
+        }
+    }
+}
+
 // Whole query in one wave (descriptor fields are wave-uniform; the host
 // validated kind and E).
 __device__ __forceinline__ unsigned run_query(const QDesc& d) {
@@ -252,20 +356,34 @@ __device__ __forceinline__ unsigned order_bits(const QDesc& d) {
     return __ballot(bits) ? (unsigned)ST_ORDER : 0u;
 }
 
-__global__ __launch_bounds__(64) void batch_kernel(const QDesc* __restrict__ desc, int64_t nq,
+__global__ __launch_bounds__(64) void batch_kernel(const QDesc* __restrict__ desc,
+                                                   const BatchItem* __restrict__ items,
+                                                   const uint32_t* __restrict__ members,
+                                                   const uint64_t* n_items,
                                                    unsigned long long* counter,
                                                    unsigned int* qflags, unsigned int* pair,
                                                    unsigned int* status, int split) {
     const int lane = threadIdx.x;
-    const uint64_t items = split ? 2 * (uint64_t)nq : (uint64_t)nq;
+    const uint64_t ni = wave_bcast(*n_items);
+    const uint64_t total = split ? 2 * ni : ni;
     for (;;) {
         uint64_t u = 0;
         if (lane == 0) u = atomicAdd(counter, 1ULL);
         u = wave_bcast(u);
-        if (u >= items) break;
+        if (u >= total) break;
         if (!split) {
-            // whole queries: both sides in one wave (most work per wave)
-            const QDesc d = desc[u];
+            // whole queries (both sides in one wave, most work per wave) or a
+            // pack of short ones
+            const BatchItem it = items[u];
+            if (it.count > 1) {
+                const int kind = desc[members[it.start]].kind;
+                if (kind == K_CTM)
+                    run_pack<K_CTM>(desc, members + it.start, (int)it.count, qflags, status);
+                else
+                    run_pack<K_RD>(desc, members + it.start, (int)it.count, qflags, status);
+                continue;
+            }
+            const QDesc d = desc[members[it.start]];
             const unsigned bits = run_query(d);
             if (lane == 0 && bits) {
                 atomicOr(&qflags[d.tag], bits);
@@ -273,9 +391,10 @@ __global__ __launch_bounds__(64) void batch_kernel(const QDesc* __restrict__ des
             }
             continue;
         }
+        // one side of item i (items are single queries when split)
         const uint64_t i = u >> 1;
         const int side = (int)(u & 1);
-        const QDesc d = desc[i];
+        const QDesc d = desc[members[items[i].start]];
         if (item_is_empty(d, side)) continue;
         unsigned bits = run_item(d, side);
         if (!item_is_whole(d)) {
@@ -364,11 +483,12 @@ __global__ __launch_bounds__(64) void serve_kernel(ServeSlot* ring, int32_t slot
     }
 }
 
-hipError_t launch_batch(const QDesc* d, int64_t nq, unsigned long long* counter,
+hipError_t launch_batch(const QDesc* d, const BatchItem* items, const uint32_t* members,
+                        const uint64_t* n_items, unsigned long long* counter,
                         unsigned int* qflags, unsigned int* pair, unsigned int* status,
                         int split, int64_t grid, hipStream_t s) {
-    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)grid), dim3(WAVE), 0, s, d, nq, counter,
-                       qflags, pair, status, split);
+    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)grid), dim3(WAVE), 0, s, d, items, members,
+                       n_items, counter, qflags, pair, status, split);
     return hipGetLastError();
 }
 

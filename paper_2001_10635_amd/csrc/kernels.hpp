@@ -146,10 +146,25 @@ struct QDesc {
 // Cells per lane of a batched query: ceil(n / 64) (lanes hold E or E - 1).
 inline int batch_cells_per_lane(int64_t n) { return (int)((n + 63) / 64); }
 
+// Short cooperative queries packed into one wave: at most kPackMax queries of
+// at most kPackMaxN cells, together at most 64 cells.
+constexpr int kPackMax = 16;
+constexpr int64_t kPackMaxN = 32;
+
+// One work item of a batch: the queries members[start .. start + count) --
+// a single query (count 1) or a pack of short ones.
+struct BatchItem {
+    uint32_t start;
+    uint32_t count;
+};
+
 // Persistent batch worker: `grid` waves pull work items through *counter:
-// whole queries, or with `split` two per query (one per side of a
-// cooperative chain), pair[i] counting the finished sides of query i.
-hipError_t launch_batch(const QDesc* d, int64_t nq, unsigned long long* counter,
+// items[0 .. *n_items) (whole queries or packs; d[] in the caller's order,
+// members[] the query indices of the items in launch order), or with `split`
+// two per item (one per side of a cooperative chain; no packs then), pair[i]
+// counting the finished sides of item i.
+hipError_t launch_batch(const QDesc* d, const BatchItem* items, const uint32_t* members,
+                        const uint64_t* n_items, unsigned long long* counter,
                         unsigned int* qflags, unsigned int* pair, unsigned int* status,
                         int split, int64_t grid, hipStream_t stream);
 // Zero `count` 32-bit words (a kernel, so it can sit in a captured graph).

@@ -14,6 +14,9 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <condition_variable>
+#include <functional>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -58,6 +61,74 @@ struct TuneEntry { int E; int K; int S; };
 
 }  // namespace
 
+// Host worker threads kept for the life of a context (starting threads per
+// call costs more than the work they share on a batch of 10^5 queries).
+// run(nth, fn) calls fn(0) on the caller and fn(1 .. nth-1) on workers and
+// returns when all have finished.
+class HostPool {
+  public:
+    explicit HostPool(int n) : n_(n) {
+        for (int i = 1; i < n; ++i) th_.emplace_back([this, i] { loop(i); });
+    }
+    ~HostPool() {
+        {
+            std::lock_guard<std::mutex> g(m_);
+            stop_ = true;
+            ++gen_;
+        }
+        start_.notify_all();
+        for (auto& t : th_) t.join();
+    }
+    int size() const { return n_; }
+    void run(int nth, const std::function<void(int)>& fn) {
+        if (nth <= 1 || n_ <= 1) {
+            fn(0);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> g(m_);
+            job_ = &fn;
+            job_n_ = std::min(nth, n_);
+            pending_ = n_ - 1;
+            ++gen_;
+        }
+        start_.notify_all();
+        fn(0);
+        std::unique_lock<std::mutex> lk(m_);
+        done_.wait(lk, [&] { return pending_ == 0; });
+        job_ = nullptr;
+    }
+
+  private:
+    void loop(int id) {
+        uint64_t seen = 0;
+        for (;;) {
+            const std::function<void(int)>* job = nullptr;
+            int jn = 0;
+            {
+                std::unique_lock<std::mutex> lk(m_);
+                start_.wait(lk, [&] { return gen_ != seen; });
+                seen = gen_;
+                if (stop_) return;
+                job = job_;
+                jn = job_n_;
+            }
+            if (id < jn) (*job)(id);
+            std::lock_guard<std::mutex> g(m_);
+            if (--pending_ == 0) done_.notify_one();
+        }
+    }
+    int n_;
+    std::vector<std::thread> th_;
+    std::mutex m_;
+    std::condition_variable start_, done_;
+    const std::function<void(int)>* job_ = nullptr;
+    int job_n_ = 0;
+    int pending_ = 0;
+    uint64_t gen_ = 0;
+    bool stop_ = false;
+};
+
 struct reach_ctx {
     int device = 0;
     int cus = 256;
@@ -67,12 +138,13 @@ struct reach_ctx {
     std::map<std::string, int64_t> opt;
     std::map<std::tuple<int, int, int>, TuneEntry> tune;  // (kind, dtype, log2 n bucket)
     // batch staging (pinned host) and graph cache
-    QDesc* staging = nullptr;
+    QDesc* staging = nullptr;            // [nq] descriptors, [nq] items, item count
     int64_t staging_cap = 0;
     hipEvent_t staging_ev = nullptr;
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::vector<hipStream_t> each_streams;
     bool log = false;                    // REACH_LOG: one JSON line per call on stderr
+    std::unique_ptr<HostPool> pool;      // batch preparation threads (on first large batch)
 };
 
 namespace {
@@ -560,6 +632,7 @@ void reach_ctx_destroy(reach_ctx* c) {
     if (c->staging) hipHostFree(c->staging);
     if (c->staging_ev) hipEventDestroy(c->staging_ev);
     if (c->status) hipFree(c->status);
+    c->pool.reset();
     delete c;
 }
 
@@ -1066,24 +1139,275 @@ int batch_host_threads(int64_t nq) {
     return (int)std::max<int64_t>(1, std::min<int64_t>({by_size, 8, hw ? (int64_t)hw : 1}));
 }
 
-// fn(t) for t in [0, nth): t = 0 on the calling thread, the rest on their own.
+// fn(t) for t in [0, nth): t = 0 on the calling thread, the rest on the pool's
+// workers (nth <= the pool's size; without a pool nth must be 1).
 template <class F>
-void run_threads(int nth, F&& fn) {
-    std::vector<std::thread> th;
-    th.reserve(nth > 1 ? nth - 1 : 0);
-    for (int t = 1; t < nth; ++t) th.emplace_back(fn, t);
-    fn(0);
-    for (auto& x : th) x.join();
+void run_threads(HostPool* pool, int nth, F&& fn) {
+    if (nth <= 1 || !pool) {
+        for (int t = 0; t < nth; ++t) fn(t);
+        return;
+    }
+    pool->run(nth, std::function<void(int)>(fn));
+}
+
+// The context's pool, started on first use with batch_host_threads' maximum.
+HostPool* host_pool(reach_ctx* c) {
+    if (!c) return nullptr;
+    if (!c->pool) {
+        const unsigned hw = std::thread::hardware_concurrency();
+        c->pool.reset(new HostPool((int)std::max<int64_t>(1, std::min<int64_t>(8, hw ? hw : 1))));
+    }
+    return c->pool.get();
+}
+
+// Descriptors (the caller's order), work items, the item count and the items'
+// query indices, uploaded as one block.
+size_t batch_block_bytes(int64_t nq) {
+    return (sizeof(QDesc) + sizeof(BatchItem) + sizeof(uint32_t)) * (size_t)nq + sizeof(uint64_t);
+}
+struct BatchBlock {
+    QDesc* desc;
+    BatchItem* items;
+    uint64_t* count;
+    uint32_t* members;
+};
+BatchBlock batch_block(void* base, int64_t nq) {
+    BatchBlock b;
+    b.desc = (QDesc*)base;
+    b.items = (BatchItem*)(b.desc + nq);
+    b.count = (uint64_t*)(b.items + nq);
+    b.members = (uint32_t*)(b.count + 1);
+    return b;
+}
+
+// 1/16-octave class of a wave time, larger for shorter work (the launch
+// order takes classes in increasing order: longest first).
+int wave_time_bucket(uint64_t cost) {
+    constexpr int kBuckets = 64 * 16;
+    const uint64_t c1 = cost + 1u;      // never 0
+    const int msb = 63 - __builtin_clzll(c1);
+    const int frac = msb >= 4 ? (int)((c1 >> (msb - 4)) & 15u) : (int)((c1 << (4 - msb)) & 15u);
+    return kBuckets - 1 - (msb * 16 + frac);
+}
+
+// The schedule of a batch: the descriptors descs[nq] in the caller's order
+// and the work items in launch order (items[k] covers members[start .. start
+// + count), indices into q, contiguous in launch order).
+//
+// Each of nth threads reads a contiguous chunk of the caller's array once:
+// it validates every query (without touching the context; the first bad
+// query, lowest index, is re-checked with the context afterwards to set the
+// error message) and packs its short cooperative queries (CTM or RD, n <=
+// kPackMaxN) with bitwise equal kind, dt and parameters and step counts in
+// the same 1/16 octave, up to 64 lanes or kPackMax queries; every other
+// query, and a pack left with one query, is an item of its own.  Items are
+// then ordered longest first by the wave time (E * nsteps, a pack counting
+// as E = 1 with its longest member's steps) at 1/16 octave, ties in chunk
+// order.
+struct PlanTimes {
+    double pass_ms = 0, order_ms = 0, members_ms = 0;
+};
+
+reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int64_t nq,
+                        int split, int nth, QDesc* descs, std::vector<uint32_t>* members_out,
+                        std::vector<BatchItem>* items_out, PlanTimes* times = nullptr) {
+    using clk = std::chrono::steady_clock;
+    auto since = [](clk::time_point t0) {
+        return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+    };
+    auto t0 = clk::now();
+    auto chunk = [&](int t, int64_t total, int64_t* lo, int64_t* hi) {
+        *lo = total * t / nth;
+        *hi = total * (t + 1) / nth;
+    };
+    constexpr int kBuckets = 64 * 16;
+    constexpr int64_t kPackLanes = 64;   // one cell per lane of a wavefront
+    struct Item {
+        uint32_t first;    // into the thread's member list
+        uint16_t count;
+        int16_t bucket;
+    };
+    struct Consts {
+        int32_t kind;
+        double dt;
+        double prm[8];
+        bool operator==(const Consts& o) const {
+            return kind == o.kind && std::memcmp(&dt, &o.dt, sizeof dt) == 0 &&
+                   std::memcmp(prm, o.prm, sizeof prm) == 0;
+        }
+    };
+    struct Open {
+        int64_t lanes = 0;
+        int64_t max_steps = 0;
+        int count = 0;
+        uint32_t mem[kPackMax];
+    };
+    constexpr int kMaxClasses = 16;      // per thread; queries of further classes run alone
+    std::vector<std::vector<Item>> titems((size_t)nth);
+    std::vector<std::vector<uint32_t>> tmembers((size_t)nth);
+    std::vector<int64_t> bad((size_t)nth, nq);
+    run_threads(pool, nth, [&](int t) {
+        int64_t lo, hi;
+        chunk(t, nq, &lo, &hi);
+        // thread-local lists (moved out at the end: vector headers written by
+        // several threads would share cache lines)
+        std::vector<Item> items;
+        std::vector<uint32_t> members;
+        int64_t my_bad = nq;
+        items.reserve((size_t)(hi - lo));
+        members.reserve((size_t)(hi - lo));
+        std::vector<Consts> classes;
+        // open packs per (class, bucket): classes x kBuckets slots, -1 = none
+        std::vector<int32_t> slot;
+        std::vector<Open> open;
+        auto emit = [&](Open& o) {
+            if (o.count == 0) return;
+            const bool pack = o.count >= 2;
+            for (int m = 0; m < o.count; ++m) {
+                if (!pack || m == 0)
+                    items.push_back(Item{(uint32_t)members.size(), (uint16_t)(pack ? o.count : 1),
+                                         (int16_t)wave_time_bucket((uint64_t)o.max_steps)});
+                members.push_back(o.mem[m]);
+            }
+            o.count = 0;
+            o.lanes = 0;
+            o.max_steps = 0;
+        };
+        for (int64_t i = lo; i < hi; ++i) {
+            QDesc& d = descs[i];
+            if (make_desc(nullptr, q[i], i, &d) != REACH_OK) {
+                my_bad = std::min(my_bad, i);
+                continue;
+            }
+            int cls = -1;
+            if (!split && (d.kind == REACH_CTM || d.kind == REACH_RD) && d.n <= kPackMaxN &&
+                d.nsteps >= 1) {
+                Consts cs;
+                std::memset(&cs, 0, sizeof cs);
+                cs.kind = q[i].sys.kind;
+                cs.dt = q[i].dt;
+                std::memcpy(cs.prm, q[i].sys.prm, sizeof cs.prm);
+                for (size_t u = 0; u < classes.size(); ++u)
+                    if (classes[u] == cs) { cls = (int)u; break; }
+                if (cls < 0 && (int)classes.size() < kMaxClasses) {
+                    classes.push_back(cs);
+                    slot.resize(classes.size() * kBuckets, -1);
+                    cls = (int)classes.size() - 1;
+                }
+            }
+            if (cls < 0) {
+                const uint64_t cost = (uint64_t)d.E * (uint64_t)std::min<int64_t>(d.nsteps, (int64_t)1 << 40);
+                items.push_back(Item{(uint32_t)members.size(), 1, (int16_t)wave_time_bucket(cost)});
+                members.push_back((uint32_t)i);
+                continue;
+            }
+            const int b = wave_time_bucket((uint64_t)std::min<int64_t>(d.nsteps, (int64_t)1 << 40));
+            int32_t& sl = slot[(size_t)cls * kBuckets + (size_t)b];
+            if (sl < 0) {
+                sl = (int32_t)open.size();
+                open.emplace_back();
+            }
+            Open& o = open[(size_t)sl];
+            if (o.lanes + d.n > kPackLanes) emit(o);
+            o.mem[o.count++] = (uint32_t)i;
+            o.lanes += d.n;
+            o.max_steps = std::max(o.max_steps, d.nsteps);
+            if (o.lanes == kPackLanes || o.count == kPackMax) emit(o);
+        }
+        for (auto& o : open) emit(o);
+        titems[(size_t)t] = std::move(items);
+        tmembers[(size_t)t] = std::move(members);
+        bad[(size_t)t] = my_bad;
+    });
+    const int64_t first_bad = *std::min_element(bad.begin(), bad.end());
+    if (first_bad < nq) {
+        QDesc tmp;
+        return make_desc(c, q[first_bad], first_bad, &tmp);
+    }
+    if (times) times->pass_ms = since(t0);
+    t0 = clk::now();
+    // launch order: bucket-major, then thread, then the thread's item order
+    std::vector<int64_t> hist((size_t)nth * kBuckets, 0);
+    run_threads(pool, nth, [&](int t) {
+        int64_t* h = &hist[(size_t)t * kBuckets];
+        for (const Item& it : titems[(size_t)t]) ++h[it.bucket];
+    });
+    int64_t ni = 0;
+    for (int b = 0; b < kBuckets; ++b)
+        for (int t = 0; t < nth; ++t) {
+            const int64_t v = hist[(size_t)t * kBuckets + b];
+            hist[(size_t)t * kBuckets + b] = ni;
+            ni += v;
+        }
+    struct Ref {
+        uint32_t t, k;
+    };
+    std::vector<Ref> sorted((size_t)ni);
+    run_threads(pool, nth, [&](int t) {
+        int64_t* h = &hist[(size_t)t * kBuckets];
+        const auto& items = titems[(size_t)t];
+        for (size_t k = 0; k < items.size(); ++k)
+            sorted[(size_t)h[items[k].bucket]++] = Ref{(uint32_t)t, (uint32_t)k};
+    });
+    std::vector<BatchItem>& io = *items_out;
+    io.resize((size_t)ni);
+    uint32_t p = 0;
+    for (int64_t k = 0; k < ni; ++k) {
+        const Item& it = titems[sorted[(size_t)k].t][sorted[(size_t)k].k];
+        io[(size_t)k] = BatchItem{p, it.count};
+        p += it.count;
+    }
+    if (times) times->order_ms = since(t0);
+    t0 = clk::now();
+    std::vector<uint32_t>& mo = *members_out;
+    mo.resize((size_t)nq);
+    run_threads(pool, nth, [&](int t) {
+        int64_t lo, hi;
+        chunk(t, ni, &lo, &hi);
+        for (int64_t k = lo; k < hi; ++k) {
+            const Ref r = sorted[(size_t)k];
+            const Item& it = titems[r.t][r.k];
+            const uint32_t* src = &tmembers[r.t][it.first];
+            std::memcpy(&mo[io[(size_t)k].start], src, sizeof(uint32_t) * it.count);
+        }
+    });
+    if (times) times->members_ms = since(t0);
+    return REACH_OK;
 }
 
 }  // namespace
 
 extern "C" {
 
-// batch workspace: [work counter][per-query flags][per-query side counters][descriptors]
+// batch workspace: [work counter][per-query flags][per-query side counters]
+// [descriptors, items, item count]
 size_t reach_batch_workspace_bytes(int64_t nq) {
     if (nq < 0) return (size_t)-1;
-    return align256(8) + 2 * align256(4 * (size_t)nq) + align256(sizeof(QDesc) * (size_t)nq);
+    return align256(8) + 2 * align256(4 * (size_t)nq) + align256(batch_block_bytes(nq));
+}
+
+reach_status reach_plan_batch(reach_ctx* c, const reach_query* q, int64_t nq,
+                              int64_t* item_start, int32_t* item_count, int64_t* member,
+                              int64_t* n_items) {
+    if (nq < 0 || !n_items || (nq > 0 && (!q || !item_start || !item_count || !member)))
+        return c ? fail(c, REACH_E_INVAL, "bad arguments") : REACH_E_INVAL;
+    *n_items = 0;
+    if (nq == 0) return REACH_OK;
+    const int split = (c && opt_get(c, "batch.split")) ? 1 : 0;
+    std::vector<QDesc> descs((size_t)nq);
+    std::vector<uint32_t> members;
+    std::vector<BatchItem> items;
+    HostPool* pool = host_pool(c);
+    const int nth = pool ? std::min(batch_host_threads(nq), pool->size()) : 1;
+    const reach_status st = plan_batch(c, pool, q, nq, split, nth, descs.data(), &members, &items);
+    if (st != REACH_OK) return st;
+    for (size_t k = 0; k < items.size(); ++k) {
+        item_start[k] = items[k].start;
+        item_count[k] = (int32_t)items[k].count;
+    }
+    for (int64_t p = 0; p < nq; ++p) member[p] = members[(size_t)p];
+    *n_items = (int64_t)items.size();
+    return REACH_OK;
 }
 
 reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t nq, void* ws,
@@ -1095,51 +1419,11 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     if (!ws || ws_bytes < need) return fail(c, REACH_E_NOMEM, "workspace of %zu bytes needed", need);
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t hs = (hipStream_t)stream;
-    // Longest query first (the workers pull in this order, so the long chains
-    // start early and the short ones fill the tail).  A counting sort on the
-    // cost n * nsteps rounded down to 1/16 of an octave keeps this O(nq): the
-    // order only steers load balance, and ties keep the caller's order.  Large
-    // batches split the host work over a few threads (histogram, scatter and
-    // descriptor building per contiguous chunk of the caller's array).
-    constexpr int kBuckets = 64 * 16;
-    const int nth = batch_host_threads(nq);
-    std::vector<int64_t> order(nq);
-    std::vector<int16_t> bucket(nq);
-    std::vector<int64_t> hist((size_t)nth * kBuckets, 0);
-    auto chunk = [&](int t, int64_t* lo, int64_t* hi) {
-        *lo = nq * t / nth;
-        *hi = nq * (t + 1) / nth;
-    };
-    run_threads(nth, [&](int t) {
-        int64_t lo, hi;
-        chunk(t, &lo, &hi);
-        int64_t* h = &hist[(size_t)t * kBuckets];
-        for (int64_t i = lo; i < hi; ++i) {
-            const uint64_t n = (uint64_t)std::min<int64_t>(std::max<int64_t>(q[i].sys.n, 0), 1ll << 31);
-            const uint64_t k = (uint64_t)std::min<int64_t>(std::max<int64_t>(q[i].nsteps, 0), 1ll << 31);
-            const uint64_t cost = n * k + 1u;   // < 2^62 + 1, never 0
-            const int msb = 63 - __builtin_clzll(cost);
-            const int frac = msb >= 4 ? (int)((cost >> (msb - 4)) & 15u)
-                                      : (int)((cost << (4 - msb)) & 15u);
-            const int b = kBuckets - 1 - (msb * 16 + frac);   // descending cost
-            bucket[i] = (int16_t)b;
-            ++h[b];
-        }
-    });
-    // exclusive offsets: bucket-major, then thread (keeps the caller's order)
-    int64_t run = 0;
-    for (int b = 0; b < kBuckets; ++b)
-        for (int t = 0; t < nth; ++t) {
-            const int64_t v = hist[(size_t)t * kBuckets + b];
-            hist[(size_t)t * kBuckets + b] = run;
-            run += v;
-        }
-    run_threads(nth, [&](int t) {
-        int64_t lo, hi;
-        chunk(t, &lo, &hi);
-        int64_t* h = &hist[(size_t)t * kBuckets];
-        for (int64_t i = lo; i < hi; ++i) order[h[bucket[i]]++] = i;
-    });
+    // whole queries per wave by default (most work per wave, best throughput);
+    // batch.split = 1 gives each side of a cooperative query its own wave
+    const int split = opt_get(c, "batch.split") ? 1 : 0;
+    HostPool* pool = batch_host_threads(nq) > 1 ? host_pool(c) : nullptr;
+    const int nth = pool ? std::min(batch_host_threads(nq), pool->size()) : 1;
     // pinned staging (reused; wait for the previous upload from it)
     if (c->staging_cap < nq) {
         HIPCHK(c, hipEventSynchronize(c->staging_ev));
@@ -1148,50 +1432,50 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
         for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
         c->graphs.clear();
         int64_t cap = std::max<int64_t>(nq, 1024);
-        HIPCHK(c, hipHostMalloc((void**)&c->staging, sizeof(QDesc) * cap, hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void**)&c->staging, batch_block_bytes(cap), hipHostMallocDefault));
         c->staging_cap = cap;
     } else {
         HIPCHK(c, hipEventSynchronize(c->staging_ev));
     }
-    // descriptors straight into the pinned staging buffer, in schedule order;
-    // the threads validate without touching the context, and the first bad
-    // query (lowest index) is then re-checked to set the error message
-    std::vector<int64_t> bad(nth, nq);
-    run_threads(nth, [&](int t) {
-        int64_t lo, hi;
-        chunk(t, &lo, &hi);
-        for (int64_t j = lo; j < hi; ++j) {
-            const int64_t i = order[j];
-            if (make_desc(nullptr, q[i], i, &c->staging[j]) != REACH_OK && i < bad[t]) bad[t] = i;
-        }
-    });
-    const int64_t first_bad = *std::min_element(bad.begin(), bad.end());
-    if (first_bad < nq) {
-        QDesc tmp;
-        return make_desc(c, q[first_bad], first_bad, &tmp);
-    }
+    const BatchBlock hb = batch_block(c->staging, nq);
+    const auto t_start = std::chrono::steady_clock::now();
+    std::vector<uint32_t> members;
+    std::vector<BatchItem> items;
+    PlanTimes pt;
+    reach_status pst = plan_batch(c, pool, q, nq, split, nth, hb.desc, &members, &items, &pt);
+    if (pst != REACH_OK) return pst;
+    const int64_t ni = (int64_t)items.size();
+    std::memcpy(hb.items, items.data(), sizeof(BatchItem) * (size_t)ni);
+    std::memcpy(hb.members, members.data(), sizeof(uint32_t) * (size_t)nq);
+    *hb.count = (uint64_t)ni;
+    const auto t_plan = std::chrono::steady_clock::now();
 
     char* base = (char*)ws;
     auto* counter = (unsigned long long*)base;
     auto* qflags = (unsigned int*)(base + align256(8));
     auto* pair = (unsigned int*)(base + align256(8) + align256(4 * (size_t)nq));
-    auto* ddesc = (QDesc*)(base + align256(8) + 2 * align256(4 * (size_t)nq));
-    // whole queries per wave by default (most work per wave, best throughput);
-    // batch.split = 1 gives each side of a cooperative query its own wave
-    const int split = opt_get(c, "batch.split") ? 1 : 0;
+    const BatchBlock db = batch_block(base + align256(8) + 2 * align256(4 * (size_t)nq), nq);
     int64_t grid = opt_get(c, "batch.waves");
     if (grid <= 0) grid = (int64_t)c->cus * 8;
     grid = std::min<int64_t>(grid, split ? 2 * nq : nq);
 
-    log_call(c, "\"call\": \"batch\", \"queries\": %lld, \"waves\": %lld, \"split\": %d, "
-                "\"host_threads\": %d",
-             (long long)nq, (long long)grid, split, nth);
+    if (c->log) {
+        using ms = std::chrono::duration<double, std::milli>;
+        log_call(c, "\"call\": \"batch\", \"queries\": %lld, \"items\": %lld, \"packed\": %lld, "
+                    "\"waves\": %lld, \"split\": %d, \"host_threads\": %d, \"plan_ms\": %.3f, "
+                    "\"plan_pass_ms\": %.3f, \"plan_order_ms\": %.3f, \"plan_members_ms\": %.3f",
+                 (long long)nq, (long long)ni, (long long)(nq - (int64_t)std::count_if(
+                     items.begin(), items.end(), [](const BatchItem& x) { return x.count == 1; })),
+                 (long long)grid, split, nth, ms(t_plan - t_start).count(), pt.pass_ms,
+                 pt.order_ms, pt.members_ms);
+    }
     auto enqueue = [&](hipStream_t s) -> hipError_t {
         hipError_t e = launch_zero(base, (int64_t)(align256(8) + 2 * align256(4 * (size_t)nq)) / 4, s);
         if (e != hipSuccess) return e;
-        e = hipMemcpyAsync(ddesc, c->staging, sizeof(QDesc) * nq, hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(db.desc, c->staging, batch_block_bytes(nq), hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
-        return launch_batch(ddesc, nq, counter, qflags, pair, c->status, split, grid, s);
+        return launch_batch(db.desc, db.items, db.members, db.count, counter, qflags, pair,
+                            c->status, split, grid, s);
     };
 
     if (hs == nullptr) {
