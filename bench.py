@@ -603,6 +603,21 @@ def extra_mc_ctm4096(rc, R, torch, workloads, cpu_samples):
                         "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
                         "frac": round(ops / sec / FP32_PEAK, 4),
                         "frac_of_nonpacked_peak": round(ops / sec / (FP32_PEAK / 2), 4)}}
+    # containment in the FP64 embedding box of the same problem (the FP32 box
+    # values are exact in FP64), with the FP32-vs-FP64 slack of the tests
+    e_lo, e_hi = rc.embed(p.kind, p.prm, x_lo.double(), x_hi.double(), p.dt, p.nsteps)
+    assert rc.sync() == R.REACH_OK
+    e_lo, e_hi = e_lo.cpu().numpy(), e_hi.cpu().numpy()
+    g_mn, g_mx = mn.double().cpu().numpy(), mx.double().cpu().numpy()
+    slack_lo = 1e-5 * np.maximum(np.abs(e_lo), 1.0)
+    slack_hi = 1e-5 * np.maximum(np.abs(e_hi), 1.0)
+    ratio = (g_mx - g_mn) / np.maximum(e_hi - e_lo, np.finfo(np.float64).tiny)
+    out["containment"] = {
+        "violations": int(np.sum(g_mn < e_lo - slack_lo) + np.sum(g_mx > e_hi + slack_hi)),
+        "cells": int(p.n), "slack": "1e-5 max(|x|, 1)",
+        "width_ratio_mc_over_embedding": {"mean": round(float(ratio.mean()), 4),
+                                          "min": round(float(ratio.min()), 4),
+                                          "max": round(float(ratio.max()), 4)}}
     if cpu_samples:
         t = time.perf_counter()
         oracle.montecarlo(p.kind, p.prm, lo.astype(np.float64), hi.astype(np.float64), dt=p.dt,
