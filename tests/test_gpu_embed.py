@@ -75,7 +75,7 @@ def run_oracle(kind, prm, lo, hi, pl, ph, dt, nsteps):
     return oracle.embed_rk4(kind, prm, f(lo), f(hi), f(pl), f(ph), dt=dt, nsteps=nsteps)
 
 
-SIZES = [1, 2, 3, 5, 63, 64, 65, 127, 511, 512, 513, 1000, 2049, 4097]
+SIZES = [1, 2, 3, 4, 5, 63, 64, 65, 127, 511, 512, 513, 1000, 2049, 4097]
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
