@@ -248,3 +248,43 @@ def test_batch_of_20000_reports_the_first_bad_query(rc):
         R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
     assert e.value.status == R.REACH_E_UNSUPPORTED and "512" in str(e.value)
     assert rc.sync() == R.REACH_OK
+
+
+def test_packed_queries_report_nonfinite_and_order_and_match_alone(rc):
+    """Twelve 10-cell CTM queries with 30 steps share waves (reach_plan_batch
+    packs them); one starts from an infinite state, one with lower > upper.
+    Both conditions reach the status word, and the clean packed queries equal
+    their single runs bit for bit."""
+    n, steps, nqs = 10, 30, 12
+    rng = np.random.default_rng(5)
+    lo = rng.uniform(12.0, 24.0, n * nqs)
+    hi = lo + rng.uniform(0.0, 2.0, n * nqs)
+    lo[3 * n + 4] = np.inf                     # query 3: non-finite
+    lo[7 * n + 2], hi[7 * n + 2] = 30.0, 20.0  # query 7: lower > upper
+    x_lo, x_hi = to_dev(lo), to_dev(hi)
+    r_lo = torch.full((n * nqs,), np.nan, dtype=torch.float64, device="cuda")
+    r_hi = torch.full_like(r_lo, np.nan)
+    qs = [R.make_query(R.REACH_CTM, n, workloads.CTM_PRM, R.REACH_F64, x_lo.data_ptr() + 8 * n * k,
+                       x_hi.data_ptr() + 8 * n * k, r_lo.data_ptr() + 8 * n * k,
+                       r_hi.data_ptr() + 8 * n * k, 0.01, steps) for k in range(nqs)]
+    plan = R.reach_plan_batch(rc.ctx, qs)
+    assert any(len(it) > 1 for it in plan) and any(3 in it and len(it) > 1 for it in plan)
+    nb = R.reach_batch_workspace_bytes(nqs)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    say("packed batch with a non-finite and a crossed query")
+    R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
+    assert rc.sync() == R.REACH_E_NONFINITE
+    got_lo, got_hi = to_host(r_lo), to_host(r_hi)
+    for k in range(nqs):
+        if k in (3, 7):
+            continue
+        a_lo, a_hi = rc.embed(R.REACH_CTM, workloads.CTM_PRM, x_lo[n * k:n * (k + 1)].contiguous(),
+                              x_hi[n * k:n * (k + 1)].contiguous(), 0.01, steps)
+        assert rc.sync() == R.REACH_OK
+        assert np.array_equal(got_lo[n * k:n * (k + 1)], to_host(a_lo)), f"query {k}"
+        assert np.array_equal(got_hi[n * k:n * (k + 1)], to_host(a_hi)), f"query {k}"
+    # the crossed query alone in a batch of packs raises the order flag
+    qs2 = [q for k, q in enumerate(qs) if k != 3]
+    R.reach_embed_rk4_batch(rc.ctx, qs2, ws, nb, 0)
+    assert rc.sync() == R.REACH_E_ORDER
+    assert rc.sync() == R.REACH_OK
