@@ -3,18 +3,22 @@
 // Every query (FP64, n <= 512 cells, scalar input) is run by one wavefront
 // with its whole lower/upper state in registers (E = ceil(n / 64) cells per
 // lane, 1..8, spread so that every lane is busy), all N RK4 steps in one go:
-// no halo, no HBM traffic inside the step loop.  The arithmetic per cell is the same code the large-n embedding kernel
-// runs, so a query gives the same box alone, in a batch, or served.
+// no halo, no HBM traffic inside the step loop; short cooperative queries
+// share a wavefront, one cell per lane.  The arithmetic per cell is the
+// large-n embedding kernel's, so a query gives the same box alone, in a batch,
+// or served.
 //
 //   batch_kernel   persistent grid; each wave pops the next work item (a whole
-//                  query, or with `split` one side of a cooperative query) from
-//                  a device counter until the batch is exhausted.
+//                  query, a pack of short ones, or with `split` one side of a
+//                  cooperative query) from a device counter until the batch is
+//                  exhausted.
 //   single_kernel  one query per launch (the baseline the batch is compared with).
 //   serve_kernel   persistent grid fed through a ring of descriptors in pinned
 //                  host memory; each wave claims the next work item (sequence
 //                  number and side), waits (bounded) until the host publishes
-//                  it, runs it and publishes that side's completion.  Waves leave when the host sets the stop
-//                  flag or after an idle limit, so the grid always drains.
+//                  it, runs it and publishes that side's completion.  Waves
+//                  leave when the host sets the stop flag or after an idle
+//                  limit, so the grid always drains.
 #include "dev.hpp"
 #include "kernels.hpp"
 
