@@ -802,10 +802,28 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         t1 = ev0.elapsed_time(ev1) / 1e3 / plan1["passes"]
+        # the device's plain-copy rate for the same bytes (two arrays of n
+        # doubles in, two out), the practical ceiling of any HBM stream
+        c_in = torch.empty(2 * p.n, dtype=torch.float64, device="cuda")
+        c_out = torch.empty_like(c_in)
+        with torch.cuda.stream(stream):
+            for _ in range(3):
+                c_out.copy_(c_in)
+            ev0.record(stream)
+            for _ in range(10):
+                c_out[:p.n].copy_(c_in[:p.n])
+                c_out[p.n:].copy_(c_in[p.n:])
+            ev1.record(stream)
+        torch.cuda.synchronize()
+        tc = ev0.elapsed_time(ev1) / 1e3 / 10
+        del c_in, c_out
         stream_k1 = {"E": plan1["E"], "launch_us": round(t1 * 1e6, 1),
                      "achieved_GBps": round(bytes_per_launch / t1 / 1e9, 1),
                      "frac": round(bytes_per_launch / t1 / HBM_PEAK, 4),
-                     "state_steps_per_s": 2.0 * p.n / t1}
+                     "state_steps_per_s": 2.0 * p.n / t1,
+                     "device_copy_us": round(tc * 1e6, 1),
+                     "device_copy_GBps": round(bytes_per_launch / tc / 1e9, 1),
+                     "frac_of_device_copy": round(tc / t1, 4)}
         rc.set_option("embed.K", args.K)
         assert rc.sync(stream) == R.REACH_OK
         log(f"K=1 stream: {stream_k1}")
@@ -836,6 +854,9 @@ def main():
         log(f"user sine: {extra['user_sine_f64']}")
         extra["embed_heat3d_1000_f64"] = extra_heat3d_1000(rc, R, torch, workloads,
                                                            not args.no_cpu)
+        if stream_k1:
+            hr = extra["embed_heat3d_1000_f64"]["roofline"]
+            hr["frac_of_device_copy"] = round(hr["achieved"] / stream_k1["device_copy_GBps"], 4)
         log(f"heat 1000^3: {extra['embed_heat3d_1000_f64']}")
 
     cpu = None
