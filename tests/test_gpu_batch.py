@@ -288,3 +288,17 @@ def test_packed_queries_report_nonfinite_and_order_and_match_alone(rc):
     R.reach_embed_rk4_batch(rc.ctx, qs2, ws, nb, 0)
     assert rc.sync() == R.REACH_E_ORDER
     assert rc.sync() == R.REACH_OK
+
+
+def test_plan_follows_the_split_option(rc, mix):
+    """With batch.split = 1 the batch runs one side per wave: no packs."""
+    qs = mix.queries()
+    packed = R.reach_plan_batch(rc.ctx, qs)
+    assert any(len(it) > 1 for it in packed)
+    rc.set_option("batch.split", 1)
+    try:
+        plan = R.reach_plan_batch(rc.ctx, qs)
+    finally:
+        rc.set_option("batch.split", 0)
+    assert all(len(it) == 1 for it in plan)
+    assert sorted(it[0] for it in plan) == list(range(len(qs)))
