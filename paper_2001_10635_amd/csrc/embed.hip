@@ -38,7 +38,7 @@ template <class T, int E> struct TileIO {
     // `fast`: the window lies inside the chain and src is 16-byte aligned.
     static __device__ __forceinline__ void load(T (&dst)[E], const T* __restrict__ src, int64_t ts,
                                                 int64_t n, T ghost, bool fast, T* lds) {
-        const int lane = threadIdx.x;
+        const int lane = threadIdx.x & (WAVE - 1);
         if constexpr (STAGED) {
             if (fast) {
                 constexpr int CPL = E / VEC;
@@ -69,7 +69,7 @@ template <class T, int E> struct TileIO {
     // Window cells [olo, ohi) of the lane registers to dst[ts + ...].
     static __device__ __forceinline__ void store(const T (&v)[E], T* __restrict__ dst, int64_t ts,
                                                  int olo, int ohi, bool fast, T* lds) {
-        const int lane = threadIdx.x;
+        const int lane = threadIdx.x & (WAVE - 1);
         if constexpr (STAGED) {
             if (fast) {
                 constexpr int CPL = E / VEC;
@@ -115,18 +115,26 @@ template <class T> __device__ __forceinline__ SysPrm<T> make_prm(const double (&
 // coupled LIN3).  S = 1: a wave holds one side (cooperative systems only, whose
 // decomposition function reads one side), so the same registers cover twice
 // the cells and the halo share halves; tiles [0, W) are the lower side and
-// [W, 2W) the upper side.
-template <int KIND, class T, int E, int MODE, int S>
-__global__ __launch_bounds__(64) void embed_tile_kernel(EmbedPass a) {
+// [W, 2W) the upper side.  PAIR (S = 1, one window): one block of two waves,
+// the lower and the upper side, which compare their boxes through LDS at the
+// end instead of a separate order-check launch.
+template <int KIND, class T, int E, int MODE, int S, bool PAIR>
+__global__ __launch_bounds__(PAIR ? 2 * WAVE : WAVE) void embed_tile_kernel(EmbedPass a) {
     using IO = TileIO<T, E>;
-    __shared__ __attribute__((aligned(16))) T lds[IO::LDS_ELEMS];
-    const int lane = threadIdx.x;
+    __shared__ __attribute__((aligned(16))) T lds[IO::LDS_ELEMS * (PAIR ? 2 : 1)];
+    const int lane = threadIdx.x & (WAVE - 1);
 
     // blockIdx -> tile: consecutive tiles on one XCD share halos in its L2.
-    const int64_t b = blockIdx.x;
-    const int64_t g = (b & 7) * (int64_t)a.per_xcd + (b >> 3);
-    if (g >= (S == 1 ? 2 * a.W : a.W)) return;
+    int64_t g;
+    if constexpr (PAIR) {
+        g = (int64_t)(threadIdx.x / WAVE);   // W = 1: tile 0 lower, tile 1 upper
+    } else {
+        const int64_t b = blockIdx.x;
+        g = (b & 7) * (int64_t)a.per_xcd + (b >> 3);
+        if (g >= (S == 1 ? 2 * a.W : a.W)) return;
+    }
     const int side = (S == 1 && g >= a.W) ? 1 : 0;
+    T* const my_lds = lds + (PAIR ? side * IO::LDS_ELEMS : 0);
     const int64_t w = g - side * a.W;
 
     const int64_t span = (int64_t)WAVE * E;
@@ -139,7 +147,7 @@ __global__ __launch_bounds__(64) void embed_tile_kernel(EmbedPass a) {
 
     T y[S][E];
 #pragma unroll
-    for (int s = 0; s < S; ++s) IO::load(y[s], src[S == 1 ? side : s], ts, a.n, ghost<KIND, T>(), fast, lds);
+    for (int s = 0; s < S; ++s) IO::load(y[s], src[S == 1 ? side : s], ts, a.n, ghost<KIND, T>(), fast, my_lds);
 
     Inputs<T, E, S, MODE> U;
 #pragma unroll
@@ -171,7 +179,7 @@ __global__ __launch_bounds__(64) void embed_tile_kernel(EmbedPass a) {
     const int olo = (w == 0) ? 0 : a.H;
     const int ohi = reaches_end ? (int)(a.n - ts) : (int)(span - a.H);
 #pragma unroll
-    for (int s = 0; s < S; ++s) IO::store(y[s], dst[S == 1 ? side : s], ts, olo, ohi, fast, lds);
+    for (int s = 0; s < S; ++s) IO::store(y[s], dst[S == 1 ? side : s], ts, olo, ohi, fast, my_lds);
 
     if (a.check) {
         unsigned bits = 0;
@@ -184,6 +192,22 @@ __global__ __launch_bounds__(64) void embed_tile_kernel(EmbedPass a) {
                     if (!finiteT(y[s][e])) bits |= ST_NONFINITE;
                 if constexpr (S == 2) {
                     if (y[0][e] > y[1][e]) bits |= ST_ORDER;
+                }
+            }
+        }
+        if constexpr (PAIR) {
+            // the upper wave hands its box to the lower one
+            __shared__ T upper[PAIR ? WAVE * E : 1];
+            if (side == 1) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) upper[lane * E + e] = y[0][e];
+            }
+            __syncthreads();
+            if (side == 0) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int el = lane * E + e;
+                    if (el >= olo && el < ohi && y[0][e] > upper[el]) bits |= ST_ORDER;
                 }
             }
         }
@@ -204,16 +228,25 @@ __global__ __launch_bounds__(256) void order_check_kernel(const T* __restrict__ 
     report_status(status, bits);
 }
 
-template <int KIND, class T, int E, int MODE, int S>
+template <int KIND, class T, int E, int MODE, int S, bool PAIR = false>
 static hipError_t go(const EmbedPass& a, int64_t grid, hipStream_t s) {
-    hipLaunchKernelGGL((embed_tile_kernel<KIND, T, E, MODE, S>), dim3((unsigned)grid), dim3(WAVE), 0, s, a);
+    if constexpr (PAIR)
+        hipLaunchKernelGGL((embed_tile_kernel<KIND, T, E, MODE, S, true>), dim3(1), dim3(2 * WAVE),
+                           0, s, a);
+    else
+        hipLaunchKernelGGL((embed_tile_kernel<KIND, T, E, MODE, S, false>), dim3((unsigned)grid),
+                           dim3(WAVE), 0, s, a);
     return hipGetLastError();
+}
+template <int KIND, class T, int E, int MODE>
+static hipError_t go_one_side(bool pair, const EmbedPass& a, int64_t grid, hipStream_t s) {
+    return pair ? go<KIND, T, E, MODE, 1, true>(a, grid, s) : go<KIND, T, E, MODE, 1, false>(a, grid, s);
 }
 
 // Shapes built: S = 2 (both sides per wave) for every system, S = 1 (one side
 // per wave, wider tiles) for the cooperative CTM and RD chains.
 template <int KIND, class T, int MODE>
-static hipError_t by_E(int E, int S, const EmbedPass& a, int64_t grid, hipStream_t s) {
+static hipError_t by_E(int E, int S, bool pair, const EmbedPass& a, int64_t grid, hipStream_t s) {
     constexpr bool F32 = sizeof(T) == 4;
     constexpr bool COOP = KIND != K_LIN3;
     if (S == 2) {
@@ -233,18 +266,18 @@ static hipError_t by_E(int E, int S, const EmbedPass& a, int64_t grid, hipStream
     if constexpr (COOP) {
         if (S == 1) {
             switch (E) {
-                case 1: return go<KIND, T, 1, MODE, 1>(a, grid, s);
-                case 2: return go<KIND, T, 2, MODE, 1>(a, grid, s);
-                case 4: return go<KIND, T, 4, MODE, 1>(a, grid, s);
-                case 8: return go<KIND, T, 8, MODE, 1>(a, grid, s);
-                case 16: return go<KIND, T, 16, MODE, 1>(a, grid, s);
-                case 24: return go<KIND, T, 24, MODE, 1>(a, grid, s);
-                case 32: return go<KIND, T, 32, MODE, 1>(a, grid, s);
+                case 1: return go_one_side<KIND, T, 1, MODE>(pair, a, grid, s);
+                case 2: return go_one_side<KIND, T, 2, MODE>(pair, a, grid, s);
+                case 4: return go_one_side<KIND, T, 4, MODE>(pair, a, grid, s);
+                case 8: return go_one_side<KIND, T, 8, MODE>(pair, a, grid, s);
+                case 16: return go_one_side<KIND, T, 16, MODE>(pair, a, grid, s);
+                case 24: return go_one_side<KIND, T, 24, MODE>(pair, a, grid, s);
+                case 32: return go_one_side<KIND, T, 32, MODE>(pair, a, grid, s);
                 case 48:
-                    if constexpr (F32) return go<KIND, T, 48, MODE, 1>(a, grid, s);
+                    if constexpr (F32) return go_one_side<KIND, T, 48, MODE>(pair, a, grid, s);
                     else return hipErrorInvalidValue;
                 case 64:
-                    if constexpr (F32) return go<KIND, T, 64, MODE, 1>(a, grid, s);
+                    if constexpr (F32) return go_one_side<KIND, T, 64, MODE>(pair, a, grid, s);
                     else return hipErrorInvalidValue;
                 default: return hipErrorInvalidValue;
             }
@@ -266,20 +299,21 @@ int embed_max_E(int dtype, int S) {
     return dtype == 1 ? 32 : 16;
 }
 
-hipError_t launch_embed(int kind, int mode, int dtype, int E, int S, const EmbedPass& a,
-                        int64_t grid, hipStream_t s) {
+hipError_t launch_embed(int kind, int mode, int dtype, int E, int S, bool pair,
+                        const EmbedPass& a, int64_t grid, hipStream_t s) {
+    if (pair && (S != 1 || a.W != 1)) return hipErrorInvalidValue;
     if (dtype == 0) {
-        if (kind == K_CTM) return by_E<K_CTM, double, IN_SCALAR>(E, S, a, grid, s);
-        if (kind == K_RD) return mode ? by_E<K_RD, double, IN_CELL>(E, S, a, grid, s)
-                                      : by_E<K_RD, double, IN_SCALAR>(E, S, a, grid, s);
-        if (kind == K_LIN3) return mode ? by_E<K_LIN3, double, IN_CELL>(E, S, a, grid, s)
-                                        : by_E<K_LIN3, double, IN_SCALAR>(E, S, a, grid, s);
+        if (kind == K_CTM) return by_E<K_CTM, double, IN_SCALAR>(E, S, pair, a, grid, s);
+        if (kind == K_RD) return mode ? by_E<K_RD, double, IN_CELL>(E, S, pair, a, grid, s)
+                                      : by_E<K_RD, double, IN_SCALAR>(E, S, pair, a, grid, s);
+        if (kind == K_LIN3) return mode ? by_E<K_LIN3, double, IN_CELL>(E, S, pair, a, grid, s)
+                                        : by_E<K_LIN3, double, IN_SCALAR>(E, S, pair, a, grid, s);
     } else {
-        if (kind == K_CTM) return by_E<K_CTM, float, IN_SCALAR>(E, S, a, grid, s);
-        if (kind == K_RD) return mode ? by_E<K_RD, float, IN_CELL>(E, S, a, grid, s)
-                                      : by_E<K_RD, float, IN_SCALAR>(E, S, a, grid, s);
-        if (kind == K_LIN3) return mode ? by_E<K_LIN3, float, IN_CELL>(E, S, a, grid, s)
-                                        : by_E<K_LIN3, float, IN_SCALAR>(E, S, a, grid, s);
+        if (kind == K_CTM) return by_E<K_CTM, float, IN_SCALAR>(E, S, pair, a, grid, s);
+        if (kind == K_RD) return mode ? by_E<K_RD, float, IN_CELL>(E, S, pair, a, grid, s)
+                                      : by_E<K_RD, float, IN_SCALAR>(E, S, pair, a, grid, s);
+        if (kind == K_LIN3) return mode ? by_E<K_LIN3, float, IN_CELL>(E, S, pair, a, grid, s)
+                                        : by_E<K_LIN3, float, IN_SCALAR>(E, S, pair, a, grid, s);
     }
     return hipErrorInvalidValue;
 }

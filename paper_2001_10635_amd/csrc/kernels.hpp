@@ -41,8 +41,10 @@ struct EmbedPass {
 // does not instantiate.
 // S: sides per wave (2 = lower and upper together, 1 = one side per wave;
 // 1 only for the cooperative CTM and RD chains).  W counts tiles per side.
-hipError_t launch_embed(int kind, int mode, int dtype, int E, int S, const EmbedPass& a,
-                        int64_t grid, hipStream_t stream);
+// pair (S = 1, W = 1 only): one block of two waves, lower and upper, that
+// also checks lower <= upper (no order-check launch needed); grid unused.
+hipError_t launch_embed(int kind, int mode, int dtype, int E, int S, bool pair,
+                        const EmbedPass& a, int64_t grid, hipStream_t stream);
 bool embed_has_shape(int kind, int dtype, int E, int S);
 int embed_max_E(int dtype, int S);
 // Flags lower > upper anywhere in a finished box.

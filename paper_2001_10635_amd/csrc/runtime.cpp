@@ -763,6 +763,9 @@ reach_status reach_embed_rk4(reach_ctx* c, const reach_system* s, reach_dtype dt
     const int mode = s->n_in > 1 ? 1 : 0;   // per-cell inputs
     if (s->n_in == 0) { a.p_lo = nullptr; a.p_hi = nullptr; }
     const int64_t grid = 8 * (int64_t)a.per_xcd;
+    // one window, one side per wave: both waves in one block, which checks
+    // the order itself
+    const bool pair = pl.S == 1 && pl.W == 1;
     int64_t done = 0;
     for (int64_t p = 0; p < pl.passes; ++p) {
         a.src_lo = lo_of[io[p].first];
@@ -771,12 +774,12 @@ reach_status reach_embed_rk4(reach_ctx* c, const reach_system* s, reach_dtype dt
         a.dst_hi = (void*)hi_of[io[p].second];
         a.ksteps = std::min<int64_t>(pl.K, nsteps - done);
         a.check = (p == pl.passes - 1) ? 1 : 0;
-        hipError_t e = launch_embed(s->kind, mode, dtype == REACH_F64 ? 0 : 1, pl.E, pl.S, a, grid,
-                                    hs);
+        hipError_t e = launch_embed(s->kind, mode, dtype == REACH_F64 ? 0 : 1, pl.E, pl.S, pair,
+                                    a, grid, hs);
         if (e != hipSuccess) return hip_fail(c, e, "embedding kernel launch");
         done += a.ksteps;
     }
-    if (pl.S == 1) {
+    if (pl.S == 1 && !pair) {
         hipError_t e = launch_order_check(dtype == REACH_F64 ? 0 : 1, lo_of[io.back().second],
                                           hi_of[io.back().second], s->n, c->status, hs);
         if (e != hipSuccess) return hip_fail(c, e, "order check launch");

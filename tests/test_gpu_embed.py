@@ -191,6 +191,34 @@ def test_nonfinite_and_order_reported(rc, S):
     assert st == R.REACH_OK
 
 
+@pytest.mark.parametrize("n", [1, 64, 700, 2048])
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_single_window_flags_from_the_paired_waves(rc, n, dtype):
+    """A chain one window holds runs as one block of two waves (lower, upper)
+    that compare their boxes themselves: order and non-finite flags still
+    reach the status word, and a clean box matches the oracle."""
+    kind, prm, lo, hi, pl, ph, dt = make_case("ctm", n, dtype, seed=n + 17)
+    dcode = R.REACH_F64 if dtype == np.float64 else R.REACH_F32
+    plan = R.reach_plan_embed(rc.ctx, R.make_system(kind, n, prm, 0), dcode, 7)
+    assert plan["S"] == 1 and plan["passes"] == 1 and plan["halo"] == 0
+    say(f"paired single window n={n}")
+    g_lo, g_hi, st = run_gpu(rc, kind, prm, lo, hi, pl, ph, dt, 7)
+    assert st == R.REACH_OK
+    o_lo, o_hi = oracle.embed_rk4(kind, prm, lo.astype(np.float64), hi.astype(np.float64), dt=dt,
+                                  nsteps=7)
+    assert_rel(g_lo, o_lo, RTOL[np.dtype(dtype)], "lower")
+    assert_rel(g_hi, o_hi, RTOL[np.dtype(dtype)], "upper")
+    crossed_lo, crossed_hi = lo.copy(), hi.copy()
+    crossed_lo[n // 2], crossed_hi[n // 2] = hi[n // 2] + 5, lo[n // 2]
+    _, _, st = run_gpu(rc, kind, prm, crossed_lo, crossed_hi, pl, ph, dt, 7)
+    assert st == R.REACH_E_ORDER
+    bad = lo.copy()
+    bad[n - 1] = np.inf
+    _, _, st = run_gpu(rc, kind, prm, bad, hi, pl, ph, dt, 7)
+    assert st == R.REACH_E_NONFINITE
+    assert rc.sync() == R.REACH_OK
+
+
 def test_invalid_arguments_rejected(rc):
     x = torch.zeros(16, dtype=torch.float64, device="cuda")
     sys_ok = R.make_system(R.REACH_RD, 16, (1.0,), 1)
