@@ -140,7 +140,7 @@ def latency_ctm64(rc, R, torch, workloads, reps=1000, cpu=True):
     emb_us = e0.elapsed_time(e1) * 1e3 / reps
     rc.montecarlo(p.kind, p.prm, x_lo, x_hi, p.dt, p.nsteps, p.m, p.seed)
     torch.cuda.synchronize()
-    mc_reps = max(10, reps // 10)
+    mc_reps = reps
     e0.record()
     for _ in range(mc_reps):
         rc.montecarlo(p.kind, p.prm, x_lo, x_hi, p.dt, p.nsteps, p.m, p.seed)
@@ -150,7 +150,7 @@ def latency_ctm64(rc, R, torch, workloads, reps=1000, cpu=True):
     mc_us = e0.elapsed_time(e1) * 1e3 / mc_reps
     out = {"workload": "CTM chain n=64 FP64, dt=0.01, 100 RK4 steps; Monte Carlo m=1000",
            "embed_us_per_call": round(emb_us, 2), "mc_us_per_call": round(mc_us, 2),
-           "reps": reps}
+           "reps": reps, "mc_reps": mc_reps}
     if cpu:
         import oracle
         threads = oracle.get_threads()

@@ -278,6 +278,14 @@ __device__ __forceinline__ U4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c
     return o;
 }
 
+// Word q (0..3) of a block, chosen by selects: indexing r.x with a lane-varying
+// q would put the block in a per-thread array, which the compiler moves to LDS
+// and addresses through the dispatch packet, one host-memory read per wave at
+// start-up (about 14 us of serialized reads for a 1000-wave launch).
+__device__ __forceinline__ uint64_t philox_word(const U4& r, int q) {
+    return q == 0 ? r.x[0] : q == 1 ? r.x[1] : q == 2 ? r.x[2] : r.x[3];
+}
+
 constexpr uint64_t MC_STREAM = 2;
 
 // Uniform from one 64-bit word: top 53 bits / 2^53 (double), top 24 / 2^24 (float).

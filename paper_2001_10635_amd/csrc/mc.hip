@@ -73,7 +73,7 @@ __global__ __launch_bounds__(WAVE * MC_WPB) void mc_kernel(McArgs a) {
             for (int e = 0; e < E; ++e) {
                 const int64_t j = (int64_t)lane * E + e;
                 const U4 r = philox4x64_10((uint64_t)(j >> 2), (uint64_t)s, MC_STREAM, 0, k0, k1);
-                const T u = unif(r.x[j & 3], T(0));
+                const T u = unif(philox_word(r, (int)(j & 3)), T(0));
                 y[0][e] = (j < n) ? fmaT(u, xhi[j] - xlo[j], xlo[j]) : ghost<KIND, T>();
             }
         }
@@ -84,9 +84,36 @@ __global__ __launch_bounds__(WAVE * MC_WPB) void mc_kernel(McArgs a) {
             } else {
                 const int64_t j = n;
                 const U4 r = philox4x64_10((uint64_t)(j >> 2), (uint64_t)s, MC_STREAM, 0, k0, k1);
-                const T u = unif(r.x[j & 3], T(0));
+                const T u = unif(philox_word(r, (int)(j & 3)), T(0));
                 const T pl = ((const T*)a.p_lo)[0], ph = ((const T*)a.p_hi)[0];
                 U.u[0] = fmaT(u, ph - pl, pl);
+            }
+        } else if constexpr (E % 4 == 0) {
+            // cells c = lane E + 4g + q sit at coordinates n + c; with o = n mod 4
+            // (the same in every lane) the four of group g fall in blocks b and
+            // b + 1, b = (n + lane E + 4g) / 4, at words o + q counted on from b
+            const int o = (int)(n & 3);
+            const int64_t b0 = (n + (int64_t)lane * E) >> 2;
+            U4 cur = philox4x64_10((uint64_t)b0, (uint64_t)s, MC_STREAM, 0, k0, k1);
+#pragma unroll
+            for (int g = 0; g < E / 4; ++g) {
+                U4 nxt = cur;
+                if (o != 0 || g + 1 < E / 4)
+                    nxt = philox4x64_10((uint64_t)(b0 + g + 1), (uint64_t)s, MC_STREAM, 0, k0, k1);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int k = o + q;
+                    const uint64_t word = k < 4 ? philox_word(cur, k) : philox_word(nxt, k - 4);
+                    const T u = unif(word, T(0));
+                    const int64_t c = (int64_t)lane * E + 4 * g + q;
+                    if (c < n) {
+                        const T pl = ((const T*)a.p_lo)[c], ph = ((const T*)a.p_hi)[c];
+                        U.u[0][4 * g + q] = fmaT(u, ph - pl, pl);
+                    } else {
+                        U.u[0][4 * g + q] = T(0);
+                    }
+                }
+                cur = nxt;
             }
         } else {
 #pragma unroll
@@ -94,7 +121,7 @@ __global__ __launch_bounds__(WAVE * MC_WPB) void mc_kernel(McArgs a) {
                 const int64_t c = (int64_t)lane * E + e;
                 const int64_t j = n + c;
                 const U4 r = philox4x64_10((uint64_t)(j >> 2), (uint64_t)s, MC_STREAM, 0, k0, k1);
-                const T u = unif(r.x[j & 3], T(0));
+                const T u = unif(philox_word(r, (int)(j & 3)), T(0));
                 if (c < n) {
                     const T pl = ((const T*)a.p_lo)[c], ph = ((const T*)a.p_hi)[c];
                     U.u[0][e] = fmaT(u, ph - pl, pl);

@@ -1,4 +1,4 @@
-"""Build-time check of the device assembly produced by build.py.
+"""Build-time checks of the device assembly produced by build.py.
 
 The kernels must never write through the scalar data cache: no scalar memory
 stores, no scalar atomics, no write-back or discard of that cache.  This scans
@@ -20,3 +20,16 @@ def check_device_asm(build_dir: str, src: str, arch: str) -> None:
         bad = [ln for ln in f if any(t in ln for t in FORBIDDEN)]
     if bad:
         raise RuntimeError(f"{src}: scalar-cache write in device code:\n" + "".join(bad[:10]))
+    # A kernel that reads the dispatch packet (the compiler asks for it when a
+    # per-thread array with a lane-varying index is moved to LDS) makes every
+    # wave read host memory at start-up; none of these kernels needs it.
+    with open(path) as f:
+        kern, uses = None, []
+        for ln in f:
+            t = ln.split()
+            if len(t) >= 2 and t[0] == ".amdhsa_kernel":
+                kern = t[1]
+            elif len(t) >= 2 and t[0] == ".amdhsa_user_sgpr_dispatch_ptr" and t[1] == "1":
+                uses.append(kern)
+    if uses:
+        raise RuntimeError(f"{src}: kernels reading the dispatch packet: " + ", ".join(uses[:5]))
