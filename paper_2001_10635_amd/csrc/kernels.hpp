@@ -118,13 +118,16 @@ struct McArgs {
     double h2, dt, dt6;
 };
 hipError_t launch_mc(int kind, int mode, int dtype, int E, const McArgs& a, hipStream_t stream);
-// r_min / r_max [n] from the partials of `nw` <= kMcMaxWaves waves (the
-// partials are overwritten: chunk results are written in place); reports
-// non-finite values.
+// r_min / r_max [n] from the partials of `nw` <= kMcMaxWaves waves of which
+// every group-th slot holds a partial (mc_kernel folds each workgroup's waves
+// into the group's first slot: group = mc_waves_per_group(); one wave per
+// slot: group = 1).  The partials are overwritten (chunk results are written in
+// place); reports non-finite values.
 constexpr int64_t kMcMaxWaves = 4096;
 hipError_t launch_mc_reduce(int dtype, int E, void* part_min, void* part_max,
-                            int64_t nw, int64_t n, void* r_min, void* r_max,
+                            int64_t nw, int64_t group, int64_t n, void* r_min, void* r_max,
                             unsigned int* status, hipStream_t stream);
+int mc_waves_per_group();
 bool mc_has_E(int dtype, int E);
 int mc_max_E(int dtype);
 

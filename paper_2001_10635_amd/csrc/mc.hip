@@ -6,8 +6,9 @@
 // own) are persistent: wave w takes
 // samples s0 + w, s0 + w + nw, ... and folds each final state into its own
 // running min / max kept in the workspace (read-modify-write once per sample,
-// interleaved [w][e][lane] so those accesses are coalesced).  A second kernel
-// reduces the nw partials per dimension.
+// interleaved [w][e][lane] so those accesses are coalesced).  At the end the
+// first wave of each workgroup folds its group's partials into its own slot,
+// and a second kernel reduces those ceil(nw / 4) partials per dimension.
 //
 // Sampling: x0_j = x_lo_j + U(s, j) (x_hi_j - x_lo_j) and, for inputs,
 // p_k = p_lo_k + U(s, n + k) (p_hi_k - p_lo_k), with U(s, j) word j mod 4 of
@@ -36,8 +37,9 @@ constexpr int MC_WPB = 4;
 template <int KIND, class T, int E, int MODE>
 __global__ __launch_bounds__(WAVE * MC_WPB) void mc_kernel(McArgs a) {
     const int lane = threadIdx.x & (WAVE - 1);
-    const int64_t w = (int64_t)blockIdx.x * MC_WPB + (int64_t)(threadIdx.x / WAVE);
-    if (w >= a.nw) return;
+    const int wv = threadIdx.x / WAVE;
+    const int64_t wb = (int64_t)blockIdx.x * MC_WPB;
+    const int64_t w = wb + wv;
     const int64_t n = a.n;
     const bool masked = (int64_t)WAVE * E > n;
     const int64_t left = n - (int64_t)lane * E;
@@ -52,7 +54,8 @@ __global__ __launch_bounds__(WAVE * MC_WPB) void mc_kernel(McArgs a) {
     const uint64_t k0 = a.seed, k1 = 0;
 
     bool first = true;
-    for (int64_t s = a.s0 + w; s < a.s0 + a.m; s += a.nw) {
+    // waves past nw (in the last workgroup) draw nothing but join the fold
+    for (int64_t s = w < a.nw ? a.s0 + w : a.s0 + a.m; s < a.s0 + a.m; s += a.nw) {
         T y[1][E];
         Inputs<T, E, 1, MODE> U;
         // initial state: one Philox block per 4 consecutive cells
@@ -153,18 +156,39 @@ __global__ __launch_bounds__(WAVE * MC_WPB) void mc_kernel(McArgs a) {
         }
         first = false;
     }
+
+    // fold the group's partials (waves wb .. wb + live - 1, each of which drew
+    // at least one sample since nw <= m) into slot wb
+    __syncthreads();
+    const int64_t rest = a.nw - wb;
+    const int live = (int)(rest < MC_WPB ? rest : MC_WPB);
+    if (wv != 0 || live <= 1) return;
+    T* bmin = (T*)a.part_min + (size_t)wb * E * WAVE;   // wave 0's own slot: may alias pmin
+    T* bmax = (T*)a.part_max + (size_t)wb * E * WAVE;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const size_t idx = (size_t)e * WAVE + lane;
+        T mn = bmin[idx], mx = bmax[idx];
+        for (int k = 1; k < live; ++k) {
+            mn = nan_min(mn, bmin[(size_t)k * E * WAVE + idx]);
+            mx = nan_max(mx, bmax[(size_t)k * E * WAVE + idx]);
+        }
+        bmin[idx] = mn;
+        bmax[idx] = mx;
+    }
 }
 
-// Reduction of the nw per-wave partials, in two launches when nw > RED_CHUNK.
-// Block (e, g) owns the 64 partial slots [w][e][0..63] (cells j = lane * E + e)
-// of partials w in [g RED_CHUNK, (g + 1) RED_CHUNK): its RED_WAVES waves issue
-// RED_CHUNK / RED_WAVES independent loads each, then combine through LDS.  The
-// first launch writes each chunk's result over the chunk's first partial; the
-// second (wstep = RED_CHUNK) reduces those and writes the box.  Min and max
-// (NaN-propagating) are exact, so the split changes no value (signed zeros
-// aside), and every block reads only its own chunk.
+// Reduction of np partials lying wstep slots apart (slot = one wave's [e][lane]
+// block), in two launches when np > RED_CHUNK.  Block (e, g) owns the 64 values
+// [e][0..63] (cells j = lane * E + e) of partials w in [g RED_CHUNK,
+// (g + 1) RED_CHUNK): its RED_WAVES waves issue RED_CHUNK / RED_WAVES
+// independent loads each, then combine through LDS.  The first launch writes
+// each chunk's result over the chunk's first partial; the second (wstep times
+// RED_CHUNK) reduces those and writes the box.  Min and max (NaN-propagating)
+// are exact, so the split changes no value (signed zeros aside), and every
+// block reads only its own chunk.
 constexpr int RED_WAVES = 16;
-constexpr int RED_CHUNK = 64;
+constexpr int RED_CHUNK = 256;
 constexpr int RED_PER_WAVE = RED_CHUNK / RED_WAVES;
 
 template <class T, int E>
@@ -179,15 +203,20 @@ __global__ __launch_bounds__(WAVE * RED_WAVES) void mc_reduce_kernel(
     const size_t stride = (size_t)E * WAVE;
     const int64_t w0 = (int64_t)blockIdx.y * RED_CHUNK;
     const int64_t w1 = w0 + RED_CHUNK < nw ? w0 + RED_CHUNK : nw;
-    // indices past the chunk read the chunk's first partial again (min and
-    // max are idempotent)
+    // indices past the chunk load nothing and stand in with the identities
+    // +inf / -inf (nan_min(x, +inf) = x for every x, NaN included; the
+    // chunk's first partial always exists)
     T a[RED_PER_WAVE], b[RED_PER_WAVE];
 #pragma unroll
     for (int u = 0; u < RED_PER_WAVE; ++u) {
         const int64_t w = w0 + wv + (int64_t)u * RED_WAVES;
-        const size_t idx = (size_t)((w < w1 ? w : w0) * wstep) * stride + off;
-        a[u] = pmin[idx];
-        b[u] = pmax[idx];
+        a[u] = T(__builtin_inf());
+        b[u] = -T(__builtin_inf());
+        if (w < w1) {   // the same in every lane of the wave
+            const size_t idx = (size_t)(w * wstep) * stride + off;
+            a[u] = pmin[idx];
+            b[u] = pmax[idx];
+        }
     }
     T mn = a[0], mx = b[0];
 #pragma unroll
@@ -268,45 +297,49 @@ hipError_t launch_mc(int kind, int mode, int dtype, int E, const McArgs& a, hipS
 }
 
 template <class T, int E>
-static hipError_t reduce_E(void* pmin, void* pmax, int64_t nw, int64_t n, void* rmin, void* rmax,
-                           unsigned int* status, hipStream_t s) {
+static hipError_t reduce_E(void* pmin, void* pmax, int64_t nw, int64_t group, int64_t n,
+                           void* rmin, void* rmax, unsigned int* status, hipStream_t s) {
     const dim3 block(WAVE * RED_WAVES);
-    const int64_t chunks = (nw + RED_CHUNK - 1) / RED_CHUNK;
+    const int64_t np = (nw + group - 1) / group;
+    const int64_t chunks = (np + RED_CHUNK - 1) / RED_CHUNK;
     if (chunks > 1) {
         hipLaunchKernelGGL((mc_reduce_kernel<T, E>), dim3(E, (unsigned)chunks), block, 0, s,
-                           (T*)pmin, (T*)pmax, nw, (int64_t)1, n, (T*)rmin, (T*)rmax, status, 0);
+                           (T*)pmin, (T*)pmax, np, group, n, (T*)rmin, (T*)rmax, status, 0);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         static_assert(RED_CHUNK * RED_CHUNK >= kMcMaxWaves, "two passes cover every wave count");
         hipLaunchKernelGGL((mc_reduce_kernel<T, E>), dim3(E, 1), block, 0, s, (T*)pmin, (T*)pmax,
-                           chunks, (int64_t)RED_CHUNK, n, (T*)rmin, (T*)rmax, status, 1);
+                           chunks, group * RED_CHUNK, n, (T*)rmin, (T*)rmax, status, 1);
     } else {
         hipLaunchKernelGGL((mc_reduce_kernel<T, E>), dim3(E, 1), block, 0, s, (T*)pmin, (T*)pmax,
-                           nw, (int64_t)1, n, (T*)rmin, (T*)rmax, status, 1);
+                           np, group, n, (T*)rmin, (T*)rmax, status, 1);
     }
     return hipGetLastError();
 }
 
 template <class T>
-static hipError_t reduce_T(int E, void* pmin, void* pmax, int64_t nw, int64_t n, void* rmin,
-                           void* rmax, unsigned int* status, hipStream_t s) {
+static hipError_t reduce_T(int E, void* pmin, void* pmax, int64_t nw, int64_t group, int64_t n,
+                           void* rmin, void* rmax, unsigned int* status, hipStream_t s) {
     switch (E) {
-        case 1: return reduce_E<T, 1>(pmin, pmax, nw, n, rmin, rmax, status, s);
-        case 2: return reduce_E<T, 2>(pmin, pmax, nw, n, rmin, rmax, status, s);
-        case 4: return reduce_E<T, 4>(pmin, pmax, nw, n, rmin, rmax, status, s);
-        case 8: return reduce_E<T, 8>(pmin, pmax, nw, n, rmin, rmax, status, s);
-        case 16: return reduce_E<T, 16>(pmin, pmax, nw, n, rmin, rmax, status, s);
-        case 32: return reduce_E<T, 32>(pmin, pmax, nw, n, rmin, rmax, status, s);
-        case 64: return reduce_E<T, 64>(pmin, pmax, nw, n, rmin, rmax, status, s);
+        case 1: return reduce_E<T, 1>(pmin, pmax, nw, group, n, rmin, rmax, status, s);
+        case 2: return reduce_E<T, 2>(pmin, pmax, nw, group, n, rmin, rmax, status, s);
+        case 4: return reduce_E<T, 4>(pmin, pmax, nw, group, n, rmin, rmax, status, s);
+        case 8: return reduce_E<T, 8>(pmin, pmax, nw, group, n, rmin, rmax, status, s);
+        case 16: return reduce_E<T, 16>(pmin, pmax, nw, group, n, rmin, rmax, status, s);
+        case 32: return reduce_E<T, 32>(pmin, pmax, nw, group, n, rmin, rmax, status, s);
+        case 64: return reduce_E<T, 64>(pmin, pmax, nw, group, n, rmin, rmax, status, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_mc_reduce(int dtype, int E, void* pmin, void* pmax, int64_t nw,
+hipError_t launch_mc_reduce(int dtype, int E, void* pmin, void* pmax, int64_t nw, int64_t group,
                             int64_t n, void* rmin, void* rmax, unsigned int* status,
                             hipStream_t s) {
-    return dtype == 0 ? reduce_T<double>(E, pmin, pmax, nw, n, rmin, rmax, status, s)
-                      : reduce_T<float>(E, pmin, pmax, nw, n, rmin, rmax, status, s);
+    if (group < 1) return hipErrorInvalidValue;
+    return dtype == 0 ? reduce_T<double>(E, pmin, pmax, nw, group, n, rmin, rmax, status, s)
+                      : reduce_T<float>(E, pmin, pmax, nw, group, n, rmin, rmax, status, s);
 }
+
+int mc_waves_per_group() { return MC_WPB; }
 
 }  // namespace reach

@@ -962,7 +962,8 @@ reach_status reach_montecarlo_range(reach_ctx* c, const reach_system* s, reach_d
              (long long)m, E, (long long)a.nw);
     hipError_t e = launch_mc(s->kind, mode, dt_id, E, a, hs);
     if (e != hipSuccess) return hip_fail(c, e, "Monte Carlo kernel launch");
-    e = launch_mc_reduce(dt_id, E, a.part_min, a.part_max, a.nw, s->n, r_min, r_max, c->status, hs);
+    e = launch_mc_reduce(dt_id, E, a.part_min, a.part_max, a.nw, mc_waves_per_group(), s->n, r_min,
+                         r_max, c->status, hs);
     if (e != hipSuccess) return hip_fail(c, e, "Monte Carlo reduction launch");
     return REACH_OK;
 }

@@ -636,7 +636,7 @@ reach_status reach_montecarlo_user(reach_ctx* c, reach_user* u, const reach_syst
     if (hipModuleLaunchKernel(u->mc[d][mode][ei], (unsigned)a.nw, 1, 1, 64, 1, 1, 0, hs, args,
                               nullptr) != hipSuccess)
         return rt::set_error(c, REACH_E_DEVICE, "user Monte Carlo launch failed");
-    if (launch_mc_reduce(d, kUserE[ei], a.part_min, a.part_max, a.nw, s->n, r_min, r_max,
+    if (launch_mc_reduce(d, kUserE[ei], a.part_min, a.part_max, a.nw, 1, s->n, r_min, r_max,
                          rt::ctx_status(c), hs) != hipSuccess)
         return rt::set_error(c, REACH_E_DEVICE, "Monte Carlo reduction launch failed");
     return REACH_OK;
