@@ -91,3 +91,25 @@ def test_step_count_from_horizon(R):
     assert R._nsteps(None, 0.0, 1.0, 0.1) == 10
     with pytest.raises(ValueError):
         R._nsteps(9, 0.0, 1.0, 0.1)
+
+
+def test_build_rejects_kernels_reading_the_dispatch_packet(tmp_path):
+    """The build's assembly check fails a source whose kernel asks for the
+    dispatch packet (every wave would read host memory at start-up) and passes
+    one that does not; the library's own assembly passes it."""
+    from paper_2001_10635_amd.isa_check import check_device_asm
+    arch = "gfx950"
+
+    def write(name, flag):
+        (tmp_path / f"{name}-hip-amdgcn-amd-amdhsa-{arch}.s").write_text(
+            f"\t.amdhsa_kernel k_{name}\n\t\t.amdhsa_user_sgpr_dispatch_ptr {flag}\n"
+            "\t.end_amdhsa_kernel\n")
+
+    write("good", 0)
+    write("bad", 1)
+    check_device_asm(str(tmp_path), "good.hip", arch)
+    with pytest.raises(RuntimeError, match="dispatch packet"):
+        check_device_asm(str(tmp_path), "bad.hip", arch)
+    build = os.path.join(ROOT, "paper_2001_10635_amd", "_build")
+    if os.path.exists(os.path.join(build, f"mc-hip-amdgcn-amd-amdhsa-{arch}.s")):
+        check_device_asm(build, "mc.hip", arch)
