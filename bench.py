@@ -477,7 +477,7 @@ def next_rows_rd(rc, R, torch, p, x_lo, x_hi, p_lo, p_hi, ref_s, stream):
         "workload": "growth bound (Algorithm 2), RD chain n=2^26 FP64, 1000 RK4 steps "
                     "(center and half-width runs)",
         "state_steps_per_s": ss / sec, "seconds": round(sec, 4),
-        "vs_embedding_time": round(sec / ref_s, 3),
+        "vs_embedding_time": round(sec / ref_s, 3) if ref_s else None,
         "roofline": {"bound": "alu", "achieved": round(ops / sec / 1e12, 3),
                      "peak": FP64_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": round(ops / sec / FP64_PEAK, 4)}}
@@ -502,7 +502,7 @@ def next_rows_rd(rc, R, torch, p, x_lo, x_hi, p_lo, p_hi, ref_s, stream):
         "workload": "reach tube, RD chain n=2^26 FP64, 1000 RK4 steps, a box every 100 steps "
                     "(10 boxes, 10 GiB)",
         "state_steps_per_s": ss / sec, "seconds": round(sec, 4),
-        "vs_embedding_time": round(sec / ref_s, 3)}
+        "vs_embedding_time": round(sec / ref_s, 3) if ref_s else None}
     del t_lo, t_hi, wse
     torch.cuda.empty_cache()
     return out
@@ -651,10 +651,12 @@ def main():
     ap.add_argument("--heat-only", type=int, default=0, metavar="STEPS",
                     help="only run the 1000^3 heat grid for STEPS RK4 steps (profiling)")
     ap.add_argument("--heat-P", type=int, default=0, help="rows per wave of the heat kernel")
-    ap.add_argument("--only", choices=("mc", "ctm31", "batch", "latency", "user"), default=None,
+    ap.add_argument("--only", choices=("mc", "ctm31", "batch", "latency", "user", "next"),
+                    default=None,
                     help="only run one extra row (profiling): the Monte Carlo run, the 2^31 "
                          "FP32 chain (one call), one batch of the query mix, the 64-cell "
-                         "latency calls or the run-time compiled systems")
+                         "latency calls, the run-time compiled systems, or the growth bound "
+                         "and reach tube on the RD 2^26 workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of one embedding pass's bytes "
                          "(the reference kernel for HBM counter calibration)")
@@ -679,6 +681,14 @@ def main():
             out = latency_ctm64(rc, R, torch, workloads, reps=200, cpu=False)
         elif args.only == "ctm31":
             out = extra_ctm_2p31_f32(rc, R, torch, workloads, steps=1, cpu_oracle=False)
+        elif args.only == "next":
+            p = workloads.rd_2p26_f64()
+            lo, hi = p.box()
+            pl, ph = p.inputs()
+            out = next_rows_rd(rc, R, torch, p, torch.from_numpy(lo).cuda(),
+                               torch.from_numpy(hi).cuda(), torch.from_numpy(pl).cuda(),
+                               torch.from_numpy(ph).cuda(), None,
+                               torch.cuda.current_stream())
         else:
             out = batch_only(rc, R, torch, workloads, args.queries)
         print(json.dumps(out), flush=True)
