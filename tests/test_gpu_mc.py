@@ -88,7 +88,8 @@ def test_mc_sample_ranges_compose_bitwise(rc):
 def test_mc_wave_count_invariance_bitwise(rc):
     case = make_case("ctm", 200, np.float32, seed=8)
     outs = []
-    for waves in (1, 7, 64, 65, 0):
+    # 6, 7 and 65 leave 2, 3 and 1 waves in the last workgroup's fold
+    for waves in (1, 6, 7, 64, 65, 0):
         rc.set_option("mc.waves", waves)
         say(f"mc waves={waves}")
         outs.append(run_mc(rc, *case, 25, 300, 9)[:2])
@@ -98,8 +99,9 @@ def test_mc_wave_count_invariance_bitwise(rc):
 
 
 def test_mc_two_pass_reduction_at_the_wave_cap_bitwise(rc):
-    """4096 waves (64 chunks of 64 partials, reduced in two passes) and 100
-    waves give the same box; a wave count above the cap is clamped."""
+    """4096 waves (1024 workgroup partials: 4 chunks of 256, reduced in two
+    passes) and 100 waves (25 partials, one pass) give the same box; a wave
+    count above the cap is clamped."""
     case = make_case("rd", 130, np.float64, seed=12)
     outs = []
     for waves in (100, 4096, 10000):
