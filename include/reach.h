@@ -327,7 +327,8 @@ size_t reach_batch_workspace_bytes(int64_t nq);
  * On return *n_items holds the item count and item k runs the queries
  * member[item_start[k] .. item_start[k] + item_count[k]) (indices into q);
  * item_start, item_count and member are host arrays of nq entries.  ctx may
- * be NULL (then packing is on, as with the default options, and errors carry
+ * be NULL (then packing is on, as with the default options, a large plan
+ * runs on host threads started for the call, and errors carry
  * no message); with a context its "batch.split" option turns packing off as
  * it does for the batch.
  * Errors: those of reach_embed_rk4_batch's query checks, REACH_E_INVAL for

@@ -1401,7 +1401,14 @@ reach_status reach_plan_batch(reach_ctx* c, const reach_query* q, int64_t nq,
     std::vector<QDesc> descs((size_t)nq);
     std::vector<uint32_t> members;
     std::vector<BatchItem> items;
+    // without a context a large plan gets a pool of its own for this call,
+    // so the schedule is computed the same way as for the batch
+    std::unique_ptr<HostPool> local;
     HostPool* pool = host_pool(c);
+    if (!pool && batch_host_threads(nq) > 1) {
+        local.reset(new HostPool(batch_host_threads(nq)));
+        pool = local.get();
+    }
     const int nth = pool ? std::min(batch_host_threads(nq), pool->size()) : 1;
     const reach_status st = plan_batch(c, pool, q, nq, split, nth, descs.data(), &members, &items);
     if (st != REACH_OK) return st;

@@ -117,3 +117,15 @@ def test_plan_rejects_what_the_batch_rejects():
         R.reach_plan_batch(None, [neg])
     assert e.value.status == R.REACH_E_INVAL
     assert R.reach_plan_batch(None, []) == []
+
+
+def test_large_plan_without_context_rejects_a_bad_query_deep_inside():
+    """20000 queries are planned by several host threads (a pool of the
+    call's own when there is no context); one bad query anywhere fails the
+    whole plan with that query's status."""
+    qs = queries_of(workloads.query_stream(20000, 5.0e4, seed=99))
+    p = workloads.small_problem(workloads.KIND_CTM, 20, 3, 10)
+    qs[15001] = R.make_query(p.kind, 20, p.prm, R.REACH_F64, FAKE, FAKE, FAKE, FAKE, -0.1, 10)
+    with pytest.raises(R.ReachError) as e:
+        R.reach_plan_batch(None, qs)
+    assert e.value.status == R.REACH_E_INVAL
