@@ -272,6 +272,9 @@ static hipError_t by_E(int E, int S, bool pair, const EmbedPass& a, int64_t grid
                 case 8: return go_one_side<KIND, T, 8, MODE>(pair, a, grid, s);
                 case 16: return go_one_side<KIND, T, 16, MODE>(pair, a, grid, s);
                 case 24: return go_one_side<KIND, T, 24, MODE>(pair, a, grid, s);
+                case 28:   // FP64: the widest one-side tile within 256 VGPRs
+                    if constexpr (!F32) return go_one_side<KIND, T, 28, MODE>(pair, a, grid, s);
+                    else return hipErrorInvalidValue;
                 case 32: return go_one_side<KIND, T, 32, MODE>(pair, a, grid, s);
                 case 48:
                     if constexpr (F32) return go_one_side<KIND, T, 48, MODE>(pair, a, grid, s);
@@ -291,7 +294,7 @@ bool embed_has_shape(int kind, int dtype, int E, int S) {
         return E == 1 || E == 2 || E == 4 || E == 8 || E == 12 || E == 16 || (dtype == 1 && E == 32);
     if (S == 1 && kind != K_LIN3)
         return E == 1 || E == 2 || E == 4 || E == 8 || E == 16 || E == 24 || E == 32 ||
-               (dtype == 1 && (E == 48 || E == 64));
+               (dtype == 0 && E == 28) || (dtype == 1 && (E == 48 || E == 64));
     return false;
 }
 int embed_max_E(int dtype, int S) {

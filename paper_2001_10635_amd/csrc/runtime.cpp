@@ -279,7 +279,7 @@ TuneEntry tuned(const reach_ctx* c, int kind, int dtype, int64_t n) {
 }
 
 int smallest_E(int kind, int dtype, int S, int64_t n) {
-    for (int E : {1, 2, 4, 8, 12, 16, 24, 32, 48, 64})
+    for (int E : {1, 2, 4, 8, 12, 16, 24, 28, 32, 48, 64})
         if (embed_has_shape(kind, dtype, E, S) && (int64_t)64 * E >= n) return E;
     return 0;
 }
@@ -649,7 +649,8 @@ reach_status reach_set_option(reach_ctx* c, const char* key, int64_t value) {
     if (!known) return fail(c, REACH_E_INVAL, "unknown option %s", key);
     if (value < 0) return fail(c, REACH_E_INVAL, "option %s must be >= 0", key);
     if (!std::strcmp(key, "embed.E") && value && !embed_has_shape(REACH_CTM, REACH_F32, (int)value, 2) &&
-        !embed_has_shape(REACH_CTM, REACH_F32, (int)value, 1))
+        !embed_has_shape(REACH_CTM, REACH_F32, (int)value, 1) &&
+        !embed_has_shape(REACH_CTM, REACH_F64, (int)value, 1))
         return fail(c, REACH_E_INVAL, "embed.E = %lld not built", (long long)value);
     if (!std::strcmp(key, "embed.S") && value != 0 && value != 1 && value != 2)
         return fail(c, REACH_E_INVAL, "embed.S must be 0, 1 or 2");
@@ -836,7 +837,7 @@ reach_status reach_autotune_embed(reach_ctx* c, const reach_system* s, reach_dty
         return autotune_heat3d(c, s, dtype, x_lo, x_hi, dt, trial_steps, r_lo, r_hi, ws, ws_bytes,
                                hs, best);
     const int64_t saveE = opt_get(c, "embed.E"), saveK = opt_get(c, "embed.K");
-    static const int Es[] = {4, 8, 12, 16, 24, 32, 48, 64};
+    static const int Es[] = {4, 8, 12, 16, 24, 28, 32, 48, 64};
     static const int Ks[] = {2, 4, 6, 8, 10, 12, 16, 20, 24};
     const int64_t saveS = opt_get(c, "embed.S");
     hipEvent_t e0, e1;
