@@ -260,10 +260,15 @@ struct EmbedPlan {
 
 // Defaults measured on MI355X for the 2^26-cell chains (overridden by the
 // autotuner or its cache).  Cooperative chains run one side per wave.
-TuneEntry default_tune(int kind, int dtype) {
+// Measured defaults per system, dtype and input mode (cell_in: per-cell inputs).
+TuneEntry default_tune(int kind, int dtype, bool cell_in) {
     if (kind == REACH_HEAT3D) return TuneEntry{2, 1, 1};   // rows per wave, 16 waves per block
     if (kind == REACH_LIN3) return dtype == REACH_F64 ? TuneEntry{12, 12, 2} : TuneEntry{16, 8, 2};
-    return dtype == REACH_F64 ? TuneEntry{24, 20, 1} : TuneEntry{48, 12, 1};
+    if (dtype == REACH_F32) return TuneEntry{48, 12, 1};
+    // RD with shared inputs fits 28 cells per lane in 256 VGPRs; the CTM
+    // chain and per-cell inputs need more there and stay at 24
+    if (kind == REACH_RD && !cell_in) return TuneEntry{28, 24, 1};
+    return TuneEntry{24, 20, 1};
 }
 
 int n_bucket(int64_t n) {
@@ -272,10 +277,10 @@ int n_bucket(int64_t n) {
     return b;
 }
 
-TuneEntry tuned(const reach_ctx* c, int kind, int dtype, int64_t n) {
+TuneEntry tuned(const reach_ctx* c, int kind, int dtype, int64_t n, bool cell_in) {
     auto it = c->tune.find({kind, dtype, n_bucket(n)});
     if (it != c->tune.end()) return it->second;
-    return default_tune(kind, dtype);
+    return default_tune(kind, dtype, cell_in);
 }
 
 int smallest_E(int kind, int dtype, int S, int64_t n) {
@@ -288,7 +293,7 @@ reach_status plan_embed(reach_ctx* c, const reach_system* s, reach_dtype dtype, 
                         EmbedPlan* p) {
     const int64_t n = s->n;
     const int64_t oE = opt_get(c, "embed.E"), oK = opt_get(c, "embed.K"), oS = opt_get(c, "embed.S");
-    const TuneEntry te = tuned(c, s->kind, dtype, n);
+    const TuneEntry te = tuned(c, s->kind, dtype, n, s->n_in > 1);
     int S = oS ? (int)oS : (oE ? (s->kind == REACH_LIN3 ? 2 : te.S) : te.S);
     if (s->kind == REACH_LIN3 && S == 1)
         return fail(c, REACH_E_INVAL, "the coupled LIN3 chain needs both sides per wave");
@@ -346,7 +351,7 @@ int heat_waves(int P) {
 
 reach_status plan_heat(reach_ctx* c, const reach_system* s, reach_dtype dtype, HeatPlan* p) {
     int P = (int)opt_get(c, "heat.P");
-    if (!P) P = tuned(c, REACH_HEAT3D, dtype, s->n).E;
+    if (!P) P = tuned(c, REACH_HEAT3D, dtype, s->n, false).E;
     const int WV = heat_waves(P);
     if (!WV || !heat_has_shape(dtype == REACH_F64 ? 0 : 1, P, WV))
         return fail(c, REACH_E_INVAL, "heat.P = %d not built for this dtype", P);
@@ -867,7 +872,7 @@ reach_status reach_autotune_embed(reach_ctx* c, const reach_system* s, reach_dty
         return r;
     };
     // coarse scan of every built shape, then the four fastest and the default
-    // shape again with five times the steps
+    // shape again with ten times the steps, fastest of five calls each
     std::vector<std::pair<double, TuneEntry>> scan;
     st = REACH_OK;
     for (int S : {2, 1})
@@ -889,7 +894,7 @@ reach_status reach_autotune_embed(reach_ctx* c, const reach_system* s, reach_dty
                          [](const auto& a, const auto& b) { return a.first < b.first; });
         std::vector<TuneEntry> finals;
         for (size_t q = 0; q < scan.size() && q < 4; ++q) finals.push_back(scan[q].second);
-        const TuneEntry d = default_tune(s->kind, dtype);
+        const TuneEntry d = default_tune(s->kind, dtype, s->n_in > 1);
         bool have_d = false;
         for (const auto& f : finals) have_d |= (f.E == d.E && f.K == d.K && f.S == d.S);
         for (const auto& q : scan)
@@ -899,7 +904,7 @@ reach_status reach_autotune_embed(reach_ctx* c, const reach_system* s, reach_dty
             }
         for (const auto& f : finals) {
             double ps = 0;
-            st = time_shape(f, 5 * trial_steps, 3, &ps);
+            st = time_shape(f, 10 * trial_steps, 5, &ps);
             if (st != REACH_OK) break;
             if (ps < best_ps) { best_ps = ps; bt = f; }
         }
