@@ -144,12 +144,15 @@ static hipError_t gb_by_E(int E, const GbPass& a, int64_t grid, hipStream_t s) {
         case 8: return go_gb<KIND, T, 8, MODE>(a, grid, s);
         case 16: return go_gb<KIND, T, 16, MODE>(a, grid, s);
         case 24: return go_gb<KIND, T, 24, MODE>(a, grid, s);
+        case 28: return go_gb<KIND, T, 28, MODE>(a, grid, s);
         case 32: return go_gb<KIND, T, 32, MODE>(a, grid, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-bool gb_has_E(int E) { return E == 1 || E == 4 || E == 8 || E == 16 || E == 24 || E == 32; }
+bool gb_has_E(int E) {
+    return E == 1 || E == 4 || E == 8 || E == 16 || E == 24 || E == 28 || E == 32;
+}
 
 hipError_t launch_gb(int kind, int mode, int dtype, int E, const GbPass& a, int64_t grid,
                      hipStream_t s) {

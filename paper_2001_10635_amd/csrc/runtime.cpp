@@ -318,6 +318,12 @@ reach_status plan_embed(reach_ctx* c, const reach_system* s, reach_dtype dtype, 
     int K = oK ? (int)oK : te.K;
     if (K < 1) K = 1;
     if ((int64_t)8 * K >= span) return fail(c, REACH_E_INVAL, "K = %d too large for E = %d", K, E);
+    if (!oK && nsteps > 0) {
+        // the same number of passes with the steps spread evenly: a smaller
+        // halo (e.g. 100 steps at K = 24 run as 5 passes of 20, not 4 x 24 + 4)
+        const int64_t passes = (nsteps + K - 1) / K;
+        K = (int)((nsteps + passes - 1) / passes);
+    }
     p->K = K;
     p->H = 4 * K;
     p->OUT = span - 2 * p->H;
@@ -1044,10 +1050,12 @@ reach_status reach_growth_bound(reach_ctx* c, const reach_system* s, reach_dtype
     const int64_t n = s->n;
     bool single = false;
     if (!E) {
-        for (int e : {1, 4, 8, 16, 24, 32})
+        for (int e : {1, 4, 8, 16, 24, 28, 32})
             if ((int64_t)64 * e >= n) { E = e; break; }
         if (E && !K) single = true;
-        if (!E) E = dtype == REACH_F64 ? 24 : 32;
+        // FP64 with shared inputs fits 28 cells per lane in 256 VGPRs (two
+        // waves per SIMD); per-cell inputs need more there
+        if (!E) E = dtype == REACH_F64 ? (s->n_in > 1 ? 24 : 28) : 32;
     } else if ((int64_t)64 * E >= n && !K) {
         single = true;
     }
@@ -1066,9 +1074,10 @@ reach_status reach_growth_bound(reach_ctx* c, const reach_system* s, reach_dtype
         a.W = 1; a.OUT = 0; a.H = 0;
         passes = 1;
     } else {
-        // 20 steps per pass: the fastest on the 2^26 RD chain (1.27e12 state-steps/s
-        // at E = 24 against 1.21e12 at K = 12; K = 24 ties)
-        if (!K) K = 20;
+        // steps per pass, measured on the 2^26 RD chain (FP64, 1000 steps): at
+        // E = 24, K = 20 (104.1 ms; K = 12 is 5% slower, K = 24 ties); at E = 28,
+        // K = 24 (101.1 ms against 102.3 at K = 20 and 104.1 at K = 16)
+        if (!K) K = E == 28 ? 24 : 20;
         if ((int64_t)8 * K >= span) return fail(c, REACH_E_INVAL, "gb.K = %d too large for E = %d", K, E);
         a.H = 4 * K;
         a.OUT = span - 2 * a.H;

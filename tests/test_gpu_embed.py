@@ -338,7 +338,10 @@ def test_autotuner_picks_a_built_shape_and_keeps_results(rc):
     assert best["E"] in (4, 8, 12, 16, 24, 28, 32) and 8 * best["K"] < 64 * best["E"]
     assert best["S"] in (1, 2) and best["fs_per_state_step"] > 0
     plan = R.reach_plan_embed(rc.ctx, sysd, R.REACH_F64, 40)
-    assert (plan["E"], plan["K"], plan["S"]) == (best["E"], best["K"], best["S"])
+    # the plan keeps the tuned pass count and spreads the 40 steps evenly
+    passes = -(-40 // best["K"])
+    assert (plan["E"], plan["K"], plan["S"]) == (best["E"], -(-40 // passes), best["S"])
+    assert plan["passes"] == passes
     got = run_gpu(rc, kind, prm, lo, hi, pl, ph, dt, 40)
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
@@ -405,3 +408,21 @@ def test_reach_log_writes_one_json_record_per_call(capfd, monkeypatch):
     assert (e["n"], e["nsteps"], e["dtype"], e["kind"]) == (5000, 30, "f64", kind)
     assert (e["E"], e["K"], e["S"], e["passes"]) == (plan["E"], plan["K"], plan["S"], plan["passes"])
     assert (m["n"], m["m"], m["nsteps"]) == (300, 40, 5) and m["waves"] == 40
+
+
+def test_default_plan_spreads_steps_evenly_over_its_passes(rc):
+    """Without a forced K the plan keeps the default pass count and evens out
+    the steps per pass (a smaller halo); results do not depend on it."""
+    kind, prm, lo, hi, pl, ph, dt = make_case("rd", 200003, np.float64, seed=23)
+    sysd = R.make_system(kind, lo.size, prm, 1)
+    k_default = R.reach_plan_embed(rc.ctx, sysd, R.REACH_F64, 100000)["K"]
+    for nsteps in (1, 7, k_default + 1, 3 * k_default - 1, 100):
+        plan = R.reach_plan_embed(rc.ctx, sysd, R.REACH_F64, nsteps)
+        passes = -(-nsteps // k_default)
+        assert plan["passes"] == passes and plan["K"] == -(-nsteps // passes), (nsteps, plan)
+    say("even passes vs forced K")
+    a = run_gpu(rc, kind, prm, lo, hi, pl, ph, dt, k_default + 1)
+    rc.set_option("embed.K", k_default)
+    b = run_gpu(rc, kind, prm, lo, hi, pl, ph, dt, k_default + 1)
+    rc.set_option("embed.K", 0)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])

@@ -56,7 +56,7 @@ def test_gb_matches_oracle(rc, variant, n, dtype):
     assert_rel(g_hi, o_hi, rt, "upper")
 
 
-@pytest.mark.parametrize("E,K", [(1, 1), (4, 5), (8, 8), (16, 12), (24, 20), (32, 9)])
+@pytest.mark.parametrize("E,K", [(1, 1), (4, 5), (8, 8), (16, 12), (24, 20), (28, 13), (32, 9)])
 @pytest.mark.parametrize("variant", ["ctm", "rd", "lin3_cell"])
 def test_gb_multitile_matches_oracle(rc, variant, E, K):
     n, nsteps = 4001, 47
