@@ -260,17 +260,19 @@ struct EmbedPlan {
 
 // Defaults measured on MI355X for the 2^26-cell chains (overridden by the
 // autotuner or its cache).  Cooperative chains run one side per wave.
-// Measured defaults per system, dtype and input mode (cell_in: per-cell inputs).
-TuneEntry default_tune(int kind, int dtype, bool cell_in) {
+// Measured defaults per system, dtype, input mode (cell_in: per-cell inputs)
+// and size.
+TuneEntry default_tune(int kind, int dtype, bool cell_in, int64_t n) {
     if (kind == REACH_HEAT3D) return TuneEntry{2, 1, 1};   // rows per wave, 16 waves per block
     if (kind == REACH_LIN3) return dtype == REACH_F64 ? TuneEntry{12, 12, 2} : TuneEntry{16, 8, 2};
     if (dtype == REACH_F32) return TuneEntry{48, 12, 1};
-    // RD with shared inputs fits 28 cells per lane in 256 VGPRs; the CTM
-    // chain and per-cell inputs need more there and stay at 24
-    if (kind == REACH_RD && !cell_in) return TuneEntry{28, 24, 1};
+    // RD with shared inputs fits 28 cells per lane in 256 VGPRs (the CTM
+    // chain and per-cell inputs need more there).  The wider tile pays on
+    // long chains (2^26: 1.5% faster); below that its fewer waves leave a
+    // larger share of the last round empty (2^24: 5% slower than 24).
+    if (kind == REACH_RD && !cell_in && n >= ((int64_t)1 << 26)) return TuneEntry{28, 24, 1};
     return TuneEntry{24, 20, 1};
 }
-
 int n_bucket(int64_t n) {
     int b = 0;
     while (((int64_t)1 << (b + 1)) <= n) ++b;
@@ -280,7 +282,7 @@ int n_bucket(int64_t n) {
 TuneEntry tuned(const reach_ctx* c, int kind, int dtype, int64_t n, bool cell_in) {
     auto it = c->tune.find({kind, dtype, n_bucket(n)});
     if (it != c->tune.end()) return it->second;
-    return default_tune(kind, dtype, cell_in);
+    return default_tune(kind, dtype, cell_in, n);
 }
 
 int smallest_E(int kind, int dtype, int S, int64_t n) {
@@ -900,7 +902,7 @@ reach_status reach_autotune_embed(reach_ctx* c, const reach_system* s, reach_dty
                          [](const auto& a, const auto& b) { return a.first < b.first; });
         std::vector<TuneEntry> finals;
         for (size_t q = 0; q < scan.size() && q < 4; ++q) finals.push_back(scan[q].second);
-        const TuneEntry d = default_tune(s->kind, dtype, s->n_in > 1);
+        const TuneEntry d = default_tune(s->kind, dtype, s->n_in > 1, s->n);
         bool have_d = false;
         for (const auto& f : finals) have_d |= (f.E == d.E && f.K == d.K && f.S == d.S);
         for (const auto& q : scan)
@@ -1054,8 +1056,9 @@ reach_status reach_growth_bound(reach_ctx* c, const reach_system* s, reach_dtype
             if ((int64_t)64 * e >= n) { E = e; break; }
         if (E && !K) single = true;
         // FP64 with shared inputs fits 28 cells per lane in 256 VGPRs (two
-        // waves per SIMD); per-cell inputs need more there
-        if (!E) E = dtype == REACH_F64 ? (s->n_in > 1 ? 24 : 28) : 32;
+        // waves per SIMD; per-cell inputs need more there), which pays on long
+        // chains only (see default_tune)
+        if (!E) E = dtype == REACH_F64 ? (s->n_in > 1 || n < ((int64_t)1 << 26) ? 24 : 28) : 32;
     } else if ((int64_t)64 * E >= n && !K) {
         single = true;
     }
