@@ -516,15 +516,17 @@ reach_status autotune_heat3d(reach_ctx* c, const reach_system* s, reach_dtype dt
         c->opt["heat.P"] = P;
         st = embed_heat3d(c, s, dtype, x_lo, x_hi, dt, trial_steps, r_lo, r_hi, ws, ws_bytes, hs);
         if (st != REACH_OK) break;
-        hipEventRecord(e0, hs);
+        if (hipEventRecord(e0, hs) != hipSuccess) { st = REACH_E_DEVICE; break; }
         for (int rep = 0; rep < 2 && st == REACH_OK; ++rep)
             st = embed_heat3d(c, s, dtype, x_lo, x_hi, dt, trial_steps, r_lo, r_hi, ws, ws_bytes,
                               hs);
-        hipEventRecord(e1, hs);
         if (st != REACH_OK) break;
-        if (hipEventSynchronize(e1) != hipSuccess) { st = REACH_E_DEVICE; break; }
+        if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+            st = REACH_E_DEVICE;
+            break;
+        }
         float ms = 0.f;
-        hipEventElapsedTime(&ms, e0, e1);
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { st = REACH_E_DEVICE; break; }
         const double ps = (double)ms * 1e9 / (2.0 * 2.0 * (double)s->n * (double)trial_steps);
         if (ps < best_ps) { best_ps = ps; bestP = P; }
     }
@@ -867,13 +869,13 @@ reach_status reach_autotune_embed(reach_ctx* c, const reach_system* s, reach_dty
                                          r_lo, r_hi, ws, ws_bytes, stream);
         double best_ms = 1e300;
         for (int rep = 0; rep < reps && r == REACH_OK; ++rep) {
-            hipEventRecord(e0, hs);
+            if (hipEventRecord(e0, hs) != hipSuccess) return REACH_E_DEVICE;
             r = reach_embed_rk4(c, s, dtype, x_lo, x_hi, p_lo, p_hi, 0.0, dt, steps, r_lo, r_hi,
                                 ws, ws_bytes, stream);
-            hipEventRecord(e1, hs);
-            if (hipEventSynchronize(e1) != hipSuccess) return REACH_E_DEVICE;
+            if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return REACH_E_DEVICE;
             float ms = 0.f;
-            hipEventElapsedTime(&ms, e0, e1);
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return REACH_E_DEVICE;
             best_ms = std::min(best_ms, (double)ms);
         }
         *ps = best_ms * 1e9 / (2.0 * (double)s->n * (double)steps);
