@@ -182,6 +182,11 @@ def test_batch_rejections_and_flags(rc):
     R.reach_embed_rk4_batch(rc.ctx, [good, qb], ws, 1 << 20, 0)
     assert rc.sync() == R.REACH_E_NONFINITE
     assert rc.sync() == R.REACH_OK
+    # an empty batch launches nothing and succeeds, with or without a workspace
+    assert R.reach_embed_rk4_batch(rc.ctx, [], ws, 1 << 20, 0) == R.REACH_OK
+    assert R.reach_embed_rk4_batch(rc.ctx, [], None, 0, 0) == R.REACH_OK
+    assert R.reach_embed_rk4_each(rc.ctx, []) == R.REACH_OK
+    assert rc.sync() == R.REACH_OK
 
 
 def packed_ctm_batch(nq, seed):
