@@ -166,14 +166,27 @@ __global__ __launch_bounds__(PAIR ? 2 * WAVE : WAVE) void embed_tile_kernel(Embe
     const SysPrm<T> P = make_prm<T>(a.prm);
     const Steps<T> st = {(T)a.h2, (T)a.dt, (T)a.dt6};
 
-    if (reaches_end) {
-        // the window holding cell n-1 (cells past it, if any, are ghosts)
-        const int64_t left = a.n - (ts + (int64_t)lane * E);
-        Mask<E, true, true> M{(int)(left < 0 ? 0 : (left > E ? E : left))};
-        rk4_steps<KIND, T, E, S, MODE>(y, a.ksteps, P, U, st, M);
-    } else {
-        Mask<E, false, false> M{E};
-        rk4_steps<KIND, T, E, S, MODE>(y, a.ksteps, P, U, st, M);
+    bool exact = false;
+    if constexpr (PAIR) {
+        // a single window filled exactly (n = 64E): the chain's end is lane
+        // 63's last cell and no cell is padding, so no per-stage masking (the
+        // latency path: every select saved shortens the dependent chain)
+        exact = a.n - ts == span;
+        if (exact) {
+            Mask<E, false, true> M{E};
+            rk4_steps<KIND, T, E, S, MODE>(y, a.ksteps, P, U, st, M);
+        }
+    }
+    if (!exact) {
+        if (reaches_end) {
+            // the window holding cell n-1 (cells past it, if any, are ghosts)
+            const int64_t left = a.n - (ts + (int64_t)lane * E);
+            Mask<E, true, true> M{(int)(left < 0 ? 0 : (left > E ? E : left))};
+            rk4_steps<KIND, T, E, S, MODE>(y, a.ksteps, P, U, st, M);
+        } else {
+            Mask<E, false, false> M{E};
+            rk4_steps<KIND, T, E, S, MODE>(y, a.ksteps, P, U, st, M);
+        }
     }
 
     const int olo = (w == 0) ? 0 : a.H;
