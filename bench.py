@@ -812,30 +812,35 @@ def main():
             R.reach_embed_rk4(rc.ctx, sysd, R.REACH_F64, x_lo, x_hi, p_lo, p_hi, 0.0, p.dt, nk,
                               r_lo, r_hi, ws, nbytes, stream)
             torch.cuda.synchronize()
-            ev0.record(stream)
-            R.reach_embed_rk4(rc.ctx, sysd, R.REACH_F64, x_lo, x_hi, p_lo, p_hi, 0.0, p.dt, nk,
-                              r_lo, r_hi, ws, nbytes, stream)
-            ev1.record(stream)
-            torch.cuda.synchronize()
-            t = ev0.elapsed_time(ev1) / 1e3 / plan1["passes"]
-            if best is None or t < best[0]:
-                best = (t, plan1)
+            for _ in range(3):      # the fastest of three calls, as for the copy below
+                ev0.record(stream)
+                R.reach_embed_rk4(rc.ctx, sysd, R.REACH_F64, x_lo, x_hi, p_lo, p_hi, 0.0, p.dt,
+                                  nk, r_lo, r_hi, ws, nbytes, stream)
+                ev1.record(stream)
+                torch.cuda.synchronize()
+                t = ev0.elapsed_time(ev1) / 1e3 / plan1["passes"]
+                if best is None or t < best[0]:
+                    best = (t, plan1)
         t1, plan1 = best
         rc.set_option("embed.E", args.E)
         # the device's plain-copy rate for the same bytes (two arrays of n
         # doubles in, two out), the practical ceiling of any HBM stream
         c_in = torch.empty(2 * p.n, dtype=torch.float64, device="cuda")
         c_out = torch.empty_like(c_in)
+        tc = None
         with torch.cuda.stream(stream):
             for _ in range(3):
                 c_out.copy_(c_in)
-            ev0.record(stream)
-            for _ in range(10):
-                c_out[:p.n].copy_(c_in[:p.n])
-                c_out[p.n:].copy_(c_in[p.n:])
-            ev1.record(stream)
+            for _ in range(3):      # the fastest of three rounds of 5
+                ev0.record(stream)
+                for _ in range(5):
+                    c_out[:p.n].copy_(c_in[:p.n])
+                    c_out[p.n:].copy_(c_in[p.n:])
+                ev1.record(stream)
+                ev1.synchronize()
+                t = ev0.elapsed_time(ev1) / 1e3 / 5
+                tc = t if tc is None else min(tc, t)
         torch.cuda.synchronize()
-        tc = ev0.elapsed_time(ev1) / 1e3 / 10
         del c_in, c_out
         stream_k1 = {"E": plan1["E"], "launch_us": round(t1 * 1e6, 1),
                      "achieved_GBps": round(bytes_per_launch / t1 / 1e9, 1),
