@@ -28,6 +28,9 @@ sys.path.insert(0, ROOT)
 HBM_PEAK = 8.0e12            # B/s, MI355X HBM3E
 FP64_PEAK = 78.6e12          # FLOP/s, MI355X FP64 vector (FMA = 2 flops)
 FP32_PEAK = 157.3e12         # FLOP/s, MI355X FP32 vector (published, packed)
+# VALU lane-instruction issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (a wave64 vector instruction occupies a SIMD for four cycles)
+VALU_LANE_PEAK = 256 * 4 * 16 * 2.4e9
 # Algorithmic FP64 operations of one RK4 state-step of the RD chain (an FMA
 # counts 2): four right-hand sides of 8 (two adds, a scaling by 1/h^2, 2*y,
 # y^3 as two products, the input and the reaction term), three stage inputs
@@ -63,9 +66,9 @@ def source_hash(files=EMBED_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(name="embed_tile_kernel_rd2p26_f64_pmc.txt", files=EMBED_SOURCES):
-    """HBM bytes per launch from a committed PMC summary, if it was taken on
-    the current kernel source (else None)."""
+def profile_value(name, key, files=EMBED_SOURCES):
+    """A figure of a committed PMC summary, if the summary was taken on the
+    current kernel source (else None)."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -77,9 +80,54 @@ def traffic_from_profile(name="embed_tile_kernel_rd2p26_f64_pmc.txt", files=EMBE
     if vals.get("source_hash") != source_hash(files):
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def traffic_from_profile(name="embed_tile_kernel_rd2p26_f64_pmc.txt", files=EMBED_SOURCES):
+    """HBM bytes per launch from a committed PMC summary (None if stale)."""
+    return profile_value(name, "hbm_bytes_per_launch", files)
+
+
+def hbm_probe(R, torch, n, stream, reps=3):
+    """The HBM ceiling for one embedding pass's traffic: the project's stream
+    kernel (libreach_probe.so) copying two arrays of n doubles into two, over
+    its launch shapes (16-byte vectors in flight per thread, non-temporal or
+    not, grid size); the fastest shape, timed as the fastest of `reps` calls."""
+    P = R.probe_lib()
+    a = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    nbytes = 8 * n
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sp = stream.cuda_stream
+    best, table = None, []
+    for unroll in (1, 2, 4, 8):
+        for nt in (0, 1):
+            for blocks in (cus * 4, cus * 8, cus * 16, cus * 32, -(-nbytes // (16 * 256 * unroll))):
+                args = (a.data_ptr(), a.data_ptr() + nbytes, b.data_ptr(), b.data_ptr() + nbytes,
+                        nbytes, unroll, nt, int(blocks), sp)
+                assert P.reach_probe_stream2(*args) == 0
+                t = None
+                for _ in range(reps):
+                    ev0.record(stream)
+                    P.reach_probe_stream2(*args)
+                    ev1.record(stream)
+                    ev1.synchronize()
+                    dt = ev0.elapsed_time(ev1) / 1e3
+                    t = dt if t is None else min(t, dt)
+                table.append((unroll, nt, int(blocks), t))
+                if best is None or t < best[3]:
+                    best = (unroll, nt, int(blocks), t)
+    ok = bool(torch.equal(a, b))
+    del a, b
+    gbps = 4.0 * nbytes / best[3] / 1e9
+    return {"kernel": "stream2_kernel (libreach_probe.so)", "unroll": best[0],
+            "nontemporal": bool(best[1]), "blocks": best[2], "us": round(best[3] * 1e6, 1),
+            "GBps": round(gbps, 1), "frac": round(gbps * 1e9 / HBM_PEAK, 4),
+            "copy_correct": ok, "shapes_timed": len(table)}
 
 
 def cpu_model() -> str:
@@ -231,7 +279,9 @@ def query_mix(rc, R, torch, workloads, nq, cpu=True):
     log(f"batch {out['batch']}, per-query launches {out['one_launch_per_query']}")
     del d_lo, d_hi, r_lo, r_hi, wsb
 
-    # online: host arrays, Poisson arrivals
+    # online: host arrays, Poisson arrivals; each query is submitted at its
+    # scheduled arrival (or as soon after it as the client gets to it) and its
+    # latency counts from the scheduled arrival to its box in host memory
     o_lo = np.empty(tot)
     o_hi = np.empty(tot)
     hq = [qstruct(i, h_lo.ctypes.data, h_hi.ctypes.data, o_lo.ctypes.data, o_hi.ctypes.data,
@@ -239,19 +289,27 @@ def query_mix(rc, R, torch, workloads, nq, cpu=True):
           for i in range(nq)]
     arrivals = np.array([q.arrival for q in qs])
     pool = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
-    for mode, name in ((0, "served_persistent"), (1, "served_launch_per_query")):
+
+    def serve(mode, count, rate_scale):
         rc.set_option("serve.mode", mode)
         o_lo.fill(np.nan)
+        sched = arrivals[:count] * rate_scale
         R.reach_server_start(rc.ctx, pool, pool.numel(), 1024)
         tickets = []
+        lag = longest = 0.0
+        t_lib = R.reach_clock_us()
         t0 = time.perf_counter()
         i = 0
-        while i < nq:
+        while i < count:
             now = time.perf_counter() - t0
-            while i < nq and arrivals[i] <= now:
-                tickets.append(R.reach_submit(rc.ctx, hq[i]))
+            while i < count and sched[i] <= now:
+                ts = time.perf_counter()
+                tickets.append(R.reach_submit_at(rc.ctx, hq[i], t_lib + sched[i] * 1e6))
+                te = time.perf_counter()
+                lag = max(lag, ts - t0 - sched[i])
+                longest = max(longest, te - ts)
                 i += 1
-        pending = list(tickets)
+        pending = tickets
         while pending:
             nxt = []
             for tk in pending:
@@ -264,11 +322,29 @@ def query_mix(rc, R, torch, workloads, nq, cpu=True):
         wall = time.perf_counter() - t0
         stats = R.reach_server_stats(rc.ctx)
         R.reach_server_stop(rc.ctx)
-        same = bool(np.array_equal(o_lo, ref_lo))
-        out[name] = {"queries_per_s": nq / wall, "p50_us": round(stats["p50_us"], 1),
-                     "p99_us": round(stats["p99_us"], 1), "max_us": round(stats["max_us"], 1),
-                     "equals_batch": same}
+        offered = count / sched[count - 1] if count > 1 else float("nan")
+        same = bool(np.array_equal(o_lo[:offs[count]], ref_lo[:offs[count]]))
+        return {"queries": count, "offered_per_s": round(offered, 1),
+                "queries_per_s": count / wall, "p50_us": round(stats["p50_us"], 1),
+                "p99_us": round(stats["p99_us"], 1), "max_us": round(stats["max_us"], 1),
+                "latency_from": "scheduled arrival to box in host memory",
+                "client_max_lag_us": round(lag * 1e6, 1),
+                "client_longest_submit_us": round(longest * 1e6, 1),
+                "equals_batch": same}
+
+    for mode, name in ((0, "served_persistent"), (1, "served_launch_per_query")):
+        out[name] = serve(mode, nq, 1.0)
         log(f"{name}: {out[name]}")
+    # launch per query cannot keep up with 5e4/s: its latency then grows with
+    # the backlog.  Its rate under that overload is the most it sustains; the
+    # same stream slowed to 80% of that rate (the first 2 s of it) gives its
+    # latency at a load it can carry.
+    lpq = out["served_launch_per_query"]
+    if lpq["queries_per_s"] < 0.95 * lpq["offered_per_s"]:
+        scale = lpq["offered_per_s"] / (0.8 * lpq["queries_per_s"])
+        count = int(min(nq, np.searchsorted(arrivals * scale, 2.0)))
+        out["served_launch_per_query_at_80pct_of_its_max"] = serve(1, count, scale)
+        log(f"launch per query slowed: {out['served_launch_per_query_at_80pct_of_its_max']}")
     rc.set_option("serve.mode", 0)
     if cpu:
         out["cpu_oracle"] = oracle_queries(qs, h_lo, h_hi, offs, u_lo, u_hi, min(nq, 2000))
@@ -614,20 +690,30 @@ def extra_mc_ctm4096(rc, R, torch, workloads, cpu_samples):
     ratio = (g_mx - g_mn) / np.maximum(e_hi - e_lo, np.finfo(np.float64).tiny)
     out["containment"] = {
         "violations": int(np.sum(g_mn < e_lo - slack_lo) + np.sum(g_mx > e_hi + slack_hi)),
+        "violations_without_slack": int(np.sum(g_mn < e_lo) + np.sum(g_mx > e_hi)),
         "cells": int(p.n), "slack": "1e-5 max(|x|, 1)",
         "width_ratio_mc_over_embedding": {"mean": round(float(ratio.mean()), 4),
                                           "min": round(float(ratio.min()), 4),
                                           "max": round(float(ratio.max()), 4)}}
     if cpu_samples:
+        # the GPU on the same sample prefix, compared with the oracle's result
+        s_mn, s_mx = rc.montecarlo(p.kind, p.prm, x_lo, x_hi, p.dt, p.nsteps, cpu_samples,
+                                   p.seed)
+        assert rc.sync() == R.REACH_OK
         t = time.perf_counter()
-        oracle.montecarlo(p.kind, p.prm, lo.astype(np.float64), hi.astype(np.float64), dt=p.dt,
-                          nsteps=p.nsteps, m=cpu_samples, seed=p.seed, ubits=24)
+        o_mn, o_mx = oracle.montecarlo(p.kind, p.prm, lo.astype(np.float64),
+                                       hi.astype(np.float64), dt=p.dt, nsteps=p.nsteps,
+                                       m=cpu_samples, seed=p.seed, ubits=24)
         el = time.perf_counter() - t
+        err = max(float(np.max(np.abs(g.double().cpu().numpy() - o) / np.maximum(np.abs(o), 1.0)))
+                  for g, o in ((s_mn, o_mn), (s_mx, o_mx)))
         out["cpu_baseline"] = {"value": float(p.n) * cpu_samples * p.nsteps / el,
                                "unit": "cell-steps/s", "kind": "oracle", "seconds": round(el, 2),
                                "cores": int(os.environ.get("OMP_NUM_THREADS",
                                                            os.cpu_count() or 1)),
-                               "sample": f"first {cpu_samples} of the 2^20 samples"}
+                               "sample": f"first {cpu_samples} of the 2^20 samples",
+                               "gpu_same_samples_max_rel_err": err,
+                               "gpu_same_samples_within_1e-5": bool(err <= 1e-5)}
     return out
 
 
@@ -657,6 +743,8 @@ def main():
                          "FP32 chain (one call), one batch of the query mix, the 64-cell "
                          "latency calls, the run-time compiled systems, or the growth bound "
                          "and reach tube on the RD 2^26 workload")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="time the HBM stream probe over its shapes and print it (only)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain device copy of one embedding pass's bytes "
                          "(the reference kernel for HBM counter calibration)")
@@ -705,6 +793,9 @@ def main():
         return
 
     p = workloads.rd_2p26_f64()
+    if args.stream_probe:
+        print(json.dumps(hbm_probe(R, torch, p.n, torch.cuda.current_stream())), flush=True)
+        return
     if args.copy_probe:
         # one embedding pass reads 2n doubles and writes 2n doubles; a copy of
         # 2n doubles moves exactly the same bytes
@@ -784,8 +875,16 @@ def main():
     alu_ach = flops_per_launch / launch_s
     hbm_frac, alu_frac = hbm_ach / HBM_PEAK, alu_ach / FP64_PEAK
     traffic = traffic_from_profile()
+    # VALU issue: rocprof lane instructions per state-step (PMC summary of the
+    # same kernel source) times this run's state-steps per second of launch
+    lanes_per_ss = profile_value("embed_tile_kernel_rd2p26_f64_pmc.txt",
+                                 "valu_lane_instructions_per_state_step")
+    ss_per_launch_s = 2.0 * p.n * (p.nsteps / plan["passes"]) / launch_s
     extra_roof = {"kernel": "embed_tile_kernel<RD,double>", "launch_us": round(launch_s * 1e6, 1),
                   "algorithmic_GBps": round(hbm_ach / 1e9, 1),
+                  "valu_lane_instructions_per_state_step": lanes_per_ss,
+                  "valu_issue_frac": (round(lanes_per_ss * ss_per_launch_s / VALU_LANE_PEAK, 4)
+                                      if lanes_per_ss else None),
                   # rocprof DRAM bytes (read + write) per launch over this launch time
                   "hbm_frac_measured": (round(traffic / launch_s / HBM_PEAK, 4)
                                         if traffic else None)}
@@ -842,13 +941,17 @@ def main():
                 tc = t if tc is None else min(tc, t)
         torch.cuda.synchronize()
         del c_in, c_out
+        probe = hbm_probe(R, torch, p.n, stream)
+        log(f"HBM stream probe: {probe}")
         stream_k1 = {"E": plan1["E"], "launch_us": round(t1 * 1e6, 1),
                      "achieved_GBps": round(bytes_per_launch / t1 / 1e9, 1),
                      "frac": round(bytes_per_launch / t1 / HBM_PEAK, 4),
                      "state_steps_per_s": 2.0 * p.n / t1,
                      "device_copy_us": round(tc * 1e6, 1),
                      "device_copy_GBps": round(bytes_per_launch / tc / 1e9, 1),
-                     "frac_of_device_copy": round(tc / t1, 4)}
+                     "frac_of_device_copy": round(tc / t1, 4),
+                     "stream_probe": probe,
+                     "frac_of_stream_probe": round(probe["us"] / 1e6 / t1, 4)}
         rc.set_option("embed.K", args.K)
         assert rc.sync(stream) == R.REACH_OK
         log(f"K=1 stream: {stream_k1}")

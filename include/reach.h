@@ -103,19 +103,26 @@ enum { REACH_F64 = 0, REACH_F32 = 1 };
 
 enum { REACH_CTM = 1, REACH_RD = 2, REACH_LIN3 = 3, REACH_HEAT3D = 4, REACH_USER = 5 };
 
-/* A system of the list above.  `reserved` must be 0. */
+/* Boundary conditions of a system: each kind has its own, stated with it above
+   (zero ghosts for RD, LIN3 and USER chains, zero inflow and free outflow for
+   the CTM, insulated faces and one open face for HEAT3D).  No other set is
+   built: any other value of reach_system.bc is REACH_E_UNSUPPORTED. */
+enum { REACH_BC_DEFAULT = 0 };
+
+/* A system of the list above. */
 typedef struct reach_system {
     int32_t kind;
-    int32_t reserved;
+    int32_t bc;       /* REACH_BC_DEFAULT */
     int64_t n;        /* number of cells (state dimension), 1 <= n < 2^40 */
-    int64_t n_in;     /* input dimension: 0, 1 or n */
+    int64_t n_in;     /* input dimension: 0, 1 or n (64-bit, since n_in = n may
+                         exceed 2^31) */
     double prm[8];    /* parameters, layout per kind (unused entries ignored) */
 } reach_system;
 
 /* One embedding query for the batch and serving entry points.  For
    reach_embed_rk4_batch all pointers are device pointers; for reach_submit
-   they are HOST pointers (inputs are copied at admission, r_lo / r_hi are
-   written before reach_poll reports completion). */
+   they are HOST pointers (inputs are copied before reach_submit returns,
+   r_lo / r_hi are written before reach_poll reports completion). */
 typedef struct reach_query {
     reach_system sys;
     reach_dtype dtype;     /* REACH_F64 (the batch and serving kernels are FP64) */
@@ -161,6 +168,9 @@ const char* reach_last_error(const reach_ctx* ctx);
      "batch.waves" resident waves of the batch kernel (0 = default)
      "batch.split" 1: one wave per side of each cooperative query (shorter
                   latency per query); 0 (default): one wave per query
+     "serve.mode" 0 (default): persistent serving kernel; 1: one launch per
+                  served query (read by reach_server_start)
+     "serve.waves" resident waves of the serving kernel (0 = default)
    Returns REACH_E_INVAL for an unknown key or a value out of range. */
 reach_status reach_set_option(reach_ctx* ctx, const char* key, int64_t value);
 int64_t reach_get_option(const reach_ctx* ctx, const char* key);
@@ -348,28 +358,55 @@ reach_status reach_embed_rk4_each(reach_ctx* ctx, const reach_query* q, int64_t 
  * Continuous batching.  reach_server_start launches a persistent kernel on
  * `stream` that keeps `max_slots` query slots; queries submitted while others
  * run are admitted as soon as a slot and enough bytes of the device `pool`
- * (caller-owned device memory, first-fit, 4 n 8 bytes per query) are free,
- * and run concurrently with them.  Admission order is submission order.
- *   reach_submit: HOST pointers in *q (inputs copied before return into
- *     pinned staging); *ticket receives the query's id.  REACH_E_NOMEM if
- *     the query can never fit the pool; REACH_E_BUSY if no server runs.
- *   reach_poll: REACH_PENDING until the query is done, then its final status
- *     (REACH_OK, REACH_E_NONFINITE, REACH_E_ORDER or REACH_E_CANCELLED) --
- *     r_lo / r_hi hold the box when it returns REACH_OK.  A ticket may be
- *     polled until it is reported done; after that it is forgotten.
- *   reach_cancel: drop a query that has not started (REACH_E_BUSY if it is
- *     already running or done).
- *   reach_server_stop: drain every admitted and waiting query, stop the
+ * (caller-owned device memory, first-fit, 2 n + 2 doubles per query, 256-byte
+ * aligned) are free, and run concurrently with them.  Admission order is
+ * submission order.  A service thread started by reach_server_start does the
+ * admission and completion work; the client calls below only append to its
+ * inbox or read its outbox under short locks, so they never wait for it.
+ *   reach_submit: HOST pointers in *q (inputs copied before return);
+ *     *ticket receives the query's id.  The query arrives at the call.
+ *     REACH_E_NOMEM if the query can never fit the pool; REACH_E_BUSY if no
+ *     server runs or it is stopping; REACH_E_INVAL / REACH_E_UNSUPPORTED as
+ *     reach_embed_rk4_batch for the query itself.
+ *   reach_submit_at: the same, with the query's arrival time given by the
+ *     caller in microseconds on the reach_clock_us() clock (for a client that
+ *     submits queries of a planned arrival schedule: their latency then counts
+ *     any delay of the client itself).  REACH_E_INVAL if it is not finite.
+ *   reach_poll: REACH_PENDING until the query is done, then REACH_OK with its
+ *     final status in *result (REACH_OK, REACH_E_NONFINITE, REACH_E_ORDER,
+ *     REACH_E_CANCELLED or, after a drain that ran out of time,
+ *     REACH_E_TIMEOUT); r_lo / r_hi hold the box when *result is REACH_OK.
+ *     A ticket is forgotten once it has been reported done (REACH_E_INVAL
+ *     afterwards and for unknown tickets).
+ *   reach_cancel: request that a query stop.  A waiting query is dropped; a
+ *     running one stops within kCancelEvery = 64 RK4 steps (the kernel reads
+ *     the query's host-written cancel word between blocks of steps).  Returns
+ *     REACH_OK when the request is recorded, REACH_E_BUSY if the query has
+ *     already finished, REACH_E_INVAL for an unknown ticket.  A query that
+ *     completes before the request takes effect reports its own status;
+ *     otherwise reach_poll reports REACH_E_CANCELLED and r_lo / r_hi are not
+ *     written.
+ *   reach_server_stop: drain every admitted and waiting query (bounded by
+ *     REACH_SERVER_DRAIN_S seconds without progress, default 60), stop the
  *     kernel and join the service thread.
- *   reach_server_stats: arrivals-to-completion latencies in microseconds of
- *     completed queries (p50, p99, max) and the count.
- * Every wave of the serving kernel exits when the host sets its stop flag,
- * and also after `REACH_SERVER_IDLE_S` seconds (default 120) without work,
- * so the kernel always drains.
+ *   reach_server_stats: latency in microseconds from arrival (see
+ *     reach_submit / reach_submit_at) to the box being in the caller's
+ *     arrays, of the queries completed so far, cancelled ones excepted
+ *     (p50, p99, max) and their count.
+ * The serving grid leaves as a whole when the host sets its stop flag or
+ * after `REACH_SERVER_IDLE_S` seconds (default 120) in which some wave saw no
+ * work, so the kernel always drains; the service thread starts a new grid
+ * for the next arrival and moves admitted queries to it.
+ * With the option "serve.mode" = 1 at reach_server_start, each admitted query
+ * is one kernel launch instead (the baseline of the persistent kernel).
  */
 reach_status reach_server_start(reach_ctx* ctx, void* pool, size_t pool_bytes,
                                 int32_t max_slots, void* stream);
 reach_status reach_submit(reach_ctx* ctx, const reach_query* q, uint64_t* ticket);
+reach_status reach_submit_at(reach_ctx* ctx, const reach_query* q, double arrival_us,
+                             uint64_t* ticket);
+/* Microseconds on the steady clock the server stamps latencies with.  Host only. */
+double reach_clock_us(void);
 reach_status reach_poll(reach_ctx* ctx, uint64_t ticket, reach_status* result);
 reach_status reach_cancel(reach_ctx* ctx, uint64_t ticket);
 reach_status reach_server_stop(reach_ctx* ctx);

@@ -42,7 +42,7 @@ class ReachError(RuntimeError):
 
 
 class reach_system(ctypes.Structure):
-    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("n", ctypes.c_int64),
+    _fields_ = [("kind", ctypes.c_int32), ("bc", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("n_in", ctypes.c_int64), ("prm", ctypes.c_double * 8)]
 
 
@@ -97,6 +97,8 @@ def lib() -> ctypes.CDLL:
         "reach_embed_rk4_each": ([vp, qp, i64, i32], i32),
         "reach_server_start": ([vp, vp, sz, i32, vp], i32),
         "reach_submit": ([vp, qp, P(u64)], i32),
+        "reach_submit_at": ([vp, qp, d, P(u64)], i32),
+        "reach_clock_us": ([], d),
         "reach_poll": ([vp, u64, P(i32)], i32),
         "reach_cancel": ([vp, u64], i32),
         "reach_server_stop": ([vp], i32),
@@ -115,6 +117,24 @@ def lib() -> ctypes.CDLL:
         f.restype = res
     _lib = L
     return L
+
+
+_probe = None
+
+
+def probe_lib():
+    """libreach_probe.so: the HBM stream probe of the benchmark (reach_probe.h)."""
+    global _probe
+    if _probe is None:
+        path = os.path.join(os.path.dirname(LIB_PATH), "libreach_probe.so")
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(path)
+        L.reach_probe_stream2.argtypes = [ctypes.c_void_p] * 4 + [
+            ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p]
+        L.reach_probe_stream2.restype = ctypes.c_int
+        _probe = L
+    return _probe
 
 
 # --------------------------------------------------------------- helpers
@@ -158,10 +178,10 @@ def _nsteps(nsteps, t0, t1, dt) -> int:
     return n
 
 
-def make_system(kind: int, n: int, prm, n_in: int = 0) -> reach_system:
+def make_system(kind: int, n: int, prm, n_in: int = 0, bc: int = 0) -> reach_system:
     s = reach_system()
     s.kind = int(kind)
-    s.reserved = 0
+    s.bc = int(bc)
     s.n = int(n)
     s.n_in = int(n_in)
     for i, v in enumerate(prm):
@@ -408,6 +428,17 @@ def reach_submit(ctx, q: reach_query) -> int:
     st = lib().reach_submit(ctx, ctypes.byref(q), ctypes.byref(t))
     _chk(ctx, st, "reach_submit")
     return int(t.value)
+
+
+def reach_submit_at(ctx, q: reach_query, arrival_us: float) -> int:
+    t = ctypes.c_uint64()
+    st = lib().reach_submit_at(ctx, ctypes.byref(q), float(arrival_us), ctypes.byref(t))
+    _chk(ctx, st, "reach_submit_at")
+    return int(t.value)
+
+
+def reach_clock_us() -> float:
+    return float(lib().reach_clock_us())
 
 
 def reach_poll(ctx, ticket: int):

@@ -14,6 +14,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 SO = os.path.join(HERE, "libreach.so")
+# the HBM ceiling probe of the benchmark, a library of its own
+PROBE_SRC = "hbm_probe.hip"
+PROBE_SO = os.path.join(HERE, "libreach_probe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
@@ -42,9 +45,10 @@ def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     jobs = min(len(SOURCES), max(1, (os.cpu_count() or 4)))
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        objs = list(ex.map(_compile, SOURCES + [PROBE_SRC]))
+    probe_obj = objs.pop()
     from .isa_check import check_device_asm
-    for src in SOURCES:
+    for src in SOURCES + [PROBE_SRC]:
         check_device_asm(BUILD, src, ARCH)
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", SO + ".tmp",
            "-lpthread", "-lhiprtc"]
@@ -52,8 +56,13 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
     os.replace(SO + ".tmp", SO)
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", probe_obj, "-o", PROBE_SO + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stderr}")
+    os.replace(PROBE_SO + ".tmp", PROBE_SO)
     if verbose:
-        print("built", SO)
+        print("built", SO, "and", PROBE_SO)
     return SO
 
 

@@ -16,13 +16,18 @@
 //   serve_kernel   persistent grid fed through a ring of descriptors in pinned
 //                  host memory; each wave claims the next work item (sequence
 //                  number and side), waits (bounded) until the host publishes
-//                  it, runs it and publishes that side's completion.  Waves
-//                  leave when the host sets the stop flag or after an idle
-//                  limit, so the grid always drains.
+//                  it, runs it and publishes that side's completion.  The grid
+//                  leaves as a whole when the host sets the stop flag or when
+//                  any wave reaches the idle limit, so it always drains.  A
+//                  served query reads its host-written cancel word every
+//                  kCancelEvery steps and stops early when it is set.
 #include "dev.hpp"
 #include "kernels.hpp"
 
 namespace reach {
+
+// Cancel word of the queries that have none (batches, single launches).
+__device__ unsigned int g_never_cancelled = 0u;
 
 __device__ __forceinline__ uint64_t wave_bcast(uint64_t v) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
@@ -187,12 +192,28 @@ __device__ __noinline__ unsigned run_query_E(const QDesc& d, int side) {
     P.a0 = d.prm[0]; P.a1 = d.prm[1]; P.a2 = d.prm[2]; P.a3 = d.prm[3]; P.a4 = d.prm[4];
     const Steps<T> st = {d.h2, d.dt, d.dt6};
     T acc[S][E], t[S][E];
-    for (int64_t k = 0; k < d.nsteps; ++k) {
-        bal_stage<KIND, 1, E, S>(y, acc, t, P, U, st, L);
-        bal_stage<KIND, 2, E, S>(y, acc, t, P, U, st, L);
-        bal_stage<KIND, 3, E, S>(y, acc, t, P, U, st, L);
-        bal_stage<KIND, 4, E, S>(y, acc, t, P, U, st, L);
+    // Steps in blocks of kCancelEvery.  A served query reads its cancel word
+    // at the start of a block and looks at the value only after the block's
+    // steps, so the host-memory read never stalls the arithmetic.  Queries
+    // without one read a device word that is always 0 (no branch around the
+    // load, so nothing has to wait for it before the steps).
+    const unsigned int* cw = d.cancel ? d.cancel : &g_never_cancelled;
+    bool cancelled = false;
+    for (int64_t k0 = 0; k0 < d.nsteps; k0 += kCancelEvery) {
+        const unsigned stop = __hip_atomic_load(cw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const int64_t k1 = k0 + kCancelEvery < d.nsteps ? k0 + kCancelEvery : d.nsteps;
+        for (int64_t k = k0; k < k1; ++k) {
+            bal_stage<KIND, 1, E, S>(y, acc, t, P, U, st, L);
+            bal_stage<KIND, 2, E, S>(y, acc, t, P, U, st, L);
+            bal_stage<KIND, 3, E, S>(y, acc, t, P, U, st, L);
+            bal_stage<KIND, 4, E, S>(y, acc, t, P, U, st, L);
+        }
+        if (wave_bcast(stop)) {
+            cancelled = true;
+            break;
+        }
     }
+    if (cancelled) return ST_CANCELLED;
     unsigned bits = 0;
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -421,9 +442,13 @@ __global__ __launch_bounds__(64) void batch_kernel(const QDesc* __restrict__ des
     }
 }
 
-__global__ __launch_bounds__(64) void single_kernel(QDesc d, unsigned int* status) {
+__global__ __launch_bounds__(64) void single_kernel(QDesc d, unsigned int* status,
+                                                    unsigned int* flags) {
     const unsigned bits = run_query(d);
-    if (threadIdx.x == 0 && bits) atomicOr(status, bits);
+    if (threadIdx.x == 0) {
+        if (flags) *flags = bits;
+        else if (bits) atomicOr(status, bits);
+    }
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(unsigned int* p, int64_t count) {
@@ -433,9 +458,12 @@ __global__ __launch_bounds__(256) void zero_kernel(unsigned int* p, int64_t coun
 
 // ctl[0]: claim counter (work items: two per sequence number, one per side),
 // ctl[1]: status bits, ctl[2]: watermark (every sequence below it has been
-// seen published).  Only the waves holding the sequence at the watermark read
-// the host ring; the others wait on device memory, so idle waves do not flood
-// the host link with polls.
+// seen published), ctl[3]: grid quit word.  Only the waves holding the
+// sequence at the watermark read the host ring; the others wait on device
+// memory, so idle waves do not flood the host link with polls.  The first wave
+// to reach the idle limit sets the quit word, and every other wave leaves at
+// its next wait iteration or claim: the grid exits as a whole, and the host
+// moves any query published to a sequence no wave will run to a new grid.
 __global__ __launch_bounds__(64) void serve_kernel(ServeSlot* ring, int32_t slots,
                                                    unsigned long long* ctl,
                                                    volatile unsigned int* stop,
@@ -443,22 +471,29 @@ __global__ __launch_bounds__(64) void serve_kernel(ServeSlot* ring, int32_t slot
     const int lane = threadIdx.x;
     unsigned long long* claim = ctl;
     unsigned long long* seen = ctl + 2;
+    unsigned long long* quitw = ctl + 3;
     for (;;) {
-        uint64_t u = 0;
-        if (lane == 0) u = atomicAdd(claim, 1ULL);
+        uint64_t u = 0, gq = 0;
+        if (lane == 0) {
+            gq = __hip_atomic_load(quitw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!gq) u = atomicAdd(claim, 1ULL);
+        }
+        if (wave_bcast(gq)) return;
         u = wave_bcast(u);
         const uint64_t t = u >> 1;
         const int side = (int)(u & 1);
         ServeSlot* sl = &ring[t % (uint64_t)slots];
         // Wait until the host publishes sequence t in this slot, the host asks
-        // to stop, or the idle limit passes.  Every branch ends the wait.
+        // to stop, another wave ends the grid, or the idle limit passes.
+        // Every branch ends the wait.
         const uint64_t t_start = wall_clock64();
         int quit = 0;
         for (uint32_t it = 0;; ++it) {
-            uint64_t seq = 0, w = 0;
+            uint64_t seq = 0, w = 0, q = 0;
             unsigned st = 0;
             if (lane == 0) {
                 w = __hip_atomic_load(seen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                q = __hip_atomic_load(quitw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (w >= t)
                     seq = __hip_atomic_load(&sl->seq, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM);
                 if ((it & 63u) == 0u)
@@ -467,10 +502,16 @@ __global__ __launch_bounds__(64) void serve_kernel(ServeSlot* ring, int32_t slot
             }
             seq = wave_bcast(seq);
             w = wave_bcast(w);
+            q = wave_bcast(q);
             st = (unsigned)wave_bcast(st);
             if (seq == t + 1) break;
-            if (st) { quit = 1; break; }
-            if ((int64_t)(wall_clock64() - t_start) > idle_cycles) { quit = 1; break; }
+            if (st || q) { quit = 1; break; }
+            if ((int64_t)(wall_clock64() - t_start) > idle_cycles) {
+                if (lane == 0)
+                    __hip_atomic_store(quitw, 1ULL, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                quit = 1;
+                break;
+            }
             if (w >= t) __builtin_amdgcn_s_sleep(2);
             else __builtin_amdgcn_s_sleep(32);
         }
@@ -481,7 +522,7 @@ __global__ __launch_bounds__(64) void serve_kernel(ServeSlot* ring, int32_t slot
         const unsigned bits = item_is_empty(d, side) ? 0u : run_item(d, side);
         if (lane == 0) {
             sl->flags[side] = bits;
-            if (bits) atomicOr(status, bits);
+            if (bits & (ST_NONFINITE | ST_ORDER)) atomicOr(status, bits & (ST_NONFINITE | ST_ORDER));
             __hip_atomic_store(&sl->done[side], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
@@ -496,8 +537,9 @@ hipError_t launch_batch(const QDesc* d, const BatchItem* items, const uint32_t* 
     return hipGetLastError();
 }
 
-hipError_t launch_single(const QDesc& d, unsigned int* status, hipStream_t s) {
-    hipLaunchKernelGGL(single_kernel, dim3(1), dim3(WAVE), 0, s, d, status);
+hipError_t launch_single(const QDesc& d, unsigned int* status, unsigned int* flags,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(single_kernel, dim3(1), dim3(WAVE), 0, s, d, status, flags);
     return hipGetLastError();
 }
 

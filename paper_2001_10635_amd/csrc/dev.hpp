@@ -242,8 +242,9 @@ template <int KIND, class T> __device__ __forceinline__ T ghost() {
 }
 
 // ------------------------------------------------------------ status --
-// Bits OR-ed into the context's device status word.
-enum { ST_NONFINITE = 1, ST_ORDER = 2 };
+// Bits OR-ed into the context's device status word (ST_CANCELLED: only in a
+// served query's own flags, never in the context's word).
+enum { ST_NONFINITE = 1, ST_ORDER = 2, ST_CANCELLED = 4 };
 
 __device__ __forceinline__ bool finiteT(float x) { return __builtin_isfinite(x); }
 __device__ __forceinline__ bool finiteT(double x) { return __builtin_isfinite(x); }

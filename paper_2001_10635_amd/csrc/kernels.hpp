@@ -146,7 +146,15 @@ struct QDesc {
     double* r_lo;
     double* r_hi;
     int64_t tag;        // caller's index (batch) or ticket slot (serving)
+    // Served queries: a host-written word (pinned, coherent host memory) that
+    // the kernel reads every kCancelEvery steps; nonzero ends the query early
+    // with the ST_CANCELLED bit.  NULL for batches.
+    const unsigned int* cancel;
 };
+
+// Status bit of a served query that stopped on its cancel word.
+enum { STATUS_CANCELLED = 4 };
+constexpr int64_t kCancelEvery = 64;
 
 // Cells per lane of a batched query: ceil(n / 64) (lanes hold E or E - 1).
 inline int batch_cells_per_lane(int64_t n) { return (int)((n + 63) / 64); }
@@ -174,17 +182,24 @@ hipError_t launch_batch(const QDesc* d, const BatchItem* items, const uint32_t* 
                         int split, int64_t grid, hipStream_t stream);
 // Zero `count` 32-bit words (a kernel, so it can sit in a captured graph).
 hipError_t launch_zero(void* p, int64_t count, hipStream_t stream);
-// One query with a plain launch (the one-launch-per-query baseline).
-hipError_t launch_single(const QDesc& d, unsigned int* status, hipStream_t stream);
+// One query with a plain launch (the one-launch-per-query baseline).  With
+// `flags` non-NULL, lane 0 stores the query's status bits there (a served
+// query's own word) instead of OR-ing them into `status`.
+hipError_t launch_single(const QDesc& d, unsigned int* status, unsigned int* flags,
+                         hipStream_t stream);
 
-// Serving ring (see runtime): slots live in pinned host memory.
+// Serving ring (see server.cpp): slots live in pinned host memory.
 struct ServeSlot {
     QDesc d;
     unsigned long long seq;      // sequence published in this slot (+1), 0 = empty
     unsigned long long done[2];  // sequence whose lower / upper side completed (+1)
     unsigned int flags[2];       // status bits of each side
+    unsigned int cancel;         // set by the host to stop the query (d.cancel points here)
+    unsigned int pad;
 };
-// ctl: device words [claim counter, status, published watermark].
+// ctl: device words [claim counter, status, published watermark, grid quit].
+// A wave that reaches the idle limit sets the quit word and every other wave
+// leaves at its next wait or claim, so the grid always exits as a whole.
 hipError_t launch_server(ServeSlot* ring, int32_t slots, unsigned long long* ctl,
                          volatile unsigned int* stop, unsigned int* status,
                          int64_t idle_cycles, int64_t grid, hipStream_t stream);

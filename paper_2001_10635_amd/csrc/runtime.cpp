@@ -192,7 +192,9 @@ int64_t opt_get(const reach_ctx* c, const char* k) {
 reach_status check_system_kind(reach_ctx* c, const reach_system* s, reach_dtype dtype,
                                bool user) {
     if (!s) return fail(c, REACH_E_INVAL, "system is NULL");
-    if (s->reserved != 0) return fail(c, REACH_E_INVAL, "reserved field must be 0");
+    if (s->bc != REACH_BC_DEFAULT)
+        return fail(c, REACH_E_UNSUPPORTED, "bc = %d: only each kind's own boundary conditions "
+                    "(REACH_BC_DEFAULT) are built", s->bc);
     if (s->kind == REACH_USER && !user)
         return fail(c, REACH_E_INVAL, "REACH_USER systems run through reach_embed_rk4_user");
     if (s->kind != REACH_CTM && s->kind != REACH_RD && s->kind != REACH_LIN3 &&
@@ -1551,7 +1553,7 @@ reach_status reach_embed_rk4_each(reach_ctx* c, const reach_query* q, int64_t nq
         if (st != REACH_OK) return st;
     }
     for (int64_t i = 0; i < nq; ++i) {
-        hipError_t e = launch_single(d[i], c->status, c->each_streams[i % nstreams]);
+        hipError_t e = launch_single(d[i], c->status, nullptr, c->each_streams[i % nstreams]);
         if (e != hipSuccess) return hip_fail(c, e, "single-query launch");
     }
     for (int32_t k = 0; k < nstreams; ++k) HIPCHK(c, hipStreamSynchronize(c->each_streams[k]));

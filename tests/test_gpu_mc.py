@@ -145,18 +145,28 @@ def test_ctm64_f64_mc_1000_samples(rc):
 
 
 def test_mc_ctm4096_f32(rc):
-    """n = 4096 FP32, 500 steps: oracle parity on a 256-sample prefix, then
-    the full 2^20 samples with containment in the FP64 embedding box."""
+    """n = 4096 FP32, 500 steps.  Oracle parity on a 4096-sample prefix at the
+    default wave count: 8 waves per CU (2048 on 256 CUs), so every wave
+    integrates two samples (its second folds into the partials it wrote for the
+    first) and the workgroup partials span two chunks of the reduction, which
+    then takes its second pass.  Then the full 2^20 samples with containment in
+    the FP64 embedding box, within the parity slack and counted without it."""
     p = workloads.mc_ctm4096_f32()
     lo, hi = p.box()
-    say("mc ctm4096 MC prefix")
-    m_sub = 256
+    m_sub = 4096
+    rc.set_option("mc.waves", 0)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    waves = min(8 * cus, 4096, m_sub)
+    assert m_sub > waves, "prefix must give some wave a second sample"
+    assert -(-waves // 4) > 256, "workgroup partials must span more than one reduction chunk"
+    say(f"mc ctm4096 MC prefix m={m_sub} waves={waves}")
     g_min, g_max, st = run_mc(rc, p.kind, p.prm, lo, hi, None, None, p.dt, p.nsteps, m_sub, p.seed)
     assert st == R.REACH_OK
     o_min, o_max = oracle.montecarlo(p.kind, p.prm, lo.astype(np.float64), hi.astype(np.float64),
                                      dt=p.dt, nsteps=p.nsteps, m=m_sub, seed=p.seed, ubits=24)
-    assert_rel(g_min, o_min, 1e-5, "min")
-    assert_rel(g_max, o_max, 1e-5, "max")
+    e1 = assert_rel(g_min, o_min, 1e-5, "min")
+    e2 = assert_rel(g_max, o_max, 1e-5, "max")
+    say(f"mc ctm4096 prefix max rel err min {e1:.2e} max {e2:.2e}")
     say("mc ctm4096 MC full")
     f_min, f_max, st = run_mc(rc, p.kind, p.prm, lo, hi, None, None, p.dt, p.nsteps, p.m, p.seed)
     assert st == R.REACH_OK
@@ -170,6 +180,10 @@ def test_mc_ctm4096_f32(rc):
     assert_rel(e_hi, o_ehi, 1e-12, "embedding upper")
     slack = 1e-5 * np.maximum(np.abs(e_lo), 1.0)
     assert np.all(f_min >= e_lo - slack) and np.all(f_max <= e_hi + slack)
+    exact = int(np.count_nonzero((f_min < e_lo) | (f_max > e_hi)))
+    # the oracle's own samples (FP64 arithmetic) lie inside the oracle box exactly
+    assert np.all(o_min >= o_elo) and np.all(o_max <= o_ehi)
+    say(f"mc ctm4096 containment: {exact} of {p.n} cells outside without slack")
 
 
 def run_embed64(rc, p, lo, hi):

@@ -1,6 +1,7 @@
 """Continuous-batching server: queries admitted while others run, admission by
-device-pool bytes, cancellation, idle exit and relaunch, and each served
-result equal to the query run alone."""
+device-pool bytes, cancellation of waiting and running queries, idle exit and
+relaunch, non-finite results, arrival-based latency, and each served result
+equal to the query run alone."""
 import os
 import time
 
@@ -146,6 +147,113 @@ def test_cancel_pending_queries(rc):
         if status[t] == R.REACH_OK and k % 10 == 0:
             a = alone(rc, items[k])
             assert np.array_equal(items[k]["r_lo"], a[0])
+
+
+def long_query(kind, n, nsteps, seed):
+    p = workloads.small_problem(kind, n, seed, nsteps)
+    return host_queries([workloads.Query(0, 0.0, p)])[0]
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["persistent", "launch_per_query"])
+def test_cancel_running_queries(rc, mode):
+    """Queries of 2e6 RK4 steps (about a second each) are cancelled while they
+    run: each stops within a few milliseconds and reports REACH_E_CANCELLED,
+    and the short queries served beside them still equal their alone runs."""
+    rc.set_option("serve.mode", mode)
+    longs = [long_query(workloads.KIND_RD if k % 2 else workloads.KIND_CTM, 40 + 30 * k,
+                        2_000_000, 50 + k) for k in range(4)]
+    items = host_queries(workloads.query_stream(80, 5.0e4, seed=21))
+    pool = torch.empty(16 << 20, dtype=torch.uint8, device="cuda")
+    say(f"serve cancel running, mode {mode}")
+    R.reach_server_start(rc.ctx, pool, pool.numel(), 64)
+    try:
+        lt = [R.reach_submit(rc.ctx, d["q"]) for d in longs]
+        st = [R.reach_submit(rc.ctx, d["q"]) for d in items]
+        time.sleep(0.05)                   # the long queries are well under way
+        t_cancel = time.perf_counter()
+        assert all(R.reach_cancel(rc.ctx, t) == R.REACH_OK for t in lt)
+        lstatus = drain(rc, lt, timeout_s=30.0)
+        waited = time.perf_counter() - t_cancel
+        status = drain(rc, st)
+    finally:
+        R.reach_server_stop(rc.ctx)
+    assert all(lstatus[t] == R.REACH_E_CANCELLED for t in lt), lstatus
+    say(f"cancelled running queries finished {waited * 1e3:.1f} ms after the request")
+    assert waited < 0.3
+    for d in longs:                        # no box is written for a cancelled query
+        assert np.all(np.isnan(d["r_lo"])) and np.all(np.isnan(d["r_hi"]))
+    assert all(v == R.REACH_OK for v in status.values())
+    for d in items:
+        a = alone(rc, d)
+        assert np.array_equal(d["r_lo"], a[0]) and np.array_equal(d["r_hi"], a[1])
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["persistent", "launch_per_query"])
+def test_served_nonfinite_reported(rc, mode):
+    """A reaction-diffusion query that overflows is reported REACH_E_NONFINITE
+    in both serving modes; a finite query served with it is REACH_OK."""
+    rc.set_option("serve.mode", mode)
+    bad = long_query(workloads.KIND_RD, 70, 40, 3)
+    bad["lo"][:] = 1e100
+    bad["hi"][:] = 2e100
+    good = long_query(workloads.KIND_RD, 70, 40, 4)
+    pool = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    say(f"serve non-finite, mode {mode}")
+    R.reach_server_start(rc.ctx, pool, pool.numel(), 8)
+    try:
+        tb = R.reach_submit(rc.ctx, bad["q"])
+        tg = R.reach_submit(rc.ctx, good["q"])
+        status = drain(rc, [tb, tg])
+    finally:
+        R.reach_server_stop(rc.ctx)
+    assert status[tb] == R.REACH_E_NONFINITE and status[tg] == R.REACH_OK
+    a = alone(rc, good)
+    assert np.array_equal(good["r_lo"], a[0]) and np.array_equal(good["r_hi"], a[1])
+    assert rc.sync() == R.REACH_OK
+
+
+def test_latency_counts_from_the_stated_arrival(rc):
+    """reach_submit_at: a query stated to have arrived 50 ms before its submit
+    call has a latency of at least 50 ms."""
+    d = long_query(workloads.KIND_CTM, 30, 20, 5)
+    pool = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    R.reach_server_start(rc.ctx, pool, pool.numel(), 4)
+    try:
+        t = R.reach_submit_at(rc.ctx, d["q"], R.reach_clock_us() - 50_000.0)
+        drain(rc, [t])
+        stats = R.reach_server_stats(rc.ctx)
+        with pytest.raises(R.ReachError) as e:
+            R.reach_submit_at(rc.ctx, d["q"], float("nan"))
+        assert e.value.status == R.REACH_E_INVAL
+    finally:
+        R.reach_server_stop(rc.ctx)
+    assert stats["completed"] == 1 and 50_000.0 <= stats["p50_us"] < 1_000_000.0
+
+
+def test_idle_exit_of_part_of_the_grid_does_not_stall(rc, monkeypatch):
+    """With a 1 s idle limit: a query at 0.9 s keeps two waves busy while the
+    rest of the grid reaches its limit at 1 s; the whole grid leaves then, so a
+    query at 1.2 s is served by a new grid at once instead of waiting for the
+    last two waves to time out at 1.9 s."""
+    monkeypatch.setenv("REACH_SERVER_IDLE_S", "1")
+    items = host_queries(workloads.query_stream(2, 5.0e4, seed=17))
+    pool = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    say("serve partial idle exit")
+    t0 = time.perf_counter()
+    R.reach_server_start(rc.ctx, pool, pool.numel(), 32)
+    try:
+        time.sleep(max(0.0, 0.9 - (time.perf_counter() - t0)))
+        drain(rc, [R.reach_submit(rc.ctx, items[0]["q"])])
+        time.sleep(max(0.0, 1.2 - (time.perf_counter() - t0)))
+        t1 = time.perf_counter()
+        drain(rc, [R.reach_submit(rc.ctx, items[1]["q"])])
+        waited = time.perf_counter() - t1
+    finally:
+        R.reach_server_stop(rc.ctx)
+    say(f"query after the partial idle exit took {waited * 1e3:.1f} ms")
+    assert waited < 0.3
+    a = alone(rc, items[1])
+    assert np.array_equal(items[1]["r_lo"], a[0]) and np.array_equal(items[1]["r_hi"], a[1])
 
 
 def test_idle_exit_and_relaunch(rc, monkeypatch):
