@@ -305,6 +305,26 @@ reach_status reach_montecarlo_range(reach_ctx* ctx, const reach_system* sys, rea
                                     void* r_min, void* r_max,
                                     void* workspace, size_t workspace_bytes, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same as
+ * reach_montecarlo_range, with no workspace argument.  The per-wave partials
+ * live in a fixed array of reach_noalloc_scratch_bytes() = 64 MiB of device
+ * memory that the library holds on each device it runs on until the process
+ * ends; the call allocates nothing.  Every call on one device shares that
+ * device's array, so calls that overlap on one device (two streams, two host
+ * threads) race and must be serialised by the caller.  Results are those of
+ * reach_montecarlo_range with the same arguments.  Errors: those of
+ * reach_montecarlo_range, and REACH_E_NOMEM when the partials
+ * (reach_workspace_bytes(ctx, sys, dtype, m)) exceed the array: only with more
+ * waves than the default, option "mc.waves". */
+reach_status reach_montecarlo_noalloc(reach_ctx* ctx, const reach_system* sys, reach_dtype dtype,
+                                      const void* x_lo, const void* x_hi,
+                                      const void* p_lo, const void* p_hi,
+                                      double t0, double dt, int64_t nsteps,
+                                      int64_t s0, int64_t m, uint64_t seed,
+                                      void* r_min, void* r_max, void* stream);
+size_t reach_noalloc_scratch_bytes(void);
+
 /* Sample count of the Monte Carlo guarantee (Sec. 2.1): with
    m = ceil((2n/eps) ln(2n/delta)) samples, with probability 1 - delta the
    box leaves out at most probability eps of the reachable set.

@@ -86,6 +86,9 @@ def lib() -> ctypes.CDLL:
                               vp], i32),
         "reach_montecarlo_range": ([vp, sysp, i32, vp, vp, vp, vp, d, d, i64, i64, i64, u64, vp,
                                     vp, vp, sz, vp], i32),
+        "reach_montecarlo_noalloc": ([vp, sysp, i32, vp, vp, vp, vp, d, d, i64, i64, i64, u64,
+                                      vp, vp, vp], i32),
+        "reach_noalloc_scratch_bytes": ([], sz),
         "reach_mc_samples": ([i64, d, d], i64),
         "reach_embed_rk4_tube": ([vp, sysp, i32, vp, vp, vp, vp, d, d, i64, i64, vp, vp, vp, sz,
                                   vp], i32),
@@ -301,6 +304,20 @@ def reach_montecarlo_range(ctx, sys: reach_system, dtype: int, x_lo, x_hi, p_lo,
                                       int(s0), int(m), int(seed), _ptr(r_min), _ptr(r_max),
                                       _ptr(workspace), int(workspace_bytes), _stream(stream))
     return _chk(ctx, st, "reach_montecarlo_range")
+
+
+def reach_montecarlo_noalloc(ctx, sys: reach_system, dtype: int, x_lo, x_hi, p_lo, p_hi,
+                             t0: float, dt: float, nsteps: int, s0: int, m: int, seed: int,
+                             r_min, r_max, stream=None) -> int:
+    st = lib().reach_montecarlo_noalloc(ctx, ctypes.byref(sys), int(dtype), _ptr(x_lo),
+                                        _ptr(x_hi), _ptr(p_lo), _ptr(p_hi), float(t0), float(dt),
+                                        int(nsteps), int(s0), int(m), int(seed), _ptr(r_min),
+                                        _ptr(r_max), _stream(stream))
+    return _chk(ctx, st, "reach_montecarlo_noalloc")
+
+
+def reach_noalloc_scratch_bytes() -> int:
+    return int(lib().reach_noalloc_scratch_bytes())
 
 
 def reach_embed_rk4_tube(ctx, sys: reach_system, dtype: int, x_lo, x_hi, p_lo, p_hi, t0: float,

@@ -20,8 +20,8 @@ PROBE_SO = os.path.join(HERE, "libreach_probe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["embed.hip", "gb.hip", "heat3d.hip", "mc.hip", "batch.hip", "runtime.cpp", "server.cpp",
-           "user.cpp"]
+SOURCES = ["embed.hip", "gb.hip", "heat3d.hip", "mc.hip", "mc_noalloc.hip", "batch.hip",
+           "runtime.cpp", "server.cpp", "user.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-ffp-contract=off", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-Wno-unused-command-line-argument", "-Wno-unused-value", "-Wno-unused-result"]

@@ -204,4 +204,8 @@ hipError_t launch_server(ServeSlot* ring, int32_t slots, unsigned long long* ctl
                          volatile unsigned int* stop, unsigned int* status,
                          int64_t idle_cycles, int64_t grid, hipStream_t stream);
 
+// With `device` current: looks up, once per device, the device address of
+// the fixed scratch array of reach_montecarlo_noalloc.
+hipError_t noalloc_setup(int device);
+
 }  // namespace reach

@@ -627,6 +627,9 @@ reach_status reach_ctx_create(int device, reach_ctx** out) {
         if (colon != std::string::npos) c->arch.resize(colon);
     }
     load_tune_cache(c);
+    // the no-allocation Monte Carlo's scratch address on this device (its
+    // failure is reported by that entry point, not here)
+    (void)noalloc_setup(device);
     if (const char* e = std::getenv("REACH_LOG")) c->log = e[0] && std::strcmp(e, "0") != 0;
     if (hipMalloc((void**)&c->status, 256) != hipSuccess) { delete c; return REACH_E_DEVICE; }
     if (hipMemset(c->status, 0, 256) != hipSuccess) { hipFree(c->status); delete c; return REACH_E_DEVICE; }

@@ -78,6 +78,15 @@ def test_null_context_is_rejected(R):
     assert L.reach_submit(None, None, None) == R.REACH_E_BUSY
 
 
+def test_noalloc_scratch_size_and_null_context(R):
+    """The no-allocation Monte Carlo's fixed scratch array is 64 MiB; a NULL
+    context is rejected before anything touches a device."""
+    L = R.lib()
+    assert R.reach_noalloc_scratch_bytes() == 64 << 20
+    assert L.reach_montecarlo_noalloc(None, None, 0, None, None, None, None, 0.0, 0.1, 1, 0, 1,
+                                      0, None, None, None) == R.REACH_E_INVAL
+
+
 def test_step_count_from_horizon(R):
     """nsteps = round((t1 - t0) / dt); a horizon that is not a whole number of
     steps (beyond 1e-9 relative) is rejected."""
