@@ -56,6 +56,13 @@ def log(msg):
 # change with the kernels that read them)
 EMBED_SOURCES = ("dev.hpp", "embed.hip")
 HEAT_SOURCES = ("dev.hpp", "heat3d.hip")
+# the packed batch's kernel sources (its instruction count also follows the
+# planner's packing, whose changes call for a new summary)
+BATCH_SOURCES = ("dev.hpp", "batch.hip")
+# FP64 VALU instructions of one state-step's arithmetic in the batch kernels
+# (per cell and stage: RD 4, CTM 5 for the right-hand side; the RK4 updates
+# 1 + 2 + 2 + 2 over the four stages)
+USEFUL_VALU_PER_STATE_STEP = {2: 23, 1: 27}
 
 
 def source_hash(files=EMBED_SOURCES) -> str:
@@ -257,14 +264,42 @@ def query_mix(rc, R, torch, workloads, nq, cpu=True):
     s = torch.cuda.Stream()
     out = {"workload": f"{nq} queries, Poisson 5e4/s, CTM/RD, n log-uniform [4,512], "
                        f"10-1000 RK4 steps, FP64", "state_steps": state_steps}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     with torch.cuda.stream(s):
+        t = time.perf_counter()
+        tune = R.reach_autotune_batch(rc.ctx, dq, wsb, nbw, s)  # pack widths, waves
+        t_tune = time.perf_counter() - t
         R.reach_embed_rk4_batch(rc.ctx, dq, wsb, nbw, s)        # capture + first replay
         s.synchronize()
         t = time.perf_counter()
+        ev0.record(s)
         R.reach_embed_rk4_batch(rc.ctx, dq, wsb, nbw, s)
+        ev1.record(s)
         s.synchronize()
         tb = time.perf_counter() - t
     assert rc.sync(s) == R.REACH_OK
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    plan = R.reach_plan_batch(rc.ctx, dq, with_E=True)
+    kinds = np.array([q.problem.kind for q in qs])
+    steps = np.array([q.problem.nsteps for q in qs])
+    slots = sum((64 * E if E else 64 * -(-ns[it[0]] // 64)) *
+                int(max(steps[i] for i in it)) for E, it in plan)
+    lanes = [sum(-(-int(ns[i]) // E) for i in it) for E, it in plan if E]
+    useful = float(sum(2.0 * ns[kinds == k] @ steps[kinds == k] * c
+                       for k, c in USEFUL_VALU_PER_STATE_STEP.items()))
+    valu = profile_value("pack_kernel_mix1e5_f64_pmc.txt", "valu_wave_instructions_per_batch",
+                         BATCH_SOURCES)
+    out["batch_plan"] = {"items": len(plan), "packs": len(lanes),
+                         "items_by_E": {str(e): int(sum(1 for E, _ in plan if E == e))
+                                        for e in sorted({E for E, _ in plan})},
+                         "mean_lanes_per_pack": round(float(np.mean(lanes)), 2) if lanes else None,
+                         "cell_step_slots_used": round(float(ns @ steps) / slots, 4),
+                         "autotune": tune, "autotune_s": round(t_tune, 3),
+                         # useful FP64 lane-instructions over the issued ones
+                         # (rocprof SQ_INSTS_VALU of the committed summary, taken
+                         # on the current batch sources)
+                         "useful_valu_lane_frac": (round(useful / (valu * 64), 4)
+                                                   if valu else None)}
     ref_lo = r_lo.cpu().numpy()
     t = time.perf_counter()
     R.reach_embed_rk4_each(rc.ctx, dq, 8)
@@ -272,7 +307,10 @@ def query_mix(rc, R, torch, workloads, nq, cpu=True):
     assert rc.sync() == R.REACH_OK
     same = bool(np.array_equal(r_lo.cpu().numpy(), ref_lo))
     out["batch"] = {"queries_per_s": nq / tb, "seconds": round(tb, 4),
-                    "state_steps_per_s": state_steps / tb}
+                    "state_steps_per_s": state_steps / tb,
+                    "gpu_seconds": round(gpu_s, 5),
+                    "valu_issue_frac": (round(valu * 64 / gpu_s / VALU_LANE_PEAK, 4)
+                                        if valu else None)}
     out["one_launch_per_query"] = {"queries_per_s": nq / te, "seconds": round(te, 4)}
     out["batch_speedup"] = round(te / tb, 2)
     out["batch_equals_per_query"] = same
@@ -352,8 +390,10 @@ def query_mix(rc, R, torch, workloads, nq, cpu=True):
     return out
 
 
-def batch_only(rc, R, torch, workloads, nq):
-    """One offline batch of the query mix (the batch kernel alone, profiling)."""
+def batch_only(rc, R, torch, workloads, nq, tune_first=False):
+    """One offline batch of the query mix (the batch kernel alone, profiling;
+    the last batch launch is the timed one), after the batch autotuner if
+    tune_first."""
     p4 = workloads.serve_mix_f64()
     qs = workloads.query_stream(nq, p4.extra["rate"], seed=p4.seed)
     ns = np.array([q.problem.n for q in qs])
@@ -376,6 +416,9 @@ def batch_only(rc, R, torch, workloads, nq):
                                      n_in=q.problem.n_in) for i, q in enumerate(qs)])
     nbw = R.reach_batch_workspace_bytes(nq)
     wsb = torch.empty(nbw, dtype=torch.uint8, device="cuda")
+    tune = None
+    if tune_first:
+        tune = R.reach_autotune_batch(rc.ctx, dq, wsb, nbw, None)
     R.reach_embed_rk4_batch(rc.ctx, dq, wsb, nbw, None)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -384,7 +427,7 @@ def batch_only(rc, R, torch, workloads, nq):
     tb = time.perf_counter() - t
     assert rc.sync() == R.REACH_OK
     return {"workload": f"{nq} queries of the mix, one batch", "seconds": round(tb, 4),
-            "queries_per_s": nq / tb}
+            "queries_per_s": nq / tb, "autotune": tune}
 
 
 def oracle_queries(qs, h_lo, h_hi, offs, u_lo, u_hi, k):
@@ -743,6 +786,12 @@ def main():
                          "FP32 chain (one call), one batch of the query mix, the 64-cell "
                          "latency calls, the run-time compiled systems, or the growth bound "
                          "and reach tube on the RD 2^26 workload")
+    ap.add_argument("--batch-pack", type=int, default=0,
+                    help="option batch.pack for --only batch (0 auto, 1 always, 2 never)")
+    ap.add_argument("--batch-E", type=int, default=0,
+                    help="option batch.E for --only batch (largest cells per lane of a pack)")
+    ap.add_argument("--batch-waves", type=int, default=0,
+                    help="option batch.waves for --only batch (resident waves)")
     ap.add_argument("--stream-probe", action="store_true",
                     help="time the HBM stream probe over its shapes and print it (only)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -778,7 +827,12 @@ def main():
                                torch.from_numpy(ph).cuda(), None,
                                torch.cuda.current_stream())
         else:
-            out = batch_only(rc, R, torch, workloads, args.queries)
+            rc.set_option("batch.pack", args.batch_pack)
+            rc.set_option("batch.E", args.batch_E)
+            rc.set_option("batch.waves", args.batch_waves)
+            out = batch_only(rc, R, torch, workloads, args.queries,
+                             tune_first=not (args.batch_pack or args.batch_E or args.batch_waves
+                                             or args.no_tune))
         print(json.dumps(out), flush=True)
         rc.close()
         return

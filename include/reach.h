@@ -165,9 +165,14 @@ const char* reach_last_error(const reach_ctx* ctx);
                   (with 16, 12, 8, 8 or 4 wavefronts per block; FP64 builds 2, 3,
                   4 and 5, FP32 2, 3, 4 and 8; 0 = tuned default)
      "mc.waves"   resident waves of the Monte Carlo kernel (0 = default, at most 4096)
-     "batch.waves" resident waves of the batch kernel (0 = default)
      "batch.split" 1: one wave per side of each cooperative query (shorter
-                  latency per query); 0 (default): one wave per query
+                  latency per query); 0 (default): one wave per query or pack
+     "batch.pack" 0 (default): segment packs when the batch has more queries
+                  than twice the resident waves; 1: always; 2: never
+     "batch.E"    largest cells per lane of a segment pack: 2, 4 or 8 (0 =
+                  the autotuned cap of the query's bucket, else 8)
+     "batch.waves" resident waves of the batch kernels (0 = default: 8 per
+                  compute unit unpacked, 12 packed or the autotuned count)
      "serve.mode" 0 (default): persistent serving kernel; 1: one launch per
                   served query (read by reach_server_start)
      "serve.waves" resident waves of the serving kernel (0 = default)
@@ -335,8 +340,8 @@ int64_t reach_mc_samples(int64_t n, double eps, double delta);
  * Many small embeddings (n <= 512, FP64, n_in 0 or 1) in one persistent
  * kernel: each wave takes the next work item from a device work counter
  * (longest first; the schedule is reach_plan_batch's) and integrates it with
- * its whole state in registers.  A work item is one query, or a pack of
- * short cooperative queries sharing a wave (one cell per lane).
+ * its whole state in registers.  A work item is one query spread over the
+ * wave, or a segment pack of queries sharing it (E cells per lane).
  * `q` is a HOST array of nq queries whose pointers are device pointers; it is
  * read during the call only.  workspace: reach_batch_workspace_bytes(nq)
  * bytes of device memory.  Results are identical to nq separate
@@ -350,24 +355,50 @@ size_t reach_batch_workspace_bytes(int64_t nq);
 
 /* The schedule reach_embed_rk4_batch launches for these queries, computed on
  * the host only (no device call; the query pointers are not dereferenced).
- * Short cooperative queries (CTM or RD, n <= 32) with the same parameters, dt
- * and step count are packed up to 16 to a wavefront, at most 64 cells in all,
- * one cell per lane; every other query runs alone.  Items come longest first
- * (wave time E * nsteps with E = ceil(n / 64), a pack counting as E = 1).
+ * A batch with more queries than twice the resident waves of the unpacked
+ * kernel (option "batch.pack": 0 = that rule, 1 = always, 2 = never) is
+ * packed: every work item is then a segment pack, queries of one kind with
+ * bitwise equal parameters and dt, step counts in the same 1/16 octave and
+ * the same cells per lane E (2, 4 or 8, chosen per query by the least
+ * estimated issue cost, at most option "batch.E" or else the (kind, size)
+ * bucket's autotuned cap) sharing a wavefront, query m on ceil(n_m / E)
+ * lanes, at most 64 lanes and 64 queries.  An unpacked batch runs every
+ * query alone, spread over a whole wavefront (E = ceil(n / 64)).  Items come
+ * longest first (wave time E * nsteps of the longest member).
  * On return *n_items holds the item count and item k runs the queries
- * member[item_start[k] .. item_start[k] + item_count[k]) (indices into q);
- * item_start, item_count and member are host arrays of nq entries.  ctx may
- * be NULL (then packing is on, as with the default options, a large plan
- * runs on host threads started for the call, and errors carry
- * no message); with a context its "batch.split" option turns packing off as
- * it does for the batch.
+ * member[item_start[k] .. item_start[k] + item_count[k]) (indices into q) at
+ * item_E[k] cells per lane (0: alone); item_start, item_count, item_E and
+ * member are host arrays of nq entries.  ctx may be NULL (then the default
+ * options apply with 256 compute units, a large plan runs on host threads
+ * started for the call, and errors carry no message); with a context its
+ * "batch.split" option turns packing off as it does for the batch.
  * Errors: those of reach_embed_rk4_batch's query checks, REACH_E_INVAL for
  * NULL arrays. */
 reach_status reach_plan_batch(reach_ctx* ctx, const reach_query* q, int64_t nq,
-                              int64_t* item_start, int32_t* item_count, int64_t* member,
-                              int64_t* n_items);
+                              int64_t* item_start, int32_t* item_count, int32_t* item_E,
+                              int64_t* member, int64_t* n_items);
 reach_status reach_embed_rk4_batch(reach_ctx* ctx, const reach_query* q, int64_t nq,
                                    void* workspace, size_t workspace_bytes, void* stream);
+
+/* Autotuner of the batch (its tile shapes per size bucket), on the caller's
+   whole batch: times it (one warm-up and four timed calls, HIP events on
+   `stream`, fastest kept, host planning included) at the current settings,
+   then, for every (kind, log2 n bucket) with at least 256 queries, most
+   queries first, tries the narrower largest pack widths 4 and 2 cells per
+   lane for that bucket and keeps one only if the whole batch gets more than
+   1% faster; then, unless option "batch.waves" is set, times 12 and 8
+   resident waves per compute unit and keeps the faster for packed batches.
+   A batch that does not pack is only timed.  The widths are recorded in the
+   context (used while option "batch.E" is 0).  Arguments as
+   reach_embed_rk4_batch, whose results the queries' r_lo / r_hi hold
+   afterwards; every setting gives the same boxes bit for bit.  best[0] =
+   resident waves (0: the default), best[1] = nanoseconds of the whole batch at
+   the chosen settings.  `best` is a host array of 2.  With
+   REACH_AUTOTUNE_CACHE set, the bucket widths are appended there and read
+   back by reach_ctx_create on the same device architecture. */
+reach_status reach_autotune_batch(reach_ctx* ctx, const reach_query* q, int64_t nq,
+                                  void* workspace, size_t workspace_bytes, void* stream,
+                                  int64_t* best);
 
 /* Baseline for the batch: one kernel launch per query, round-robin over
    `nstreams` internal streams (1..16).  Same results; host-blocking. */

@@ -96,8 +96,9 @@ def lib() -> ctypes.CDLL:
         "reach_growth_bound": ([vp, sysp, i32, vp, vp, vp, vp, d, d, i64, vp, vp, vp, sz, vp], i32),
         "reach_batch_workspace_bytes": ([i64], sz),
         "reach_embed_rk4_batch": ([vp, qp, i64, vp, sz, vp], i32),
-        "reach_plan_batch": ([vp, qp, i64, P(i64), P(i32), P(i64), P(i64)], i32),
+        "reach_plan_batch": ([vp, qp, i64, P(i64), P(i32), P(i32), P(i64), P(i64)], i32),
         "reach_embed_rk4_each": ([vp, qp, i64, i32], i32),
+        "reach_autotune_batch": ([vp, qp, i64, vp, sz, vp, P(i64)], i32),
         "reach_server_start": ([vp, vp, sz, i32, vp], i32),
         "reach_submit": ([vp, qp, P(u64)], i32),
         "reach_submit_at": ([vp, qp, d, P(u64)], i32),
@@ -396,22 +397,28 @@ def reach_batch_workspace_bytes(nq: int) -> int:
     return int(lib().reach_batch_workspace_bytes(int(nq)))
 
 
-def reach_plan_batch(ctx, queries) -> list:
+def reach_plan_batch(ctx, queries, with_E: bool = False) -> list:
     """The batch's work items in launch order, each a list of query indices
-    (more than one: a pack sharing a wavefront).  Host only; ctx may be None."""
+    (more than one: a segment pack sharing a wavefront); with_E: (E, list)
+    pairs, E the pack's cells per lane (0: one query over the whole wave).
+    Host only; ctx may be None."""
     arr = query_array(queries)
     nq = len(queries)
     start = (ctypes.c_int64 * max(nq, 1))()
     count = (ctypes.c_int32 * max(nq, 1))()
+    ecnt = (ctypes.c_int32 * max(nq, 1))()
     member = (ctypes.c_int64 * max(nq, 1))()
     ni = ctypes.c_int64(0)
-    st = lib().reach_plan_batch(ctx, arr, nq, start, count, member, ctypes.byref(ni))
+    st = lib().reach_plan_batch(ctx, arr, nq, start, count, ecnt, member, ctypes.byref(ni))
     if ctx is None:
         if st != REACH_OK:
             raise ReachError(st, "reach_plan_batch")
     else:
         _chk(ctx, st, "reach_plan_batch")
-    return [[int(member[start[k] + m]) for m in range(count[k])] for k in range(ni.value)]
+    items = [[int(member[start[k] + m]) for m in range(count[k])] for k in range(ni.value)]
+    if with_E:
+        return [(int(ecnt[k]), items[k]) for k in range(ni.value)]
+    return items
 
 
 def query_array(queries):
@@ -426,6 +433,15 @@ def reach_embed_rk4_batch(ctx, queries, workspace, workspace_bytes: int, stream=
     st = lib().reach_embed_rk4_batch(ctx, arr, len(queries), _ptr(workspace),
                                      int(workspace_bytes), _stream(stream))
     return _chk(ctx, st, "reach_embed_rk4_batch")
+
+
+def reach_autotune_batch(ctx, queries, workspace, workspace_bytes: int, stream=None) -> dict:
+    arr = query_array(queries)
+    best = (ctypes.c_int64 * 2)()
+    st = lib().reach_autotune_batch(ctx, arr, len(queries), _ptr(workspace), int(workspace_bytes),
+                                    _stream(stream), best)
+    _chk(ctx, st, "reach_autotune_batch")
+    return {"waves": int(best[0]), "batch_ns": int(best[1])}
 
 
 def reach_embed_rk4_each(ctx, queries, nstreams: int = 8) -> int:

@@ -9,9 +9,10 @@
 // or served.
 //
 //   batch_kernel   persistent grid; each wave pops the next work item (a whole
-//                  query, a pack of short ones, or with `split` one side of a
-//                  cooperative query) from a device counter until the batch is
-//                  exhausted.
+//                  query, or with `split` one side of a cooperative query) from
+//                  a device counter until the batch is exhausted.
+//   pack_kernel    the same for a packed batch, whose items are segment packs:
+//                  queries sharing a wave at E cells per lane.
 //   single_kernel  one query per launch (the baseline the batch is compared with).
 //   serve_kernel   persistent grid fed through a ring of descriptors in pinned
 //                  host memory; each wave claims the next work item (sequence
@@ -48,6 +49,7 @@ __device__ __forceinline__ uint64_t wave_bcast(uint64_t v) {
 // same alone, batched or served.
 struct Lanes {
     bool shortl;   // this lane holds E - 1 cells
+    bool begin;    // this lane holds cell 0 (read by segment packs only)
     bool end;      // this lane holds cell n-1
     int cnt;       // cells held
     int64_t first; // index of the first cell held
@@ -61,6 +63,7 @@ __device__ __forceinline__ Lanes lanes_of(int64_t n) {
     L.shortl = lane >= F;
     L.cnt = L.shortl ? E - 1 : E;
     L.first = (int64_t)lane * E - (L.shortl ? (int64_t)lane - F : 0);
+    L.begin = lane == 0;
     L.end = (E == 1) ? (lane == n - 1) : (lane == WAVE - 1);
     return L;
 }
@@ -79,7 +82,11 @@ __device__ __forceinline__ T last_of(const T (&in)[E], bool shortl) {
     else return shortl ? in[E - 2] : in[E - 1];
 }
 
-template <int KIND, int STAGE, int E, int S>
+// SEG: the query occupies a run of lanes inside the wave (a segment pack), so
+// its first lane takes the left boundary value and its last lane the right
+// ghost by a select, where a query spanning the whole wave gets them from the
+// shifts' zero fill.
+template <int KIND, int STAGE, int E, int S, bool SEG = false>
 __device__ __forceinline__ void bal_stage(double (&y)[S][E], double (&acc)[S][E],
                                           double (&t)[S][E], const SysPrm<double>& P,
                                           const Inputs<double, E, S, IN_SCALAR>& U,
@@ -100,6 +107,7 @@ __device__ __forceinline__ void bal_stage(double (&y)[S][E], double (&acc)[S][E]
             for (int e = 0; e < E; ++e)
                 F[e] = minT(minT(v * in[s][e], fmaT(-w, right_of<E>(in[s], e, rn, L.shortl), wc)), q);
             T Fprev = from_left(last_of<E>(F, L.shortl));
+            if (SEG) Fprev = L.begin ? T(0) : Fprev;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const T k = Fprev - F[e];
@@ -112,9 +120,10 @@ __device__ __forceinline__ void bal_stage(double (&y)[S][E], double (&acc)[S][E]
         const T ih2 = P.a0, two_ih2 = P.a1;
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const T ln = from_left(last_of<E>(in[s], L.shortl));
+            T ln = from_left(last_of<E>(in[s], L.shortl));
+            if (SEG) ln = L.begin ? T(0) : ln;
             T rn = from_right(in[s][0]);
-            if (E == 1) rn = L.end ? T(0) : rn;
+            if (E == 1 || SEG) rn = L.end ? T(0) : rn;
             T left = ln;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -136,8 +145,9 @@ __device__ __forceinline__ void bal_stage(double (&y)[S][E], double (&acc)[S][E]
 #pragma unroll
         for (int s = 0; s < 2; ++s) {
             ln[s] = from_left(last_of<E>(in[s], L.shortl));
+            if (SEG) ln[s] = L.begin ? T(0) : ln[s];
             rn[s] = from_right(in[s][0]);
-            if (E == 1) rn[s] = L.end ? T(0) : rn[s];
+            if (E == 1 || SEG) rn[s] = L.end ? T(0) : rn[s];
             left[s] = ln[s];
         }
 #pragma unroll
@@ -248,107 +258,88 @@ __device__ __forceinline__ unsigned run_query_kind(const QDesc& d, int side) {
     }
 }
 
-// Packed short queries: up to kPackMax cooperative queries (CTM or RD) of at
-// most kPackMaxN cells with the same system constants and dt share one wave,
-// query m on a contiguous segment of n_m lanes (one cell per lane, both
-// sides).  A segment's first lane takes the left boundary value (ghost 0;
-// zero inflow for the CTM) and its last lane the right ghost (0; -inf, free
-// outflow, for the CTM) instead of the neighbouring segment's values; the
-// wave runs the longest member's step count and a member's lanes keep their
-// state once its own steps are done.  Per cell this is the arithmetic of the
-// single-query path, so the results are bitwise those of the query run alone.
-template <int KIND, int STAGE>
-__device__ __forceinline__ void pack_stage(double (&y)[2], double (&acc)[2], double (&t)[2],
-                                           const SysPrm<double>& P, const double (&u)[2],
-                                           const Steps<double>& st, bool first, bool last,
-                                           bool live) {
+// Segment packs: several queries of one kind with bitwise equal constants and
+// dt share a wave, E cells per lane (E = 2, 4 or 8, one E per pack).  Member m
+// runs on the L_m = ceil(n_m / E) lanes after the previous members', in the
+// balanced layout of those lanes: the first F_m = n_m - L_m (E - 1) lanes hold
+// E cells and the others E - 1 (the planner packs a query at this E only when
+// F_m >= 0).  A member's first and last lanes take the chain's boundary values
+// by a select, so members never read each other's cells; lanes past the last
+// member hold ghosts and stay masked off.  The wave runs the longest member's
+// steps, a member's lanes masked off once its own steps are done.  Per cell
+// this is the single-query arithmetic, so every box is bitwise the one the
+// query gets alone.
+template <int KIND, int E>
+__device__ __forceinline__ void run_seg(const QDesc* __restrict__ desc,
+                                     const uint32_t* __restrict__ mem_idx, int count,
+                                     unsigned int* qflags, unsigned int* status) {
     using T = double;
-    T (&in)[2] = (STAGE == 1) ? y : t;
-    if constexpr (KIND == K_CTM) {
-        const T v = P.a0, w = P.a1, wc = P.a2, q = P.a3;
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            T rn = from_right(in[s]);
-            rn = last ? neg_inf<T>() : rn;
-            const T F = minT(minT(v * in[s], fmaT(-w, rn, wc)), q);
-            T Fprev = from_left(F);
-            Fprev = first ? T(0) : Fprev;
-            const T y0 = y[s];
-            rk_update<STAGE>(Fprev - F, y[s], acc[s], t[s], st);
-            if (STAGE == 4) y[s] = live ? y[s] : y0;
-        }
-    } else {
-        const T ih2 = P.a0, two_ih2 = P.a1;
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            T ln = from_left(in[s]);
-            ln = first ? T(0) : ln;
-            T rn = from_right(in[s]);
-            rn = last ? T(0) : rn;
-            const T mid = in[s];
-            const T loc = fmaT(-mid, fmaT(mid, mid, two_ih2), u[s]);
-            const T y0 = y[s];
-            rk_update<STAGE>(fmaT(ln + rn, ih2, loc), y[s], acc[s], t[s], st);
-            if (STAGE == 4) y[s] = live ? y[s] : y0;
-        }
-    }
-}
-
-template <int KIND>
-__device__ __noinline__ void run_pack(const QDesc* __restrict__ desc,
-                                      const uint32_t* __restrict__ mem_idx, int count,
-                                      unsigned int* qflags, unsigned int* status) {
-    using T = double;
+    constexpr int S = 2;
     const int lane = threadIdx.x;
-    const QDesc* d = desc + mem_idx[0];
-    int mem = -1;
-    int64_t c = 0;
-    int off = 0;
+    const QDesc* d0 = desc + mem_idx[0];
+    int mem = -1, off = 0, base = 0, len = 0;
     int64_t steps = 0;   // the longest member's
     for (int m = 0; m < count; ++m) {
         const QDesc* dm = desc + mem_idx[m];
-        const int nm = (int)dm->n;
-        if (lane >= off && lane < off + nm) {
+        const int l = (int)((dm->n + E - 1) / E);
+        if (lane >= off && lane < off + l) {
             mem = m;
-            c = lane - off;
+            base = off;
+            len = l;
         }
-        off += nm;
+        off += l;
         steps = dm->nsteps > steps ? dm->nsteps : steps;
     }
     const bool valid = mem >= 0;
     const QDesc* me = desc + mem_idx[valid ? mem : 0];
     const int64_t n = me->n;
-    const bool first = valid && c == 0;
-    const bool last = valid && c == n - 1;
-    T y[2], u[2], acc[2], t[2];
+    const int rel = lane - base;
+    const int64_t F = n - (int64_t)len * (E - 1);   // lanes holding E cells
+    Lanes L;
+    L.shortl = rel >= F;
+    L.cnt = !valid ? 0 : (L.shortl ? E - 1 : E);
+    L.first = (int64_t)rel * E - (L.shortl ? (int64_t)rel - F : 0);
+    L.begin = valid && rel == 0;
+    L.end = valid && rel == len - 1;
     const double* src[2] = {me->x_lo, me->x_hi};
     const double* pin[2] = {me->p_lo, me->p_hi};
+    T y[S][E];
+    Inputs<T, E, S, IN_SCALAR> U;
 #pragma unroll
-    for (int s = 0; s < 2; ++s) {
-        y[s] = valid ? src[s][c] : ghost<KIND, T>();
-        u[s] = (valid && pin[s]) ? *pin[s] : T(0);
+    for (int s = 0; s < S; ++s) {
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            y[s][e] = (e < L.cnt) ? src[s][L.first + e] : ghost<KIND, T>();
+        U.u[s] = (valid && pin[s]) ? *pin[s] : T(0);
     }
     SysPrm<T> P;
-    P.a0 = d->prm[0]; P.a1 = d->prm[1]; P.a2 = d->prm[2]; P.a3 = d->prm[3]; P.a4 = d->prm[4];
-    const Steps<T> st = {d->h2, d->dt, d->dt6};
-    const int64_t my_steps = me->nsteps;
+    P.a0 = d0->prm[0]; P.a1 = d0->prm[1]; P.a2 = d0->prm[2]; P.a3 = d0->prm[3]; P.a4 = d0->prm[4];
+    const Steps<T> st = {d0->h2, d0->dt, d0->dt6};
+    T acc[S][E], t[S][E];
+    const int64_t mine = valid ? me->nsteps : 0;
     for (int64_t k = 0; k < steps; ++k) {
-        const bool live = k < my_steps;
-        pack_stage<KIND, 1>(y, acc, t, P, u, st, first, last, live);
-        pack_stage<KIND, 2>(y, acc, t, P, u, st, first, last, live);
-        pack_stage<KIND, 3>(y, acc, t, P, u, st, first, last, live);
-        pack_stage<KIND, 4>(y, acc, t, P, u, st, first, last, live);
-    }
-    if (valid) {
-        me->r_lo[c] = y[0];
-        me->r_hi[c] = y[1];
-        unsigned bits = 0;
-        if (!finiteT(y[0]) || !finiteT(y[1])) bits |= ST_NONFINITE;
-        if (y[0] > y[1]) bits |= ST_ORDER;
-        if (bits) {
-            atomicOr(&qflags[me->tag], bits);
-            atomicOr(status, bits);
+        if (k < mine) {
+            bal_stage<KIND, 1, E, S, true>(y, acc, t, P, U, st, L);
+            bal_stage<KIND, 2, E, S, true>(y, acc, t, P, U, st, L);
+            bal_stage<KIND, 3, E, S, true>(y, acc, t, P, U, st, L);
+            bal_stage<KIND, 4, E, S, true>(y, acc, t, P, U, st, L);
         }
+    }
+    unsigned bits = 0;
+    double* dst[2] = {me->r_lo, me->r_hi};
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        if (e < L.cnt) {
+            const int64_t j = L.first + e;
+            dst[0][j] = y[0][e];
+            dst[1][j] = y[1][e];
+            if (!finiteT(y[0][e]) || !finiteT(y[1][e])) bits |= ST_NONFINITE;
+            if (y[0][e] > y[1][e]) bits |= ST_ORDER;
+        }
+    }
+    if (bits) {
+        atomicOr(&qflags[me->tag], bits);
+        atomicOr(status, bits);
     }
 }
 
@@ -397,17 +388,8 @@ __global__ __launch_bounds__(64) void batch_kernel(const QDesc* __restrict__ des
         u = wave_bcast(u);
         if (u >= total) break;
         if (!split) {
-            // whole queries (both sides in one wave, most work per wave) or a
-            // pack of short ones
+            // a whole query over the wave (both sides, E = ceil(n / 64))
             const BatchItem it = items[u];
-            if (it.count > 1) {
-                const int kind = desc[members[it.start]].kind;
-                if (kind == K_CTM)
-                    run_pack<K_CTM>(desc, members + it.start, (int)it.count, qflags, status);
-                else
-                    run_pack<K_RD>(desc, members + it.start, (int)it.count, qflags, status);
-                continue;
-            }
             const QDesc d = desc[members[it.start]];
             const unsigned bits = run_query(d);
             if (lane == 0 && bits) {
@@ -442,6 +424,43 @@ __global__ __launch_bounds__(64) void batch_kernel(const QDesc* __restrict__ des
     }
 }
 
+// Persistent worker of a packed batch: every item is a segment pack.  The
+// packs' bodies are inlined into this one kernel (no calls), whose registers
+// are capped for three waves per SIMD: packs carry at most 8 cells per lane,
+// and the extra resident wave hides the FP64 dependency latency of the stage
+// chains.
+__global__ __launch_bounds__(64, 3) void pack_kernel(const QDesc* __restrict__ desc,
+                                                      const BatchItem* __restrict__ items,
+                                                      const uint32_t* __restrict__ members,
+                                                      const uint64_t* n_items,
+                                                      unsigned long long* counter,
+                                                      unsigned int* qflags, unsigned int* status) {
+    const int lane = threadIdx.x;
+    const uint64_t ni = wave_bcast(*n_items);
+    for (;;) {
+        uint64_t u = 0;
+        if (lane == 0) u = atomicAdd(counter, 1ULL);
+        u = wave_bcast(u);
+        if (u >= ni) break;
+        const BatchItem it = items[u];
+        const int kind = desc[members[it.start]].kind;
+        const uint32_t* mi = members + it.start;
+        const int cnt = it.count;
+        const int sel = (kind == K_CTM ? 0 : kind == K_RD ? 3 : 6) + (it.E == 2 ? 0 : it.E == 4 ? 1 : 2);
+        switch (sel) {
+            case 0: run_seg<K_CTM, 2>(desc, mi, cnt, qflags, status); break;
+            case 1: run_seg<K_CTM, 4>(desc, mi, cnt, qflags, status); break;
+            case 2: run_seg<K_CTM, 8>(desc, mi, cnt, qflags, status); break;
+            case 3: run_seg<K_RD, 2>(desc, mi, cnt, qflags, status); break;
+            case 4: run_seg<K_RD, 4>(desc, mi, cnt, qflags, status); break;
+            case 5: run_seg<K_RD, 8>(desc, mi, cnt, qflags, status); break;
+            case 6: run_seg<K_LIN3, 2>(desc, mi, cnt, qflags, status); break;
+            case 7: run_seg<K_LIN3, 4>(desc, mi, cnt, qflags, status); break;
+            default: run_seg<K_LIN3, 8>(desc, mi, cnt, qflags, status); break;
+        }
+    }
+}
+
 __global__ __launch_bounds__(64) void single_kernel(QDesc d, unsigned int* status,
                                                     unsigned int* flags) {
     const unsigned bits = run_query(d);
@@ -454,6 +473,34 @@ __global__ __launch_bounds__(64) void single_kernel(QDesc d, unsigned int* statu
 __global__ __launch_bounds__(256) void zero_kernel(unsigned int* p, int64_t count) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < count) p[i] = 0u;
+}
+
+// A served item's box arrives in pinned host staging; the wave that runs it
+// copies what it reads (its side, or both sides of a coupled LIN3 query) into
+// the query's device pool block, points its copy of the descriptor there, and
+// runs from it.  The fences make the lanes' stores visible to the wave's own
+// loads of other lanes' cells (agent-scope release, then acquire: the vector
+// L1 may hold the block from an earlier query).
+__device__ __forceinline__ void park_box(QDesc& d, int side) {
+    const int lane = threadIdx.x;
+    const int64_t n = d.n;
+    double* blk = d.park;
+    const bool both = item_is_whole(d);
+    for (int s = 0; s < 2; ++s) {
+        if (!both && s != side) continue;
+        const double* src = s ? d.x_hi : d.x_lo;
+        double* dst = blk + (int64_t)s * n;
+        for (int64_t j = lane; j < n; j += WAVE) dst[j] = src[j];
+        if (d.p_lo && lane == 0) blk[2 * n + s] = s ? *d.p_hi : *d.p_lo;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    d.x_lo = blk;
+    d.x_hi = blk + n;
+    if (d.p_lo) {
+        d.p_lo = blk + 2 * n;
+        d.p_hi = blk + 2 * n + 1;
+    }
 }
 
 // ctl[0]: claim counter (work items: two per sequence number, one per side),
@@ -518,8 +565,10 @@ __global__ __launch_bounds__(64) void serve_kernel(ServeSlot* ring, int32_t slot
         if (quit) return;
         if (lane == 0) atomicMax(seen, (unsigned long long)(t + 1));
         __atomic_thread_fence(__ATOMIC_ACQUIRE);
-        const QDesc d = sl->d;
-        const unsigned bits = item_is_empty(d, side) ? 0u : run_item(d, side);
+        QDesc d = sl->d;
+        const bool empty = item_is_empty(d, side);
+        if (d.park && !empty) park_box(d, side);
+        const unsigned bits = empty ? 0u : run_item(d, side);
         if (lane == 0) {
             sl->flags[side] = bits;
             if (bits & (ST_NONFINITE | ST_ORDER)) atomicOr(status, bits & (ST_NONFINITE | ST_ORDER));
@@ -531,9 +580,13 @@ __global__ __launch_bounds__(64) void serve_kernel(ServeSlot* ring, int32_t slot
 hipError_t launch_batch(const QDesc* d, const BatchItem* items, const uint32_t* members,
                         const uint64_t* n_items, unsigned long long* counter,
                         unsigned int* qflags, unsigned int* pair, unsigned int* status,
-                        int split, int64_t grid, hipStream_t s) {
-    hipLaunchKernelGGL(batch_kernel, dim3((unsigned)grid), dim3(WAVE), 0, s, d, items, members,
-                       n_items, counter, qflags, pair, status, split);
+                        int split, bool packed, int64_t grid, hipStream_t s) {
+    if (packed)
+        hipLaunchKernelGGL(pack_kernel, dim3((unsigned)grid), dim3(WAVE), 0, s, d, items, members,
+                           n_items, counter, qflags, status);
+    else
+        hipLaunchKernelGGL(batch_kernel, dim3((unsigned)grid), dim3(WAVE), 0, s, d, items,
+                           members, n_items, counter, qflags, pair, status, split);
     return hipGetLastError();
 }
 

@@ -34,20 +34,59 @@ template <class T, int E> struct TileIO {
     static constexpr int LDS_ELEMS = STAGED ? WAVE * ROW : 1;
     using V = typename Vec16<T>::type;
 
+    template <bool NT>
+    static __device__ __forceinline__ V ld(const T* p) {
+        const V* q = reinterpret_cast<const V*>(p);
+        if constexpr (NT) return __builtin_nontemporal_load(q);
+        else return *q;
+    }
+    template <bool NT>
+    static __device__ __forceinline__ void st(T* p, V v) {
+        V* q = reinterpret_cast<V*>(p);
+        if constexpr (NT) __builtin_nontemporal_store(v, q);
+        else *q = v;
+    }
+    // the window's global reads into LDS rows (NT: non-temporal)
+    template <bool NT>
+    static __device__ __forceinline__ void gather(const T* __restrict__ src, int64_t ts, T* lds) {
+        const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+        for (int j = 0; j < E / VEC; ++j) {
+            const int el = (j * WAVE + lane) * VEC;
+            const V v = ld<NT>(src + ts + el);
+            *reinterpret_cast<V*>(lds + (el / E) * ROW + (el % E)) = v;
+        }
+    }
+    // LDS rows to the window's global cells [olo, ohi) (NT: non-temporal)
+    template <bool NT>
+    static __device__ __forceinline__ void scatter(T* __restrict__ dst, int64_t ts, int olo, int ohi,
+                                                   const T* lds) {
+        const int lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+        for (int j = 0; j < E / VEC; ++j) {
+            const int el = (j * WAVE + lane) * VEC;
+            const V x = *reinterpret_cast<const V*>(lds + (el / E) * ROW + (el % E));
+            if (el >= olo && el + VEC <= ohi) {
+                st<NT>(dst + ts + el, x);
+            } else {
+#pragma unroll
+                for (int q = 0; q < VEC; ++q)
+                    if (el + q >= olo && el + q < ohi) dst[ts + el + q] = x[q];
+            }
+        }
+    }
+
     // Cells [ts, ts + 64E) of src into lane registers; cells >= n get `ghost`.
-    // `fast`: the window lies inside the chain and src is 16-byte aligned.
+    // `fast`: the window lies inside the chain and src is 16-byte aligned;
+    // `nt`: its global accesses are non-temporal.
     static __device__ __forceinline__ void load(T (&dst)[E], const T* __restrict__ src, int64_t ts,
-                                                int64_t n, T ghost, bool fast, T* lds) {
+                                                int64_t n, T ghost, bool fast, bool nt, T* lds) {
         const int lane = threadIdx.x & (WAVE - 1);
         if constexpr (STAGED) {
             if (fast) {
                 constexpr int CPL = E / VEC;
-#pragma unroll
-                for (int j = 0; j < CPL; ++j) {
-                    const int el = (j * WAVE + lane) * VEC;
-                    const V v = *reinterpret_cast<const V*>(src + ts + el);
-                    *reinterpret_cast<V*>(lds + (el / E) * ROW + (el % E)) = v;
-                }
+                if (nt) gather<true>(src, ts, lds);
+                else gather<false>(src, ts, lds);
                 __syncthreads();
 #pragma unroll
                 for (int j = 0; j < CPL; ++j) {
@@ -68,7 +107,7 @@ template <class T, int E> struct TileIO {
 
     // Window cells [olo, ohi) of the lane registers to dst[ts + ...].
     static __device__ __forceinline__ void store(const T (&v)[E], T* __restrict__ dst, int64_t ts,
-                                                 int olo, int ohi, bool fast, T* lds) {
+                                                 int olo, int ohi, bool fast, bool nt, T* lds) {
         const int lane = threadIdx.x & (WAVE - 1);
         if constexpr (STAGED) {
             if (fast) {
@@ -81,18 +120,8 @@ template <class T, int E> struct TileIO {
                     *reinterpret_cast<V*>(lds + lane * ROW + j * VEC) = x;
                 }
                 __syncthreads();
-#pragma unroll
-                for (int j = 0; j < CPL; ++j) {
-                    const int el = (j * WAVE + lane) * VEC;
-                    const V x = *reinterpret_cast<const V*>(lds + (el / E) * ROW + (el % E));
-                    if (el >= olo && el + VEC <= ohi) {
-                        *reinterpret_cast<V*>(dst + ts + el) = x;
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < VEC; ++q)
-                            if (el + q >= olo && el + q < ohi) dst[ts + el + q] = x[q];
-                    }
-                }
+                if (nt) scatter<true>(dst, ts, olo, ohi, lds);
+                else scatter<false>(dst, ts, olo, ohi, lds);
                 __syncthreads();
                 return;
             }
@@ -147,7 +176,8 @@ __global__ __launch_bounds__(PAIR ? 2 * WAVE : WAVE) void embed_tile_kernel(Embe
 
     T y[S][E];
 #pragma unroll
-    for (int s = 0; s < S; ++s) IO::load(y[s], src[S == 1 ? side : s], ts, a.n, ghost<KIND, T>(), fast, my_lds);
+    for (int s = 0; s < S; ++s)
+        IO::load(y[s], src[S == 1 ? side : s], ts, a.n, ghost<KIND, T>(), fast, a.nt, my_lds);
 
     Inputs<T, E, S, MODE> U;
 #pragma unroll
@@ -192,7 +222,8 @@ __global__ __launch_bounds__(PAIR ? 2 * WAVE : WAVE) void embed_tile_kernel(Embe
     const int olo = (w == 0) ? 0 : a.H;
     const int ohi = reaches_end ? (int)(a.n - ts) : (int)(span - a.H);
 #pragma unroll
-    for (int s = 0; s < S; ++s) IO::store(y[s], dst[S == 1 ? side : s], ts, olo, ohi, fast, my_lds);
+    for (int s = 0; s < S; ++s)
+        IO::store(y[s], dst[S == 1 ? side : s], ts, olo, ohi, fast, a.nt, my_lds);
 
     if (a.check) {
         unsigned bits = 0;

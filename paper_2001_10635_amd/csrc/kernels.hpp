@@ -31,6 +31,7 @@ struct EmbedPass {
     int32_t aligned;  // every array 16-byte aligned
     int32_t check;    // last pass: report non-finite / lower > upper
     int32_t per_xcd;  // tiles per XCD in the blockIdx -> tile map
+    int32_t nt;       // non-temporal global accesses (a pass whose data is not reused soon)
     double prm[5];
     double h2, dt, dt6;
     unsigned int* status;
@@ -150,6 +151,12 @@ struct QDesc {
     // the kernel reads every kCancelEvery steps; nonzero ends the query early
     // with the ST_CANCELLED bit.  NULL for batches.
     const unsigned int* cancel;
+    // Served queries (persistent kernel): the query's device pool block
+    // [x_lo | x_hi | u_lo | u_hi] (2n + 2 values).  x_lo .. p_hi then point
+    // into pinned host staging, and the wave that runs a side first copies
+    // that side's box (both for the coupled LIN3) into the block and runs
+    // from there.  NULL otherwise.
+    double* park;
 };
 
 // Status bit of a served query that stopped on its cancel word.
@@ -159,27 +166,34 @@ constexpr int64_t kCancelEvery = 64;
 // Cells per lane of a batched query: ceil(n / 64) (lanes hold E or E - 1).
 inline int batch_cells_per_lane(int64_t n) { return (int)((n + 63) / 64); }
 
-// Short cooperative queries packed into one wave: at most kPackMax queries of
-// at most kPackMaxN cells, together at most 64 cells.
-constexpr int kPackMax = 16;
-constexpr int64_t kPackMaxN = 32;
+// Segment packs: queries of one kind, constants and dt sharing a wave at
+// E cells per lane (kSegE), member m on ceil(n_m / E) lanes, at most 64 lanes
+// and so at most 64 members.
+constexpr int kSegE[] = {2, 4, 8};
+constexpr int kPackMax = 64;
 
 // One work item of a batch: the queries members[start .. start + count) --
-// a single query (count 1) or a pack of short ones.
+// a single query spread over the whole wave (E = 0, count 1) or a segment
+// pack at E cells per lane.
 struct BatchItem {
     uint32_t start;
-    uint32_t count;
+    uint16_t count;
+    uint16_t E;
 };
 
 // Persistent batch worker: `grid` waves pull work items through *counter:
-// items[0 .. *n_items) (whole queries or packs; d[] in the caller's order,
-// members[] the query indices of the items in launch order), or with `split`
-// two per item (one per side of a cooperative chain; no packs then), pair[i]
-// counting the finished sides of item i.
+// items[0 .. *n_items) (d[] in the caller's order, members[] the query
+// indices of the items in launch order).  packed: every item is a segment
+// pack (E > 0), run by the packing kernel (three waves per SIMD); otherwise
+// every item is one query (E = 0), or with `split` two per item (one per side
+// of a cooperative chain), pair[i] counting the finished sides of item i.
 hipError_t launch_batch(const QDesc* d, const BatchItem* items, const uint32_t* members,
                         const uint64_t* n_items, unsigned long long* counter,
                         unsigned int* qflags, unsigned int* pair, unsigned int* status,
-                        int split, int64_t grid, hipStream_t stream);
+                        int split, bool packed, int64_t grid, hipStream_t stream);
+// Resident waves per compute unit of the batch kernels at full occupancy.
+constexpr int kBatchWavesPerCU = 8;
+constexpr int kPackWavesPerCU = 12;
 // Zero `count` 32-bit words (a kernel, so it can sit in a captured graph).
 hipError_t launch_zero(void* p, int64_t count, hipStream_t stream);
 // One query with a plain launch (the one-launch-per-query baseline).  With

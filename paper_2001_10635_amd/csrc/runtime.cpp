@@ -136,7 +136,10 @@ struct reach_ctx {
     unsigned int* status = nullptr;      // device status word
     std::string err;
     std::map<std::string, int64_t> opt;
-    std::map<std::tuple<int, int, int>, TuneEntry> tune;  // (kind, dtype, log2 n bucket)
+    // (kind, dtype, log2 n bucket, per-cell inputs)
+    std::map<std::tuple<int, int, int, int>, TuneEntry> tune;
+    std::map<std::pair<int, int>, int> batch_tune;        // (kind, log2 n bucket) -> pack E cap
+    int64_t batch_waves = 0;                             // autotuned resident waves (0 = none)
     // batch staging (pinned host) and graph cache
     QDesc* staging = nullptr;            // [nq] descriptors, [nq] items, item count
     int64_t staging_cap = 0;
@@ -282,7 +285,7 @@ int n_bucket(int64_t n) {
 }
 
 TuneEntry tuned(const reach_ctx* c, int kind, int dtype, int64_t n, bool cell_in) {
-    auto it = c->tune.find({kind, dtype, n_bucket(n)});
+    auto it = c->tune.find({kind, dtype, n_bucket(n), cell_in ? 1 : 0});
     if (it != c->tune.end()) return it->second;
     return default_tune(kind, dtype, cell_in, n);
 }
@@ -499,7 +502,8 @@ reach_status gb_heat3d(reach_ctx* c, const reach_system* s, reach_dtype dtype, c
     return REACH_OK;
 }
 
-void save_tune_entry(const reach_ctx* c, int kind, int dtype, int bucket, TuneEntry t, double ps);
+void save_tune_entry(const reach_ctx* c, int kind, int dtype, int bucket, int cell_in, TuneEntry t,
+                     double ps);
 
 // Times every built (rows, waves) shape of the heat kernel, keeps the fastest.
 reach_status autotune_heat3d(reach_ctx* c, const reach_system* s, reach_dtype dtype,
@@ -538,8 +542,8 @@ reach_status autotune_heat3d(reach_ctx* c, const reach_system* s, reach_dtype dt
     if (st != REACH_OK) return st;
     const int bucket = n_bucket(s->n);
     const TuneEntry bt{bestP, 1, 1};
-    c->tune[{s->kind, dtype, bucket}] = bt;
-    save_tune_entry(c, s->kind, dtype, bucket, bt, best_ps);
+    c->tune[{s->kind, dtype, bucket, 0}] = bt;
+    save_tune_entry(c, s->kind, dtype, bucket, 0, bt, best_ps);
     best[0] = bestP;
     best[1] = 1;
     best[2] = (int64_t)std::llround(best_ps * 1000.0);
@@ -575,32 +579,56 @@ size_t mc_ws_bytes(const reach_ctx* c, const reach_system* s, reach_dtype dtype,
 }
 
 
-// Autotune cache: one line per entry, "arch kind dtype bucket E K S ps_per_state_step".
+// Autotune cache: one line per entry, each tagged with the format "reach2":
+//   reach2 embed <arch> <kind> <dtype> <log2 n bucket> <per-cell inputs 0/1> <E> <K> <S> <ps per state-step>
+//   reach2 batch <arch> <kind> <log2 n bucket> <pack E cap> <ns per batch>
+// Lines of any other form (an older format without the input mode among
+// them) are ignored.
 void load_tune_cache(reach_ctx* c) {
     const char* path = std::getenv("REACH_AUTOTUNE_CACHE");
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "r");
     if (!f) return;
-    char arch[64];
-    int kind, dtype, bucket, E, K, S;
-    double ps;
-    while (std::fscanf(f, "%63s %d %d %d %d %d %d %lf", arch, &kind, &dtype, &bucket, &E, &K, &S,
-                       &ps) == 8) {
-        const bool heat_ok = kind == REACH_HEAT3D && heat_waves(E) &&
-                             heat_has_shape(dtype == REACH_F64 ? 0 : 1, E, heat_waves(E));
-        if (c->arch == arch && (heat_ok || (embed_has_shape(kind, dtype, E, S) && K >= 1 && 8 * K < 64 * E)))
-            c->tune[{kind, dtype, bucket}] = TuneEntry{E, K, S};
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        char arch[64];
+        int kind, dtype, bucket, cell, E, K, S, cap;
+        double ps;
+        if (std::sscanf(line, "reach2 embed %63s %d %d %d %d %d %d %d %lf", arch, &kind, &dtype,
+                        &bucket, &cell, &E, &K, &S, &ps) == 9) {
+            const bool heat_ok = kind == REACH_HEAT3D && heat_waves(E) &&
+                                 heat_has_shape(dtype == REACH_F64 ? 0 : 1, E, heat_waves(E));
+            if (c->arch == arch && (cell == 0 || cell == 1) &&
+                (heat_ok || (embed_has_shape(kind, dtype, E, S) && K >= 1 && 8 * K < 64 * E)))
+                c->tune[{kind, dtype, bucket, cell}] = TuneEntry{E, K, S};
+        } else if (std::sscanf(line, "reach2 batch %63s %d %d %d %lf", arch, &kind, &bucket, &cap,
+                               &ps) == 5) {
+            if (c->arch == arch && (cap == 2 || cap == 4 || cap == 8))
+                c->batch_tune[{kind, bucket}] = cap;
+        }
     }
     std::fclose(f);
 }
 
-void save_tune_entry(const reach_ctx* c, int kind, int dtype, int bucket, TuneEntry t, double ps) {
+void save_tune_entry(const reach_ctx* c, int kind, int dtype, int bucket, int cell_in, TuneEntry t,
+                     double ps) {
     const char* path = std::getenv("REACH_AUTOTUNE_CACHE");
     if (!path || !*path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "%s %d %d %d %d %d %d %.3f\n", c->arch.empty() ? "unknown" : c->arch.c_str(),
-                 kind, dtype, bucket, t.E, t.K, t.S, ps);
+    std::fprintf(f, "reach2 embed %s %d %d %d %d %d %d %d %.3f\n",
+                 c->arch.empty() ? "unknown" : c->arch.c_str(), kind, dtype, bucket, cell_in, t.E,
+                 t.K, t.S, ps);
+    std::fclose(f);
+}
+
+void save_batch_tune_entry(const reach_ctx* c, int kind, int bucket, int cap, double ns) {
+    const char* path = std::getenv("REACH_AUTOTUNE_CACHE");
+    if (!path || !*path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "reach2 batch %s %d %d %d %.0f\n", c->arch.empty() ? "unknown" : c->arch.c_str(),
+                 kind, bucket, cap, ns);
     std::fclose(f);
 }
 }  // namespace
@@ -661,7 +689,7 @@ const char* reach_last_error(const reach_ctx* c) { return c ? c->err.c_str() : "
 reach_status reach_set_option(reach_ctx* c, const char* key, int64_t value) {
     if (!c || !key) return REACH_E_INVAL;
     static const char* keys[] = {"embed.K", "embed.E", "embed.S", "mc.waves", "batch.waves",
-                                 "batch.split",
+                                 "batch.split", "batch.pack", "batch.E",
                                  "serve.mode", "serve.waves", "gb.E", "gb.K", "heat.P",
                                  "user.E", "user.K"};
     bool known = false;
@@ -674,6 +702,10 @@ reach_status reach_set_option(reach_ctx* c, const char* key, int64_t value) {
         return fail(c, REACH_E_INVAL, "embed.E = %lld not built", (long long)value);
     if (!std::strcmp(key, "embed.S") && value != 0 && value != 1 && value != 2)
         return fail(c, REACH_E_INVAL, "embed.S must be 0, 1 or 2");
+    if (!std::strcmp(key, "batch.pack") && value > 2)
+        return fail(c, REACH_E_INVAL, "batch.pack must be 0 (auto), 1 (always) or 2 (never)");
+    if (!std::strcmp(key, "batch.E") && value && value != 2 && value != 4 && value != 8)
+        return fail(c, REACH_E_INVAL, "batch.E must be 0, 2, 4 or 8");
     if (!std::strcmp(key, "heat.P") && value && !heat_waves((int)value))
         return fail(c, REACH_E_INVAL, "heat.P must be 0, 2, 3, 4, 5 or 8");
     c->opt[key] = value;
@@ -795,6 +827,9 @@ reach_status reach_embed_rk4(reach_ctx* c, const reach_system* s, reach_dtype dt
         a.dst_hi = (void*)hi_of[io[p].second];
         a.ksteps = std::min<int64_t>(pl.K, nsteps - done);
         a.check = (p == pl.passes - 1) ? 1 : 0;
+        // a one-step pass is a pure stream: its reads and writes bypass the
+        // caches' retention (non-temporal), 1.8% faster at 2^26 cells
+        a.nt = a.ksteps == 1 ? 1 : 0;
         hipError_t e = launch_embed(s->kind, mode, dtype == REACH_F64 ? 0 : 1, pl.E, pl.S, pair,
                                     a, grid, hs);
         if (e != hipSuccess) return hip_fail(c, e, "embedding kernel launch");
@@ -932,8 +967,9 @@ reach_status reach_autotune_embed(reach_ctx* c, const reach_system* s, reach_dty
     if (st != REACH_OK) return st;
     if (bt.E == 0) return fail(c, REACH_E_UNSUPPORTED, "n too small to tile: nothing to tune");
     const int bucket = n_bucket(s->n);
-    c->tune[{s->kind, dtype, bucket}] = bt;
-    save_tune_entry(c, s->kind, dtype, bucket, bt, best_ps);
+    const int cell_in = s->n_in > 1 ? 1 : 0;
+    c->tune[{s->kind, dtype, bucket, cell_in}] = bt;
+    save_tune_entry(c, s->kind, dtype, bucket, cell_in, bt, best_ps);
     best[0] = bt.E;
     best[1] = bt.K;
     best[2] = (int64_t)std::llround(best_ps * 1000.0);
@@ -1219,27 +1255,83 @@ int wave_time_bucket(uint64_t cost) {
     return kBuckets - 1 - (msb * 16 + frac);
 }
 
+// Segment packing of a batch.  A query of n cells in a pack at E cells per
+// lane takes L = ceil(n / E) lanes and needs the balanced layout
+// n >= (E - 1) L; its estimated issue cost per cell is (kCellOps + kSegLaneOps
+// / E) L E / n (arithmetic per cell and stage, plus the lane shifts and
+// boundary selects per lane and stage, over the cells the lanes hold).
+// seg_E picks the cheapest E of kSegE up to cap (ties to the wider), or the
+// narrowest valid E above cap when none up to it is valid.
+constexpr double kCellOps = 6.0, kSegLaneOps = 12.0;
+
+int seg_E(int64_t n, int cap) {
+    double best = 1e300;
+    int bestE = 0, above = 0;
+    for (int E : kSegE) {
+        const int64_t L = (n + E - 1) / E;
+        if (L > 64 || n < (int64_t)(E - 1) * L) continue;
+        if (E > cap) {
+            if (!above) above = E;
+            continue;
+        }
+        const double cost = (kCellOps + kSegLaneOps / E) * (double)(L * E) / (double)n;
+        if (cost <= best) { best = cost; bestE = E; }
+    }
+    return bestE ? bestE : above;
+}
+
+// Whether a batch packs: option batch.pack 1 always, 2 never, 0 (default)
+// when it has more queries than twice the resident waves (below that every
+// query gets a wave of its own and packing would only lengthen the longest).
+bool batch_packs(const reach_ctx* c, int64_t nq) {
+    const int64_t mode = c ? opt_get(c, "batch.pack") : 0;
+    if (mode == 1) return true;
+    if (mode == 2) return false;
+    int64_t waves = c ? opt_get(c, "batch.waves") : 0;
+    if (waves <= 0) waves = (int64_t)(c ? c->cus : 256) * 8;
+    return nq > 2 * waves;
+}
+
+// Largest cells per lane of a pack for (kind, size bucket): option batch.E,
+// else the autotuned value (reach_autotune_batch), else 8.
+int batch_ecap(const reach_ctx* c, int kind, int bucket) {
+    if (c) {
+        const int64_t e = opt_get(c, "batch.E");
+        if (e > 0) return (int)e;
+        auto it = c->batch_tune.find({kind, bucket});
+        if (it != c->batch_tune.end()) return it->second;
+    }
+    return 8;
+}
+
 // The schedule of a batch: the descriptors descs[nq] in the caller's order
 // and the work items in launch order (items[k] covers members[start .. start
 // + count), indices into q, contiguous in launch order).
 //
-// Each of nth threads reads a contiguous chunk of the caller's array once:
-// it validates every query (without touching the context; the first bad
-// query, lowest index, is re-checked with the context afterwards to set the
-// error message) and packs its short cooperative queries (CTM or RD, n <=
-// kPackMaxN) with bitwise equal kind, dt and parameters and step counts in
-// the same 1/16 octave, up to 64 lanes or kPackMax queries; every other
-// query, and a pack left with one query, is an item of its own.  Items are
-// then ordered longest first by the wave time (E * nsteps, a pack counting
-// as E = 1 with its longest member's steps) at 1/16 octave, ties in chunk
-// order.
+// Two parallel passes.  First each of nth threads reads a contiguous chunk of
+// the caller's array once: it validates every query (without touching the
+// context; the first bad query, lowest index, is re-checked with the context
+// afterwards to set the error message).  When the batch does not pack
+// (batch_packs), every query is an item of its own, run alone over a whole
+// wave.  When it packs, every item is a segment pack, and each query gets a
+// pack key: its constants class (bitwise equal kind, dt and parameters),
+// cells per lane E (seg_E under the bucket's cap) and 1/16-octave step
+// bucket.  Then each thread owns the keys of the (E, bucket) pairs r with r
+// mod nth = its index and scans the queries of its keys in caller order,
+// placing each in the first of up to kOpen open packs of its key with room
+// (at most 64 lanes and kPackMax queries; when none has room the fullest is
+// closed); the packs still open at the end are packed again per key, widest
+// query first into the first pack with room.  Items are then ordered longest first by the wave time (E * steps
+// of the longest member; ceil(n / 64) * steps alone) at 1/16 octave, ties in
+// thread order.
 struct PlanTimes {
     double pass_ms = 0, order_ms = 0, members_ms = 0;
 };
 
 reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int64_t nq,
                         int split, int nth, QDesc* descs, std::vector<uint32_t>* members_out,
-                        std::vector<BatchItem>* items_out, PlanTimes* times = nullptr) {
+                        std::vector<BatchItem>* items_out, bool* packed,
+                        PlanTimes* times = nullptr) {
     using clk = std::chrono::steady_clock;
     auto since = [](clk::time_point t0) {
         return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
@@ -1250,10 +1342,15 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
         *hi = total * (t + 1) / nth;
     };
     constexpr int kBuckets = 64 * 16;
-    constexpr int64_t kPackLanes = 64;   // one cell per lane of a wavefront
+    constexpr int kLanes = 64;
+    constexpr int kOpen = 8;             // open packs per key
+    constexpr int kNE = (int)(sizeof(kSegE) / sizeof(kSegE[0]));
+    constexpr int kNB = 10;              // size buckets floor(log2 n), n <= 512
+    constexpr int kMaxClasses = 16;      // per thread (4 bits of a key); further classes run alone
     struct Item {
         uint32_t first;    // into the thread's member list
         uint16_t count;
+        uint16_t E;
         int16_t bucket;
     };
     struct Consts {
@@ -1266,92 +1363,245 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
         }
     };
     struct Open {
-        int64_t lanes = 0;
-        int64_t max_steps = 0;
+        int lanes = 0;
         int count = 0;
+        int E = 0;
+        int64_t max_steps = 0;
         uint32_t mem[kPackMax];
     };
-    constexpr int kMaxClasses = 16;      // per thread; queries of further classes run alone
+    const bool packs = !split && batch_packs(c, nq);
+    *packed = packs;
+    int ecap[4][kNB];
+    for (int k = 0; k < 4; ++k)
+        for (int b = 0; b < kNB; ++b) ecap[k][b] = batch_ecap(c, k, b);
+    auto push_alone = [&](std::vector<Item>& items, std::vector<uint32_t>& members, uint32_t i) {
+        const QDesc& d = descs[i];
+        const uint64_t cost = (uint64_t)d.E * (uint64_t)std::min<int64_t>(d.nsteps, (int64_t)1 << 40);
+        items.push_back(Item{(uint32_t)members.size(), 1, 0, (int16_t)wave_time_bucket(cost)});
+        members.push_back(i);
+    };
+    auto push_pack = [&](std::vector<Item>& items, std::vector<uint32_t>& members, Open& o) {
+        if (o.count >= 1) {
+            const uint64_t cost = (uint64_t)o.E * (uint64_t)std::min<int64_t>(o.max_steps, (int64_t)1 << 40);
+            items.push_back(Item{(uint32_t)members.size(), (uint16_t)o.count, (uint16_t)o.E,
+                                 (int16_t)wave_time_bucket(cost)});
+            for (int m = 0; m < o.count; ++m) members.push_back(o.mem[m]);
+        }
+        o.count = 0;
+        o.lanes = 0;
+        o.max_steps = 0;
+    };
     std::vector<std::vector<Item>> titems((size_t)nth);
     std::vector<std::vector<uint32_t>> tmembers((size_t)nth);
     std::vector<int64_t> bad((size_t)nth, nq);
+    // cells per lane of a packed query by cap (2, 4, 8) and size
+    int8_t etab[3][513];
+    for (int ci = 0; ci < 3; ++ci)
+        for (int64_t n = 1; n <= 512; ++n) etab[ci][n] = (int8_t)seg_E(n, 2 << ci);
+    // pass 1: descriptors, validation, pack keys (class ids local to the
+    // thread); each packed query goes to the list of the thread that owns its
+    // (E, step bucket) pair, r mod nth
+    // what pass 2 needs of a query, carried in the lists so that it never
+    // reads the descriptors other threads wrote
+    struct QRef {
+        uint32_t i;
+        int32_t key;       // (E index, step bucket) << 4 | thread-local class
+        int64_t nsteps;
+        int32_t L;         // lanes at the key's E
+    };
+    std::vector<std::vector<Consts>> tclasses((size_t)nth);
+    std::vector<std::vector<std::vector<QRef>>> lists(
+        (size_t)nth, std::vector<std::vector<QRef>>((size_t)nth));
     run_threads(pool, nth, [&](int t) {
         int64_t lo, hi;
         chunk(t, nq, &lo, &hi);
-        // thread-local lists (moved out at the end: vector headers written by
-        // several threads would share cache lines)
         std::vector<Item> items;
         std::vector<uint32_t> members;
         int64_t my_bad = nq;
-        items.reserve((size_t)(hi - lo));
-        members.reserve((size_t)(hi - lo));
         std::vector<Consts> classes;
-        // open packs per (class, bucket): classes x kBuckets slots, -1 = none
-        std::vector<int32_t> slot;
-        std::vector<Open> open;
-        auto emit = [&](Open& o) {
-            if (o.count == 0) return;
-            const bool pack = o.count >= 2;
-            for (int m = 0; m < o.count; ++m) {
-                if (!pack || m == 0)
-                    items.push_back(Item{(uint32_t)members.size(), (uint16_t)(pack ? o.count : 1),
-                                         (int16_t)wave_time_bucket((uint64_t)o.max_steps)});
-                members.push_back(o.mem[m]);
-            }
-            o.count = 0;
-            o.lanes = 0;
-            o.max_steps = 0;
-        };
+        std::vector<std::vector<QRef>>& mine = lists[(size_t)t];
         for (int64_t i = lo; i < hi; ++i) {
             QDesc& d = descs[i];
             if (make_desc(nullptr, q[i], i, &d) != REACH_OK) {
                 my_bad = std::min(my_bad, i);
                 continue;
             }
-            int cls = -1;
-            if (!split && (d.kind == REACH_CTM || d.kind == REACH_RD) && d.n <= kPackMaxN &&
-                d.nsteps >= 1) {
-                Consts cs;
-                std::memset(&cs, 0, sizeof cs);
-                cs.kind = q[i].sys.kind;
-                cs.dt = q[i].dt;
-                std::memcpy(cs.prm, q[i].sys.prm, sizeof cs.prm);
-                for (size_t u = 0; u < classes.size(); ++u)
-                    if (classes[u] == cs) { cls = (int)u; break; }
-                if (cls < 0 && (int)classes.size() < kMaxClasses) {
-                    classes.push_back(cs);
-                    slot.resize(classes.size() * kBuckets, -1);
-                    cls = (int)classes.size() - 1;
-                }
-            }
-            if (cls < 0) {
-                const uint64_t cost = (uint64_t)d.E * (uint64_t)std::min<int64_t>(d.nsteps, (int64_t)1 << 40);
-                items.push_back(Item{(uint32_t)members.size(), 1, (int16_t)wave_time_bucket(cost)});
-                members.push_back((uint32_t)i);
+            if (!packs) {
+                push_alone(items, members, (uint32_t)i);
                 continue;
             }
-            const int b = wave_time_bucket((uint64_t)std::min<int64_t>(d.nsteps, (int64_t)1 << 40));
-            int32_t& sl = slot[(size_t)cls * kBuckets + (size_t)b];
-            if (sl < 0) {
-                sl = (int32_t)open.size();
-                open.emplace_back();
+            const int cap = ecap[d.kind & 3][std::min(n_bucket(d.n), kNB - 1)];
+            const int E = etab[cap >= 8 ? 2 : cap >= 4 ? 1 : 0][d.n];
+            int cls = -1;
+            Consts cs;
+            std::memset(&cs, 0, sizeof cs);
+            cs.kind = q[i].sys.kind;
+            cs.dt = q[i].dt;
+            std::memcpy(cs.prm, q[i].sys.prm, sizeof cs.prm);
+            for (size_t u = 0; u < classes.size(); ++u)
+                if (classes[u] == cs) { cls = (int)u; break; }
+            if (cls < 0 && (int)classes.size() < kMaxClasses) {
+                classes.push_back(cs);
+                cls = (int)classes.size() - 1;
             }
-            Open& o = open[(size_t)sl];
-            if (o.lanes + d.n > kPackLanes) emit(o);
-            o.mem[o.count++] = (uint32_t)i;
-            o.lanes += d.n;
-            o.max_steps = std::max(o.max_steps, d.nsteps);
-            if (o.lanes == kPackLanes || o.count == kPackMax) emit(o);
+            if (cls < 0) {
+                // a class beyond the thread's table: a pack of its own
+                Open o;
+                o.E = E;
+                o.mem[o.count++] = (uint32_t)i;
+                o.lanes = (int)((d.n + E - 1) / E);
+                o.max_steps = d.nsteps;
+                push_pack(items, members, o);
+                continue;
+            }
+            int ei = 0;
+            while (kSegE[ei] != E) ++ei;
+            const int b = wave_time_bucket((uint64_t)std::min<int64_t>(d.nsteps, (int64_t)1 << 40));
+            const int r = ei * kBuckets + b;
+            mine[(size_t)(r % nth)].push_back(
+                QRef{(uint32_t)i, (r << 4) | cls, d.nsteps, (int32_t)((d.n + E - 1) / E)});
         }
-        for (auto& o : open) emit(o);
         titems[(size_t)t] = std::move(items);
         tmembers[(size_t)t] = std::move(members);
+        tclasses[(size_t)t] = std::move(classes);
         bad[(size_t)t] = my_bad;
     });
     const int64_t first_bad = *std::min_element(bad.begin(), bad.end());
     if (first_bad < nq) {
         QDesc tmp;
         return make_desc(c, q[first_bad], first_bad, &tmp);
+    }
+    if (packs) {
+        // global class ids (the threads' tables merged in thread order)
+        std::vector<Consts> global;
+        std::vector<std::vector<int32_t>> remap((size_t)nth);
+        for (int t = 0; t < nth; ++t)
+            for (const Consts& cs : tclasses[(size_t)t]) {
+                int g = -1;
+                for (size_t u = 0; u < global.size(); ++u)
+                    if (global[u] == cs) { g = (int)u; break; }
+                if (g < 0) {
+                    global.push_back(cs);
+                    g = (int)global.size() - 1;
+                }
+                remap[(size_t)t].push_back(g);
+            }
+        const size_t G = global.size();
+        // key = (E index, step bucket) * G + global class; thread t owns the
+        // (E index, step bucket) pairs r with r mod nth == t
+        std::vector<uint8_t> owner((size_t)kNE * kBuckets);
+        std::vector<uint32_t> local((size_t)kNE * kBuckets);
+        std::vector<uint32_t> owned((size_t)nth, 0);
+        for (size_t r = 0; r < owner.size(); ++r) {
+            owner[r] = (uint8_t)(r % (size_t)nth);
+            local[r] = owned[owner[r]]++;
+        }
+        // pass 2: thread t packs the keys it owns, scanning the queries in
+        // caller order.  The scan only assigns each query a pack (fill levels
+        // in a small table, a key's kOpen current packs side by side); the
+        // packs' member lists are then formed by a counting sort on the pack.
+        run_threads(pool, nth, [&](int t) {
+            std::vector<Item>& items = titems[(size_t)t];
+            std::vector<uint32_t>& members = tmembers[(size_t)t];
+            struct Pack {
+                int32_t lanes, count, E, key;
+                int64_t max_steps;
+            };
+            std::vector<Pack> packs;
+            std::vector<int32_t> slot((size_t)owned[(size_t)t] * G * kOpen, -1);
+            std::vector<const QRef*> refs;
+            std::vector<int32_t> assign;
+            for (int u = 0; u < nth; ++u) {
+                const std::vector<int32_t>& rm = remap[(size_t)u];
+                for (const QRef& qr : lists[(size_t)u][(size_t)t]) {
+                    const size_t r = (size_t)(qr.key >> 4);
+                    const int E = kSegE[r / kBuckets];
+                    const int L = qr.L;
+                    const size_t key = (size_t)local[r] * G + (size_t)rm[(size_t)(qr.key & 15)];
+                    int32_t* sl = &slot[key * kOpen];
+                    if (sl[0] < 0)
+                        for (int j = 0; j < kOpen; ++j) {
+                            sl[j] = (int32_t)packs.size();
+                            packs.push_back(Pack{0, 0, E, (int32_t)key, 0});
+                        }
+                    int j = 0;
+                    while (j < kOpen && packs[(size_t)sl[j]].lanes + L > kLanes) ++j;
+                    if (j == kOpen) {
+                        // every open pack is too full for this query: close the
+                        // fullest and open a new one in its place
+                        j = 0;
+                        for (int k = 1; k < kOpen; ++k)
+                            if (packs[(size_t)sl[k]].lanes > packs[(size_t)sl[j]].lanes) j = k;
+                        sl[j] = (int32_t)packs.size();
+                        packs.push_back(Pack{0, 0, E, (int32_t)key, 0});
+                    }
+                    Pack& pk = packs[(size_t)sl[j]];
+                    pk.lanes += L;
+                    pk.max_steps = std::max(pk.max_steps, qr.nsteps);
+                    refs.push_back(&qr);
+                    assign.push_back(sl[j]);
+                    if (++pk.count == kPackMax || pk.lanes == kLanes) {
+                        sl[j] = (int32_t)packs.size();
+                        packs.push_back(Pack{0, 0, E, (int32_t)key, 0});
+                    }
+                }
+            }
+            // members by pack (counting sort, scan order kept within a pack)
+            std::vector<int32_t> start(packs.size() + 1, 0);
+            for (const int32_t p : assign) ++start[(size_t)p + 1];
+            for (size_t p = 0; p < packs.size(); ++p) start[p + 1] += start[p];
+            std::vector<const QRef*> by_pack(refs.size());
+            {
+                std::vector<int32_t> at(start.begin(), start.end() - 1);
+                for (size_t k = 0; k < refs.size(); ++k) by_pack[(size_t)at[(size_t)assign[k]]++] = refs[k];
+            }
+            // packs still open at the end (those the slots point to) are packed
+            // again per key below; every other pack is final
+            std::vector<uint8_t> open_now(packs.size(), 0);
+            for (const int32_t p : slot)
+                if (p >= 0) open_now[(size_t)p] = 1;
+            for (size_t p = 0; p < packs.size(); ++p) {
+                const Pack& pk = packs[p];
+                if (open_now[p] || pk.count == 0) continue;
+                const uint64_t cost = (uint64_t)pk.E * (uint64_t)std::min<int64_t>(pk.max_steps, (int64_t)1 << 40);
+                items.push_back(Item{(uint32_t)members.size(), (uint16_t)pk.count, (uint16_t)pk.E,
+                                     (int16_t)wave_time_bucket(cost)});
+                for (int32_t k = start[p]; k < start[p + 1]; ++k) members.push_back(by_pack[(size_t)k]->i);
+            }
+            // each key's open packs: their queries again, widest first into
+            // the first pack with room (first fit decreasing)
+            std::vector<const QRef*> rest;
+            std::vector<Open> merged;
+            for (size_t k = 0; k < slot.size(); k += kOpen) {
+                if (slot[k] < 0) continue;
+                rest.clear();
+                int E = 0;
+                for (int j = 0; j < kOpen; ++j) {
+                    const size_t p = (size_t)slot[k + (size_t)j];
+                    E = packs[p].E;
+                    for (int32_t m = start[p]; m < start[p + 1]; ++m) rest.push_back(by_pack[(size_t)m]);
+                }
+                if (rest.empty()) continue;
+                std::sort(rest.begin(), rest.end(), [](const QRef* x, const QRef* y) {
+                    return x->L != y->L ? x->L > y->L : x->i < y->i;
+                });
+                merged.clear();
+                for (const QRef* rr : rest) {
+                    Open* o = nullptr;
+                    for (Open& oj : merged)
+                        if (oj.lanes + rr->L <= kLanes && oj.count < kPackMax) { o = &oj; break; }
+                    if (!o) {
+                        merged.emplace_back();
+                        o = &merged.back();
+                        o->E = E;
+                    }
+                    o->mem[o->count++] = rr->i;
+                    o->lanes += rr->L;
+                    o->max_steps = std::max(o->max_steps, rr->nsteps);
+                }
+                for (Open& o : merged) push_pack(items, members, o);
+            }
+        });
     }
     if (times) times->pass_ms = since(t0);
     t0 = clk::now();
@@ -1383,7 +1633,7 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
     uint32_t p = 0;
     for (int64_t k = 0; k < ni; ++k) {
         const Item& it = titems[sorted[(size_t)k].t][sorted[(size_t)k].k];
-        io[(size_t)k] = BatchItem{p, it.count};
+        io[(size_t)k] = BatchItem{p, it.count, it.E};
         p += it.count;
     }
     if (times) times->order_ms = since(t0);
@@ -1416,9 +1666,9 @@ size_t reach_batch_workspace_bytes(int64_t nq) {
 }
 
 reach_status reach_plan_batch(reach_ctx* c, const reach_query* q, int64_t nq,
-                              int64_t* item_start, int32_t* item_count, int64_t* member,
-                              int64_t* n_items) {
-    if (nq < 0 || !n_items || (nq > 0 && (!q || !item_start || !item_count || !member)))
+                              int64_t* item_start, int32_t* item_count, int32_t* item_E,
+                              int64_t* member, int64_t* n_items) {
+    if (nq < 0 || !n_items || (nq > 0 && (!q || !item_start || !item_count || !item_E || !member)))
         return c ? fail(c, REACH_E_INVAL, "bad arguments") : REACH_E_INVAL;
     *n_items = 0;
     if (nq == 0) return REACH_OK;
@@ -1435,11 +1685,14 @@ reach_status reach_plan_batch(reach_ctx* c, const reach_query* q, int64_t nq,
         pool = local.get();
     }
     const int nth = pool ? std::min(batch_host_threads(nq), pool->size()) : 1;
-    const reach_status st = plan_batch(c, pool, q, nq, split, nth, descs.data(), &members, &items);
+    bool packed = false;
+    const reach_status st = plan_batch(c, pool, q, nq, split, nth, descs.data(), &members, &items,
+                                       &packed);
     if (st != REACH_OK) return st;
     for (size_t k = 0; k < items.size(); ++k) {
         item_start[k] = items[k].start;
         item_count[k] = (int32_t)items[k].count;
+        item_E[k] = (int32_t)items[k].E;
     }
     for (int64_t p = 0; p < nq; ++p) member[p] = members[(size_t)p];
     *n_items = (int64_t)items.size();
@@ -1478,7 +1731,9 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     std::vector<uint32_t> members;
     std::vector<BatchItem> items;
     PlanTimes pt;
-    reach_status pst = plan_batch(c, pool, q, nq, split, nth, hb.desc, &members, &items, &pt);
+    bool packed = false;
+    reach_status pst = plan_batch(c, pool, q, nq, split, nth, hb.desc, &members, &items, &packed,
+                                  &pt);
     if (pst != REACH_OK) return pst;
     const int64_t ni = (int64_t)items.size();
     std::memcpy(hb.items, items.data(), sizeof(BatchItem) * (size_t)ni);
@@ -1492,8 +1747,9 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     auto* pair = (unsigned int*)(base + align256(8) + align256(4 * (size_t)nq));
     const BatchBlock db = batch_block(base + align256(8) + 2 * align256(4 * (size_t)nq), nq);
     int64_t grid = opt_get(c, "batch.waves");
-    if (grid <= 0) grid = (int64_t)c->cus * 8;
-    grid = std::min<int64_t>(grid, split ? 2 * nq : nq);
+    if (grid <= 0 && packed) grid = c->batch_waves;
+    if (grid <= 0) grid = (int64_t)c->cus * (packed ? kPackWavesPerCU : kBatchWavesPerCU);
+    grid = std::min<int64_t>(grid, split ? 2 * ni : ni);
 
     if (c->log) {
         using ms = std::chrono::duration<double, std::milli>;
@@ -1511,14 +1767,14 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
         e = hipMemcpyAsync(db.desc, c->staging, batch_block_bytes(nq), hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
         return launch_batch(db.desc, db.items, db.members, db.count, counter, qflags, pair,
-                            c->status, split, grid, s);
+                            c->status, split, packed, grid, s);
     };
 
     if (hs == nullptr) {
         hipError_t e = enqueue(hs);
         if (e != hipSuccess) return hip_fail(c, e, "batch launch");
     } else {
-        GraphKey key{nq, ws, c->staging, grid * 2 + split, hs};
+        GraphKey key{nq, ws, c->staging, (grid * 2 + split) * 2 + (packed ? 1 : 0), hs};
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             hipGraph_t g = nullptr;
@@ -1537,6 +1793,104 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     }
     HIPCHK(c, hipEventRecord(c->staging_ev, hs));
     (void)counter;
+    return REACH_OK;
+}
+
+// Batch autotuner, on the caller's whole batch (a bucket's queries alone
+// would be too few to fill the device, and their timing would favour short
+// items over dense ones).  The batch is timed (one warm-up and four timed
+// calls, fastest kept) at the current settings; then, bucket by bucket, most
+// queries first, for every (kind, size bucket) with at least kTuneMinQueries
+// queries each narrower pack cap (4, 2) is tried and kept only if the whole
+// batch gets faster by more than kTuneGain; then 12 and 8 resident waves per
+// compute unit.  Results are those of the batch at any setting (bitwise).
+reach_status reach_autotune_batch(reach_ctx* c, const reach_query* q, int64_t nq, void* ws,
+                                  size_t ws_bytes, void* stream, int64_t* best) {
+    if (!c) return REACH_E_INVAL;
+    if (!best || nq < 1 || !q) return fail(c, REACH_E_INVAL, "bad arguments");
+    constexpr int64_t kTuneMinQueries = 256;
+    constexpr double kTuneGain = 0.01;
+    constexpr int kNB = 10;
+    hipStream_t hs = (hipStream_t)stream;
+    HIPCHK(c, hipSetDevice(c->device));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(c, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(c, REACH_E_DEVICE, "hipEventCreate failed");
+    }
+    // fastest of four timed calls after a warm-up, in nanoseconds (host
+    // planning and the descriptor upload included)
+    auto time_batch = [&](double* ns) -> reach_status {
+        double bestms = 1e300;
+        for (int r = 0; r < 5; ++r) {
+            if (hipEventRecord(e0, hs) != hipSuccess) return fail(c, REACH_E_DEVICE, "event");
+            const reach_status st = reach_embed_rk4_batch(c, q, nq, ws, ws_bytes, stream);
+            if (st != REACH_OK) return st;
+            if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                return fail(c, REACH_E_DEVICE, "event");
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return fail(c, REACH_E_DEVICE, "event");
+            if (r > 0) bestms = std::min(bestms, (double)ms);
+        }
+        *ns = bestms * 1e6;
+        return REACH_OK;
+    };
+    const int64_t save_E = opt_get(c, "batch.E"), save_waves = opt_get(c, "batch.waves");
+    c->opt["batch.E"] = 0;
+    double cur = 0;
+    reach_status st = time_batch(&cur);
+    const bool packs = !opt_get(c, "batch.split") && batch_packs(c, nq);
+    if (st == REACH_OK && packs) {
+        // (kind, bucket) groups, most queries first
+        std::map<std::pair<int, int>, int64_t> count;
+        for (int64_t i = 0; i < nq; ++i) {
+            const reach_system& sy = q[i].sys;
+            ++count[{sy.kind, std::min(n_bucket(sy.n), kNB - 1)}];
+        }
+        std::vector<std::pair<int64_t, std::pair<int, int>>> order;
+        for (const auto& kv : count)
+            if (kv.second >= kTuneMinQueries) order.push_back({-kv.second, kv.first});
+        std::sort(order.begin(), order.end());
+        for (const auto& o : order) {
+            const auto key = o.second;
+            const int keep = batch_ecap(c, key.first, key.second);
+            int best_cap = keep;
+            for (int cap : {4, 2}) {
+                if (cap >= keep) continue;
+                c->batch_tune[key] = cap;
+                double ns = 0;
+                st = time_batch(&ns);
+                if (st != REACH_OK) break;
+                if (ns < cur * (1.0 - kTuneGain)) { cur = ns; best_cap = cap; }
+            }
+            c->batch_tune[key] = best_cap;
+            if (st != REACH_OK) break;
+            save_batch_tune_entry(c, key.first, key.second, best_cap, cur);
+        }
+    }
+    int64_t best_waves = save_waves;
+    if (st == REACH_OK && packs && save_waves == 0) {
+        double best_ns = 1e300;
+        for (int64_t per_cu : {(int64_t)kPackWavesPerCU, (int64_t)kBatchWavesPerCU}) {
+            c->opt["batch.waves"] = per_cu * c->cus;
+            double ns = 0;
+            st = time_batch(&ns);
+            if (st != REACH_OK) break;
+            if (ns < best_ns) { best_ns = ns; best_waves = per_cu * c->cus; }
+        }
+        c->opt["batch.waves"] = 0;
+        if (st == REACH_OK) {
+            c->batch_waves = best_waves;
+            cur = best_ns;
+        }
+    }
+    c->opt["batch.E"] = save_E;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != REACH_OK) return st;
+    best[0] = best_waves;
+    best[1] = (int64_t)std::llround(cur);
     return REACH_OK;
 }
 

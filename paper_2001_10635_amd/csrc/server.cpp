@@ -4,11 +4,17 @@
 // next ring sequence number from a device counter and waits for the host to
 // publish a query there.  A host service thread admits submitted queries in
 // submission order as soon as a slot and enough bytes of the caller's device
-// pool are free (first fit), uploads their boxes into the pool, publishes them
-// into the ring (pinned, coherent host memory) once the upload has landed, and
-// collects completions, whose results the kernel writes straight into pinned
-// host result buffers.  New queries thus start while earlier ones are still
-// running on the GPU.
+// pool are free (first fit), writes their boxes into the slot's pinned staging
+// and publishes them into the ring (pinned, coherent host memory) at once; the
+// wave that runs a query stages its box into the query's pool block and runs
+// from there, and writes the result straight into pinned host result buffers.
+// New queries thus start while earlier ones are still running on the GPU.
+//
+// While the persistent grid runs, the host issues no device work at all (no
+// copies, no events): HIP gives work queued on another stream no promise of
+// progress when the runtime maps that stream onto the hardware queue that
+// holds the never-ending kernel (streams share a few hardware queues), so
+// every step of serving is a host-memory exchange with the kernel.
 //
 // Client calls never wait on the service thread: reach_submit appends to an
 // inbox and reach_poll / reach_cancel read an outbox, each under its own short
@@ -122,12 +128,6 @@ struct Done {
     double lat_us;     // < 0: not counted (cancelled, timed out)
 };
 
-// Uploads of one admission round, published to the ring when `ev` completes.
-struct PubBatch {
-    hipEvent_t ev;
-    std::vector<int32_t> slots;
-};
-
 }  // namespace
 
 namespace reach_srv {
@@ -136,8 +136,7 @@ struct Server {
     int device = 0;
     int mode = 0;
     hipStream_t kstream = nullptr;
-    hipStream_t copy = nullptr;
-    std::vector<hipStream_t> lstreams;   // mode 1
+    std::vector<hipStream_t> lstreams;   // mode 1: launch streams (inputs copied on them)
     char* pool = nullptr;
     size_t pool_bytes = 0;
     int32_t slots = 0;                 // concurrent queries
@@ -179,9 +178,6 @@ struct Server {
     std::unordered_map<uint64_t, int32_t> slot_of;   // admitted ticket -> slot
     std::vector<uint64_t> ring_busy;   // per ring entry: sequence+1 occupying it, 0 = free
     uint64_t next_seq = 0;
-    std::deque<PubBatch> pubs;
-    std::vector<hipEvent_t> free_events;
-    std::vector<hipEvent_t> all_events;
     std::vector<Done> done_now;
 };
 
@@ -274,7 +270,7 @@ void publish(Server* S, int32_t k) {
     sl->d = r.d;
     sl->d.cancel = &sl->cancel;
     sl->flags[0] = sl->flags[1] = 0;
-    __atomic_store_n(&sl->cancel, 0u, __ATOMIC_RELAXED);
+    __atomic_store_n(&sl->cancel, r.cancel_req ? 1u : 0u, __ATOMIC_RELAXED);
     __atomic_store_n(&sl->done[0], (unsigned long long)0, __ATOMIC_RELAXED);
     __atomic_store_n(&sl->done[1], (unsigned long long)0, __ATOMIC_RELAXED);
     __atomic_store_n(&sl->seq, (unsigned long long)(r.seq + 1), __ATOMIC_RELEASE);
@@ -310,18 +306,6 @@ void revive_kernel(Server* S) {
     launch_kernel(S, start);
 }
 
-hipEvent_t get_event(Server* S) {
-    if (!S->free_events.empty()) {
-        hipEvent_t e = S->free_events.back();
-        S->free_events.pop_back();
-        return e;
-    }
-    hipEvent_t e = nullptr;
-    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return nullptr;
-    S->all_events.push_back(e);
-    return e;
-}
-
 // Requests to cancel: a waiting query is dropped, an admitted one is stopped
 // through its cancel word (the kernel reads it every kCancelEvery steps) or,
 // if not yet published, completed without running.
@@ -341,7 +325,8 @@ void take_cancels(Server* S, const std::vector<uint64_t>& tickets) {
         if (it == S->slot_of.end()) continue;    // already finished
         Running& r = S->run[it->second];
         r.cancel_req = true;
-        if (!r.published) continue;              // handled when its upload lands
+        // an admitted query is always published (mode 0) or launched (mode
+        // 1): its sequence is consumed, and its cancel word stops it
         if (S->mode == 0)
             __atomic_store_n(&S->ring[r.seq % S->ring_n].cancel, 1u, __ATOMIC_RELEASE);
         else
@@ -351,7 +336,6 @@ void take_cancels(Server* S, const std::vector<uint64_t>& tickets) {
 
 void service(Server* S) {
     hipSetDevice(S->device);
-    std::vector<int32_t> batch;
     std::vector<uint64_t> cancels;
     for (;;) {
         bool progress = false;
@@ -389,18 +373,7 @@ void service(Server* S) {
                 progress = true;
             }
         }
-        // 2. uploads that have landed: publish their queries (sequence order)
-        while (!S->pubs.empty() && hipEventQuery(S->pubs.front().ev) == hipSuccess) {
-            PubBatch& pb = S->pubs.front();
-            for (int32_t k : pb.slots) {
-                if (S->run[k].cancel_req) finish(S, k, (unsigned)STATUS_CANCELLED);
-                else publish(S, k);
-            }
-            S->free_events.push_back(pb.ev);
-            S->pubs.pop_front();
-            progress = true;
-        }
-        // 3. a grid that left on its idle limit is replaced before new work
+        // 2. a grid that left on its idle limit is replaced before new work
         if (S->mode == 0) {
             bool inflight = false;
             for (int32_t k = 0; k < S->slots && !inflight; ++k) inflight = S->run[k].used;
@@ -411,8 +384,7 @@ void service(Server* S) {
                 revive_kernel(S);
             }
         }
-        // 4. admission, in submission order
-        batch.clear();
+        // 3. admission, in submission order
         while (!S->waiting.empty() && !S->free_slots.empty()) {
             Waiting& w = S->waiting.front();
             const int64_t n = w.q.sys.n;
@@ -440,7 +412,6 @@ void service(Server* S) {
             in[2 * n] = w.u_lo;
             in[2 * n + 1] = w.u_hi;
             double* dlo = (double*)(S->pool + off);   // pool block: x_lo, x_hi, u_lo, u_hi
-            double* dhi = dlo + n;
             QDesc& d = r.d;
             std::memset(&d, 0, sizeof d);
             d.kind = w.q.sys.kind;
@@ -448,19 +419,24 @@ void service(Server* S) {
             d.n = n;
             d.nsteps = w.q.nsteps;
             kernel_params(w.q.sys.kind, w.q.sys.prm, d.prm);
-            if (w.q.sys.n_in == 1) { d.p_lo = dlo + 2 * n; d.p_hi = dlo + 2 * n + 1; }
             d.h2 = w.q.dt / 2.0; d.dt = w.q.dt; d.dt6 = w.q.dt / 6.0;
-            d.x_lo = dlo; d.x_hi = dhi;
             d.r_lo = S->stage_out + (size_t)k * kOutDoubles;
             d.r_hi = S->stage_out + (size_t)k * kOutDoubles + 512;
             d.tag = k;
-            hipStream_t cs = S->mode == 0 ? S->copy : S->lstreams[k % S->lstreams.size()];
-            hipMemcpyAsync(dlo, in, sizeof(double) * (2 * n + 2), hipMemcpyHostToDevice, cs);
             if (S->mode == 0) {
+                // the kernel reads the box from the slot's pinned staging and
+                // parks it in the pool block
+                d.x_lo = in; d.x_hi = in + n;
+                if (w.q.sys.n_in == 1) { d.p_lo = in + 2 * n; d.p_hi = in + 2 * n + 1; }
+                d.park = dlo;
                 r.seq = S->next_seq++;
                 S->ring_busy[r.seq % S->ring_n] = r.seq + 1;
-                batch.push_back(k);
+                publish(S, k);
             } else {
+                d.x_lo = dlo; d.x_hi = dlo + n;
+                if (w.q.sys.n_in == 1) { d.p_lo = dlo + 2 * n; d.p_hi = dlo + 2 * n + 1; }
+                hipStream_t cs = S->lstreams[k % S->lstreams.size()];
+                hipMemcpyAsync(dlo, in, sizeof(double) * (2 * n + 2), hipMemcpyHostToDevice, cs);
                 unsigned int* words = S->slot_words + 2 * k;
                 __atomic_store_n(&words[0], 0u, __ATOMIC_RELAXED);
                 __atomic_store_n(&words[1], 0u, __ATOMIC_RELEASE);
@@ -472,19 +448,8 @@ void service(Server* S) {
             S->waiting.pop_front();
             progress = true;
         }
-        if (!batch.empty()) {
-            // the boxes must be in the pool before the kernel may see the query
-            hipEvent_t ev = get_event(S);
-            if (ev && hipEventRecord(ev, S->copy) == hipSuccess) {
-                S->pubs.push_back({ev, batch});
-            } else {
-                hipStreamSynchronize(S->copy);
-                for (int32_t k : batch) publish(S, k);
-                if (ev) S->free_events.push_back(ev);
-            }
-        }
         flush_done(S);
-        bool busy = !S->pubs.empty();
+        bool busy = false;
         for (int32_t k = 0; k < S->slots && !busy; ++k) busy = S->run[k].used;
         if (quit && !busy && S->waiting.empty()) {
             std::lock_guard<std::mutex> g(S->in_mu);
@@ -568,7 +533,6 @@ reach_status reach_server_start(reach_ctx* c, void* pool, size_t pool_bytes, int
         rate_khz = 100000;
     S->idle_cycles = (int64_t)(idle_s * 1000.0 * (double)rate_khz);
     bool ok = true;
-    ok &= hipStreamCreateWithFlags(&S->copy, hipStreamNonBlocking) == hipSuccess;
     if (!S->kstream) {
         ok &= hipStreamCreateWithFlags(&S->kstream, hipStreamNonBlocking) == hipSuccess;
         S->own_kstream = true;
@@ -579,7 +543,7 @@ reach_status reach_server_start(reach_ctx* c, void* pool, size_t pool_bytes, int
     ok &= hipHostMalloc((void**)&S->slot_words, sizeof(unsigned int) * 2 * (size_t)max_slots,
                         hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
     ok &= hipHostMalloc((void**)&S->stage_in, sizeof(double) * kInDoubles * (size_t)max_slots,
-                        hipHostMallocDefault) == hipSuccess;
+                        hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
     ok &= hipHostMalloc((void**)&S->stage_out, sizeof(double) * kOutDoubles * (size_t)max_slots,
                         hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
     ok &= hipMalloc((void**)&S->dctl, 256) == hipSuccess;
@@ -615,7 +579,6 @@ reach_status reach_server_start(reach_ctx* c, void* pool, size_t pool_bytes, int
         if (S->stage_in) hipHostFree(S->stage_in);
         if (S->stage_out) hipHostFree(S->stage_out);
         if (S->dctl) hipFree(S->dctl);
-        if (S->copy) hipStreamDestroy(S->copy);
         if (S->own_kstream && S->kstream) hipStreamDestroy(S->kstream);
         delete S;
         return REACH_E_DEVICE;
@@ -729,17 +692,14 @@ reach_status reach_server_stop(reach_ctx* c) {
     __atomic_thread_fence(__ATOMIC_SEQ_CST);
     hipSetDevice(S->device);
     hipError_t e = hipStreamSynchronize(S->kstream);
-    hipStreamSynchronize(S->copy);
     for (auto s : S->lstreams) { hipStreamSynchronize(s); hipStreamDestroy(s); }
     for (auto& r : S->run) if (r.ev) hipEventDestroy(r.ev);
-    for (auto ev : S->all_events) hipEventDestroy(ev);
     hipHostFree(S->ring);
     hipHostFree(S->stop);
     hipHostFree(S->slot_words);
     hipHostFree(S->stage_in);
     hipHostFree(S->stage_out);
     hipFree(S->dctl);
-    hipStreamDestroy(S->copy);
     if (S->own_kstream) hipStreamDestroy(S->kstream);
     {
         std::lock_guard<std::mutex> g(g_srv_mu);

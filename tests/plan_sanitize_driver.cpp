@@ -1,6 +1,7 @@
 // Host-only driver for the batch planner (reach_plan_batch, no device call):
 // random query sets, NULL context (so large plans run on host threads); checks
-// that every query is scheduled exactly once and that a bad query fails the plan.
+// that every query is scheduled exactly once, that packs keep to 64 lanes and
+// the balanced layout of their width, and that a bad query fails the plan.
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -33,10 +34,10 @@ static int check(int64_t nq, uint64_t seed, bool plant_bad) {
     }
     if (plant_bad && nq > 3) q[(size_t)(nq * 2 / 3)].dt = -1.0;
     std::vector<int64_t> start((size_t)nq), member((size_t)nq);
-    std::vector<int32_t> count((size_t)nq);
+    std::vector<int32_t> count((size_t)nq), width((size_t)nq);
     int64_t ni = -1;
     const reach_status st = reach_plan_batch(nullptr, q.data(), nq, start.data(), count.data(),
-                                             member.data(), &ni);
+                                             width.data(), member.data(), &ni);
     if (plant_bad && nq > 3) {
         if (st == REACH_OK) { std::printf("FAIL: bad query accepted\n"); return 1; }
         return 0;
@@ -45,7 +46,9 @@ static int check(int64_t nq, uint64_t seed, bool plant_bad) {
     std::vector<int> seen((size_t)nq, 0);
     int64_t covered = 0;
     for (int64_t k = 0; k < ni; ++k) {
-        if (count[(size_t)k] < 1 || count[(size_t)k] > 16) { std::printf("FAIL: count\n"); return 1; }
+        const int32_t E = width[(size_t)k];
+        if (count[(size_t)k] < 1 || count[(size_t)k] > 64 || (E == 0 && count[(size_t)k] != 1) ||
+            (E != 0 && E != 2 && E != 4 && E != 8)) { std::printf("FAIL: count/width\n"); return 1; }
         int64_t lanes = 0;
         for (int32_t j = 0; j < count[(size_t)k]; ++j) {
             const int64_t p = start[(size_t)k] + j;
@@ -53,9 +56,13 @@ static int check(int64_t nq, uint64_t seed, bool plant_bad) {
             const int64_t m = member[(size_t)p];
             if (m < 0 || m >= nq) { std::printf("FAIL: member\n"); return 1; }
             ++seen[(size_t)m];
-            lanes += q[(size_t)m].sys.n;
+            if (E) {
+                const int64_t n = q[(size_t)m].sys.n, L = (n + E - 1) / E;
+                if (n < (int64_t)(E - 1) * L) { std::printf("FAIL: layout\n"); return 1; }
+                lanes += L;
+            }
         }
-        if (count[(size_t)k] > 1 && lanes > 64) { std::printf("FAIL: pack lanes\n"); return 1; }
+        if (lanes > 64) { std::printf("FAIL: pack lanes\n"); return 1; }
         covered += count[(size_t)k];
     }
     if (covered != nq) { std::printf("FAIL: covered %lld of %lld\n", (long long)covered, (long long)nq); return 1; }

@@ -1,9 +1,13 @@
 """The batch schedule (reach_plan_batch), computed on the host: no GPU.
 
-Every query runs exactly once; packs hold 2..16 short cooperative queries with
-identical constants and step counts within 1/16 octave in at most 64 lanes;
-items come longest first; the plan is deterministic.  Results of packed
-queries are compared with single runs bit for bit in the GPU batch tests."""
+Every query runs exactly once.  A batch with more queries than twice the
+resident waves (4096 without a context) packs, and then every item is a
+segment pack: 1..64 queries of one kind with identical constants, step counts
+within 1/16 octave and one cells-per-lane E in {2, 4, 8}, each on
+ceil(n / E) lanes in the balanced layout (n >= (E - 1) ceil(n / E)), at most
+64 lanes.  A smaller batch runs every query alone (E = 0).  Items come longest
+first; the plan is deterministic.  Results of packed queries are compared with single runs bit
+for bit in the GPU batch tests."""
 import math
 
 import numpy as np
@@ -14,6 +18,7 @@ import workloads
 R = pytest.importorskip("paper_2001_10635_amd")
 
 FAKE = 1 << 20     # device addresses are never dereferenced by the planner
+PACK_MIN = 2 * 8 * 256 + 1   # smallest batch that packs without a context
 
 
 def queries_of(stream):
@@ -36,22 +41,26 @@ def bucket(cost):
 
 
 def check_plan(qs, plan):
-    seen = sorted(i for item in plan for i in item)
+    """plan: (E, members) pairs."""
+    seen = sorted(i for _, item in plan for i in item)
     assert seen == list(range(len(qs))), "every query exactly once"
     costs = []
-    for item in plan:
-        if len(item) > 1:
-            assert 2 <= len(item) <= 16
-            assert sum(qs[i].sys.n for i in item) <= 64
+    for E, item in plan:
+        if E:
+            assert E in (2, 4, 8)
+            assert 1 <= len(item) <= 64
+            lanes = [math.ceil(qs[i].sys.n / E) for i in item]
+            assert sum(lanes) <= 64
             lead = qs[item[0]]
-            for i in item:
+            for i, L in zip(item, lanes):
                 q = qs[i]
-                assert q.sys.kind in (R.REACH_CTM, R.REACH_RD) and q.sys.n <= 32
+                assert q.sys.n >= (E - 1) * L, "balanced layout exists"
                 assert (q.sys.kind, q.dt, tuple(q.sys.prm)) == \
                     (lead.sys.kind, lead.dt, tuple(lead.sys.prm))
                 assert bucket(q.nsteps) == bucket(lead.nsteps), "step counts within 1/16 octave"
-            costs.append(bucket(max(qs[i].nsteps for i in item)))
+            costs.append(bucket(E * max(qs[i].nsteps for i in item)))
         else:
+            assert len(item) == 1
             q = qs[item[0]]
             costs.append(bucket(math.ceil(q.sys.n / 64) * q.nsteps))
     assert all(a >= b for a, b in zip(costs, costs[1:])), "longest item first"
@@ -60,50 +69,64 @@ def check_plan(qs, plan):
 @pytest.mark.parametrize("nq", [1, 7, 400, 20000])
 def test_plan_covers_every_query_once_and_packs_validly(nq):
     qs = queries_of(workloads.query_stream(nq, 5.0e4, seed=4242 + nq))
-    plan = R.reach_plan_batch(None, qs)
+    plan = R.reach_plan_batch(None, qs, with_E=True)
     check_plan(qs, plan)
-    assert plan == R.reach_plan_batch(None, qs), "deterministic"
+    assert plan == R.reach_plan_batch(None, qs, with_E=True), "deterministic"
+    if nq < PACK_MIN:
+        assert all(E == 0 for E, _ in plan), "small batches do not pack"
+    else:
+        assert all(E for E, _ in plan), "a packed batch runs packs only"
 
 
-def test_short_queries_are_packed():
-    qs = queries_of(workloads.query_stream(4000, 5.0e4, seed=99))
-    plan = R.reach_plan_batch(None, qs)
-    packs = [it for it in plan if len(it) > 1]
-    short = sum(1 for q in qs if q.sys.n <= 32)
-    in_packs = sum(len(it) for it in packs)
-    assert packs and in_packs > 0.5 * short
-    lanes = [sum(qs[i].sys.n for i in it) for it in packs]
-    assert np.mean(lanes) > 32
+def test_queries_are_packed_densely():
+    """In a large mix the packs fill most of their wave's lanes and cell
+    slots."""
+    qs = queries_of(workloads.query_stream(20000, 5.0e4, seed=99))
+    plan = R.reach_plan_batch(None, qs, with_E=True)
+    packs = [(E, it) for E, it in plan if E]
+    assert len(packs) == len(plan)
+    lanes = [sum(math.ceil(qs[i].sys.n / E) for i in it) for E, it in packs]
+    assert np.mean(lanes) > 56
+    cells = sum(qs[i].sys.n for _, it in packs for i in it)
+    slots = sum(64 * E for E, _ in packs)
+    assert cells > 0.8 * slots
 
 
 def test_only_identical_constants_share_a_wave():
     p = workloads.small_problem(workloads.KIND_CTM, 10, 3, 50)
     qs = []
-    for k in range(12):
+    for k in range(PACK_MIN):
         dt = 0.01 if k % 3 else 0.02          # two step sizes
         steps = 50 if k % 4 else 49           # two step counts, same 1/16 octave
         qs.append(R.make_query(p.kind, 10, p.prm, R.REACH_F64, FAKE, FAKE, FAKE, FAKE, dt, steps))
     lin = R.make_query(R.REACH_LIN3, 8, (0.1, -0.5, 0.2, 1.0), R.REACH_F64, FAKE, FAKE, FAKE,
                        FAKE, 0.01, 50)
     qs.append(lin)
-    plan = R.reach_plan_batch(None, qs)
+    plan = R.reach_plan_batch(None, qs, with_E=True)
     check_plan(qs, plan)
-    assert [len(it) for it in plan if 12 in it] == [1], "LIN3 runs alone"
-    for it in plan:
+    assert [len(it) for _, it in plan if len(qs) - 1 in it] == [1], "one LIN3 query runs alone"
+    for _, it in plan:
         assert len({qs[i].dt for i in it}) == 1
-    assert any(len({qs[i].nsteps for i in it}) == 2 for it in plan), "49 and 50 steps share packs"
+    assert any(len({qs[i].nsteps for i in it}) == 2 for _, it in plan), \
+        "49 and 50 steps share packs"
 
 
-def test_long_and_wide_queries_run_alone():
-    qs = []
-    for n in (33, 64, 65, 512):
+def test_cells_per_lane_follow_the_cost_rule():
+    """n = 10 packs at E = 4 (3 lanes), n = 5 at E = 2 (no balanced 4-cell
+    layout), n = 100 at E = 8 (13 lanes), n = 512 at E = 8 (the whole wave),
+    n = 320 at E = 8 (40 lanes)."""
+    qs, want = [], {}
+    for n, E in ((10, 4), (5, 2), (100, 8), (512, 8), (320, 8)):
         p = workloads.small_problem(workloads.KIND_RD, n, 5, 20)
-        for _ in range(3):
+        for _ in range(1000):
+            want[len(qs)] = E
             qs.append(R.make_query(p.kind, n, p.prm, R.REACH_F64, FAKE, FAKE, FAKE, FAKE, p.dt,
                                    20, FAKE, FAKE, n_in=1))
-    plan = R.reach_plan_batch(None, qs)
+    plan = R.reach_plan_batch(None, qs, with_E=True)
     check_plan(qs, plan)
-    assert all(len(it) == 1 for it in plan)
+    for E, it in plan:
+        for i in it:
+            assert want[i] == E
 
 
 def test_plan_rejects_what_the_batch_rejects():

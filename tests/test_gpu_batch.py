@@ -66,19 +66,46 @@ def mix():
     return Batch(workloads.query_stream(400, 5.0e4, seed=4242))
 
 
-@pytest.mark.parametrize("split", [0, 1])
-def test_batch_equals_alone_and_oracle(rc, mix, split):
+# batch modes: every query alone over a wave, segment packs (capped at E cells
+# per lane), one side per wave
+MODES = {"alone": {"batch.pack": 2}, "packed": {"batch.pack": 1},
+         "packed_E4": {"batch.pack": 1, "batch.E": 4}, "packed_E2": {"batch.pack": 1, "batch.E": 2},
+         "split": {"batch.split": 1}}
+
+
+class options:
+    """Context options set for a block and reset to their defaults after it."""
+
+    def __init__(self, rc, opts):
+        self.rc, self.opts = rc, opts
+
+    def __enter__(self):
+        for k, v in self.opts.items():
+            self.rc.set_option(k, v)
+
+    def __exit__(self, *exc):
+        for k in self.opts:
+            self.rc.set_option(k, 0)
+
+
+@pytest.mark.parametrize("mode", list(MODES))
+def test_batch_equals_alone_and_oracle(rc, mix, mode):
     qs = mix.queries()
     nb = R.reach_batch_workspace_bytes(len(qs))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     mix.clear()
-    say(f"batch 400 queries split={split}")
-    rc.set_option("batch.split", split)
-    try:
+    say(f"batch 400 queries {mode}")
+    with options(rc, MODES[mode]):
+        plan = R.reach_plan_batch(rc.ctx, qs, with_E=True)
         R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
         assert rc.sync() == R.REACH_OK
-    finally:
-        rc.set_option("batch.split", 0)
+    cap = MODES[mode].get("batch.E", 8)
+    if mode.startswith("packed"):
+        assert any(E == cap for E, _ in plan), "packs at the cap"
+        # wider than the cap only for queries too long for 64 lanes at it
+        assert all(E <= cap or all(qs[i].sys.n > 64 * cap for i in it) for E, it in plan)
+    else:
+        assert all(E == 0 for E, _ in plan)
     got = mix.results()
     for k, d in enumerate(mix.items):
         a = alone(rc, d)
@@ -92,7 +119,8 @@ def test_batch_equals_alone_and_oracle(rc, mix, split):
         assert_rel(got[k][1], o_hi, 1e-12, f"query {k} upper")
 
 
-def test_batch_graph_replays_match_eager(rc, mix):
+@pytest.mark.parametrize("mode", ["alone", "packed"])
+def test_batch_graph_replays_match_eager(rc, mix, mode):
     """The captured graph (counter reset kernel, descriptor upload, worker) is
     replayed with eager work and synchronisation in between; every replay
     equals the eager result."""
@@ -100,17 +128,19 @@ def test_batch_graph_replays_match_eager(rc, mix):
     nb = R.reach_batch_workspace_bytes(len(qs))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     mix.clear()
-    R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)        # eager (default stream, no graph)
-    assert rc.sync() == R.REACH_OK
+    with options(rc, MODES[mode]):
+        R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)    # eager (default stream, no graph)
+        assert rc.sync() == R.REACH_OK
     ref = mix.results()
     s = torch.cuda.Stream()
     for rep in range(4):
         mix.clear()
         torch.cuda.synchronize()
-        say(f"graph replay {rep}")
-        with torch.cuda.stream(s):
-            R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, s)
-        assert rc.sync(s) == R.REACH_OK
+        say(f"graph replay {rep} {mode}")
+        with options(rc, MODES[mode]):
+            with torch.cuda.stream(s):
+                R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, s)
+            assert rc.sync(s) == R.REACH_OK
         x = torch.randn(1000, device="cuda").sum()      # eager work between replays
         torch.cuda.synchronize()
         got = mix.results()
@@ -135,21 +165,17 @@ def test_each_equals_batch(rc, mix):
         assert np.array_equal(got[k][0], ref[k][0]) and np.array_equal(got[k][1], ref[k][1])
 
 
-@pytest.mark.parametrize("split", [0, 1])
+@pytest.mark.parametrize("mode", ["alone", "packed", "split"])
 @pytest.mark.parametrize("waves", [1, 3, 64])
-def test_batch_wave_count_invariance(rc, mix, waves, split):
+def test_batch_wave_count_invariance(rc, mix, waves, mode):
     qs = mix.queries()[:60]
     nb = R.reach_batch_workspace_bytes(len(qs))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     mix.clear()
-    rc.set_option("batch.waves", waves)
-    rc.set_option("batch.split", split)
-    try:
+    say(f"batch 60 queries waves={waves} {mode}")
+    with options(rc, {"batch.waves": waves, **MODES[mode]}):
         R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
         assert rc.sync() == R.REACH_OK
-    finally:
-        rc.set_option("batch.waves", 0)
-        rc.set_option("batch.split", 0)
     got = mix.results()[:60]
     for k in range(60):
         a = alone(rc, mix.items[k])
@@ -272,8 +298,10 @@ def test_packed_queries_report_nonfinite_and_order_and_match_alone(rc):
     qs = [R.make_query(R.REACH_CTM, n, workloads.CTM_PRM, R.REACH_F64, x_lo.data_ptr() + 8 * n * k,
                        x_hi.data_ptr() + 8 * n * k, r_lo.data_ptr() + 8 * n * k,
                        r_hi.data_ptr() + 8 * n * k, 0.01, steps) for k in range(nqs)]
+    rc.set_option("batch.pack", 1)
     plan = R.reach_plan_batch(rc.ctx, qs)
     assert any(len(it) > 1 for it in plan) and any(3 in it and len(it) > 1 for it in plan)
+    assert any(7 in it and len(it) > 1 for it in plan)
     nb = R.reach_batch_workspace_bytes(nqs)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     say("packed batch with a non-finite and a crossed query")
@@ -291,19 +319,87 @@ def test_packed_queries_report_nonfinite_and_order_and_match_alone(rc):
     # the crossed query alone in a batch of packs raises the order flag
     qs2 = [q for k, q in enumerate(qs) if k != 3]
     R.reach_embed_rk4_batch(rc.ctx, qs2, ws, nb, 0)
+    rc.set_option("batch.pack", 0)
     assert rc.sync() == R.REACH_E_ORDER
     assert rc.sync() == R.REACH_OK
+
+
+def test_packs_with_unequal_steps_and_sizes_equal_alone(rc):
+    """Packs whose members have different step counts (49 and 50: one 1/16
+    octave) and sizes (every cells-per-lane layout: n = 2..64 at E = 2, 4, 8,
+    short lanes included): finished members' lanes stay masked while the
+    others step, and every box equals its single run bit for bit."""
+    rng = np.random.default_rng(11)
+    ns = [int(v) for v in rng.integers(2, 65, 90)]
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    lo = rng.uniform(-0.5, 0.5, offs[-1])
+    hi = lo + rng.uniform(0.0, 0.05, offs[-1])
+    x_lo, x_hi = to_dev(lo), to_dev(hi)
+    p_lo, p_hi = to_dev(np.array([-0.1])), to_dev(np.array([0.1]))
+    r_lo = torch.full((int(offs[-1]),), np.nan, dtype=torch.float64, device="cuda")
+    r_hi = torch.full_like(r_lo, np.nan)
+    steps = [49 if k % 3 else 50 for k in range(len(ns))]
+    qs = [R.make_query(R.REACH_RD, ns[k], (1.0,), R.REACH_F64, x_lo.data_ptr() + 8 * int(offs[k]),
+                       x_hi.data_ptr() + 8 * int(offs[k]), r_lo.data_ptr() + 8 * int(offs[k]),
+                       r_hi.data_ptr() + 8 * int(offs[k]), 0.1, steps[k], p_lo, p_hi, n_in=1)
+          for k in range(len(ns))]
+    nb = R.reach_batch_workspace_bytes(len(qs))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    for cap in (2, 4, 8):
+        r_lo.fill_(np.nan)
+        r_hi.fill_(np.nan)
+        with options(rc, {"batch.pack": 1, "batch.E": cap}):
+            plan = R.reach_plan_batch(rc.ctx, qs, with_E=True)
+            assert any(E == cap and len({steps[i] for i in it}) == 2 for E, it in plan)
+            say(f"packs with unequal steps, E cap {cap}")
+            R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
+            assert rc.sync() == R.REACH_OK
+        got_lo, got_hi = to_host(r_lo), to_host(r_hi)
+        for k in range(len(ns)):
+            a, e = int(offs[k]), int(offs[k + 1])
+            a_lo, a_hi = rc.embed(R.REACH_RD, (1.0,), x_lo[a:e].contiguous(),
+                                  x_hi[a:e].contiguous(), 0.1, steps[k], p_lo=p_lo, p_hi=p_hi)
+            assert rc.sync() == R.REACH_OK
+            assert np.array_equal(got_lo[a:e], to_host(a_lo)), f"query {k} n={ns[k]} cap {cap}"
+            assert np.array_equal(got_hi[a:e], to_host(a_hi)), f"query {k} n={ns[k]} cap {cap}"
 
 
 def test_plan_follows_the_split_option(rc, mix):
     """With batch.split = 1 the batch runs one side per wave: no packs."""
     qs = mix.queries()
-    packed = R.reach_plan_batch(rc.ctx, qs)
-    assert any(len(it) > 1 for it in packed)
-    rc.set_option("batch.split", 1)
-    try:
+    with options(rc, {"batch.pack": 1}):
+        packed = R.reach_plan_batch(rc.ctx, qs)
+        assert any(len(it) > 1 for it in packed)
+    with options(rc, {"batch.pack": 1, "batch.split": 1}):
         plan = R.reach_plan_batch(rc.ctx, qs)
-    finally:
-        rc.set_option("batch.split", 0)
     assert all(len(it) == 1 for it in plan)
     assert sorted(it[0] for it in plan) == list(range(len(qs)))
+
+
+def test_batch_autotune_keeps_results_bitwise(rc):
+    """reach_autotune_batch times every (kind, size) bucket of a 6000-query mix
+    at each pack width and the whole batch at two wave counts; the batch after
+    tuning gives the same boxes bit for bit, and its plan keeps to the tuned
+    widths."""
+    b = Batch(workloads.query_stream(6000, 5.0e4, seed=31))
+    qs = b.queries()
+    nb = R.reach_batch_workspace_bytes(len(qs))
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    say("batch 6000 before tuning")
+    R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
+    assert rc.sync() == R.REACH_OK
+    ref = b.results()
+    say("batch autotune")
+    best = R.reach_autotune_batch(rc.ctx, qs, ws, nb, 0)
+    assert rc.sync() == R.REACH_OK
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    assert best["waves"] in (12 * cus, 8 * cus) and best["batch_ns"] > 0
+    plan = R.reach_plan_batch(rc.ctx, qs, with_E=True)
+    assert any(E for E, _ in plan), "a 6000-query batch packs"
+    b.clear()
+    say("batch 6000 after tuning")
+    R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
+    assert rc.sync() == R.REACH_OK
+    got = b.results()
+    for k in range(len(ref)):
+        assert np.array_equal(got[k][0], ref[k][0]) and np.array_equal(got[k][1], ref[k][1]), k

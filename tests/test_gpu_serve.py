@@ -149,6 +149,38 @@ def test_cancel_pending_queries(rc):
             assert np.array_equal(items[k]["r_lo"], a[0])
 
 
+@pytest.mark.parametrize("mode", [0, 1], ids=["persistent", "launch_per_query"])
+def test_cancel_at_submission_does_not_hold_up_later_queries(rc, mode):
+    """Every other query is cancelled the moment it is submitted, while all of
+    them have slots (each is admitted at once and so already owns a ring
+    sequence): the cancelled ones report REACH_E_CANCELLED (or REACH_OK when
+    they finished first) and every other query completes and equals its alone
+    run, so no cancelled sequence holds up those after it."""
+    rc.set_option("serve.mode", mode)
+    items = host_queries(workloads.query_stream(200, 5.0e4, seed=77))
+    pool = torch.empty(64 << 20, dtype=torch.uint8, device="cuda")
+    say(f"serve cancel at submission, mode {mode}")
+    R.reach_server_start(rc.ctx, pool, pool.numel(), 256)
+    try:
+        tickets = []
+        for k, d in enumerate(items):
+            t = R.reach_submit(rc.ctx, d["q"])
+            tickets.append(t)
+            if k % 2:
+                assert R.reach_cancel(rc.ctx, t) in (R.REACH_OK, R.REACH_E_BUSY)
+        status = drain(rc, tickets, timeout_s=60.0)
+    finally:
+        R.reach_server_stop(rc.ctx)
+    for k, t in enumerate(tickets):
+        if k % 2:
+            assert status[t] in (R.REACH_E_CANCELLED, R.REACH_OK)
+        else:
+            assert status[t] == R.REACH_OK
+            a = alone(rc, items[k])
+            assert np.array_equal(items[k]["r_lo"], a[0])
+            assert np.array_equal(items[k]["r_hi"], a[1])
+
+
 def long_query(kind, n, nsteps, seed):
     p = workloads.small_problem(kind, n, seed, nsteps)
     return host_queries([workloads.Query(0, 0.0, p)])[0]

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2001_10635_amd", "csrc")
 BUILD = os.path.join(ROOT, "paper_2001_10635_amd", "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-KERNEL_OBJS = ["embed.o", "gb.o", "heat3d.o", "mc.o", "batch.o"]
+KERNEL_OBJS = ["embed.o", "gb.o", "heat3d.o", "mc.o", "mc_noalloc.o", "batch.o"]
 FLAGS = ["-O1", "-g", "-std=c++17", "-fPIC", "-ffp-contract=off", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument", "-Wno-unused-value", "-Wno-unused-result"]
