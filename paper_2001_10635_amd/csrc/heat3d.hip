@@ -200,7 +200,8 @@ __device__ __forceinline__ void heat_level(HeatRegs<T, P>& R, HeatLds<T, WV>& L,
         for (int p = 0; p < P; ++p) {
             const T v = nv[p];
             if (live && rows.out[p] && c.xout) {
-                out[rows.off[p] + c.xl] = v;
+                // the new state is not read again in this pass: non-temporal
+                __builtin_nontemporal_store(v, &out[rows.off[p] + c.xl]);
                 if (!finiteT(v)) c.bits |= ST_NONFINITE;
             }
         }

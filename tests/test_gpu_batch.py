@@ -376,11 +376,12 @@ def test_plan_follows_the_split_option(rc, mix):
     assert sorted(it[0] for it in plan) == list(range(len(qs)))
 
 
-def test_batch_autotune_keeps_results_bitwise(rc):
+def test_batch_autotune_keeps_results_bitwise(rc, tmp_path, monkeypatch):
     """reach_autotune_batch times every (kind, size) bucket of a 6000-query mix
     at each pack width and the whole batch at two wave counts; the batch after
-    tuning gives the same boxes bit for bit, and its plan keeps to the tuned
-    widths."""
+    tuning gives the same boxes bit for bit, its plan keeps to the tuned
+    widths, and a context created later reads the widths back from
+    REACH_AUTOTUNE_CACHE and plans the same packs."""
     b = Batch(workloads.query_stream(6000, 5.0e4, seed=31))
     qs = b.queries()
     nb = R.reach_batch_workspace_bytes(len(qs))
@@ -390,6 +391,22 @@ def test_batch_autotune_keeps_results_bitwise(rc):
     assert rc.sync() == R.REACH_OK
     ref = b.results()
     say("batch autotune")
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("REACH_AUTOTUNE_CACHE", str(cache))
+    tuner = R.Reach(0)
+    try:
+        best = R.reach_autotune_batch(tuner.ctx, qs, ws, nb, 0)
+        assert tuner.sync() == R.REACH_OK
+        tuned_plan = R.reach_plan_batch(tuner.ctx, qs, with_E=True)
+    finally:
+        tuner.close()
+    assert any(l.startswith("reach2 batch ") for l in cache.read_text().splitlines())
+    later = R.Reach(0)
+    try:
+        assert R.reach_plan_batch(later.ctx, qs, with_E=True) == tuned_plan
+    finally:
+        later.close()
+    monkeypatch.delenv("REACH_AUTOTUNE_CACHE")
     best = R.reach_autotune_batch(rc.ctx, qs, ws, nb, 0)
     assert rc.sync() == R.REACH_OK
     cus = torch.cuda.get_device_properties(0).multi_processor_count

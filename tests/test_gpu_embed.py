@@ -426,3 +426,36 @@ def test_default_plan_spreads_steps_evenly_over_its_passes(rc):
     b = run_gpu(rc, kind, prm, lo, hi, pl, ph, dt, k_default + 1)
     rc.set_option("embed.K", 0)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_autotune_cache_keys_the_input_mode_and_ignores_old_lines(tmp_path, monkeypatch):
+    """REACH_AUTOTUNE_CACHE: entries carry the input mode (shared or per-cell
+    inputs), so a shape tuned for one never reaches the other; lines of the
+    older format without it are ignored; batch pack-width lines apply to
+    their (kind, size) bucket."""
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    n = 300000
+    b = n.bit_length() - 1
+    cache = tmp_path / "tune.txt"
+    cache.write_text(
+        f"{arch} 2 0 {b} 4 3 2 1.0\n"                       # old format: ignored
+        f"reach2 embed {arch} 2 0 {b} 0 16 6 1 1.0\n"       # RD FP64, shared input
+        f"reach2 embed {arch} 2 0 {b} 1 8 5 1 1.0\n"        # RD FP64, per-cell inputs
+        f"reach2 batch {arch} 1 4 2 1000\n")                # CTM, n in [16, 32): width 2
+    monkeypatch.setenv("REACH_AUTOTUNE_CACHE", str(cache))
+    r = R.Reach(0)
+    try:
+        shared = R.reach_plan_embed(r.ctx, R.make_system(R.REACH_RD, n, (1.0,), 1),
+                                    R.REACH_F64, 60)
+        cell = R.reach_plan_embed(r.ctx, R.make_system(R.REACH_RD, n, (1.0,), n),
+                                  R.REACH_F64, 60)
+        assert (shared["E"], shared["S"]) == (16, 1) and shared["passes"] == 10
+        assert (cell["E"], cell["S"]) == (8, 1) and cell["passes"] == 12
+        r.set_option("batch.pack", 1)
+        p = workloads.small_problem(workloads.KIND_CTM, 20, 3, 30)
+        qs = [R.make_query(p.kind, 20, p.prm, R.REACH_F64, 1 << 20, 1 << 20, 1 << 20, 1 << 20,
+                           p.dt, 30) for _ in range(40)]
+        plan = R.reach_plan_batch(r.ctx, qs, with_E=True)
+        assert plan and all(E == 2 for E, _ in plan)
+    finally:
+        r.close()
