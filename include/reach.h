@@ -169,10 +169,12 @@ const char* reach_last_error(const reach_ctx* ctx);
                   latency per query); 0 (default): one wave per query or pack
      "batch.pack" 0 (default): segment packs when the batch has more queries
                   than twice the resident waves; 1: always; 2: never
-     "batch.E"    largest cells per lane of a segment pack: 2, 4 or 8 (0 =
-                  the autotuned cap of the query's bucket, else 8)
-     "batch.waves" resident waves of the batch kernels (0 = default: 8 per
-                  compute unit unpacked, 12 packed or the autotuned count)
+     "batch.E"    largest cells per lane of a segment pack: 2, 4, 8 or 16 (0 =
+                  the autotuned cap of the query's bucket, else that of the
+                  whole batch, else 16)
+     "batch.waves" resident waves of the batch kernels (0 = default: the
+                  autotuned count for a packed batch, else 8 per compute unit,
+                  4 when a pack has 16 cells per lane)
      "serve.mode" 0 (default): persistent serving kernel; 1: one launch per
                   served query (read by reach_server_start)
      "serve.waves" resident waves of the serving kernel (0 = default)
@@ -359,7 +361,7 @@ size_t reach_batch_workspace_bytes(int64_t nq);
  * kernel (option "batch.pack": 0 = that rule, 1 = always, 2 = never) is
  * packed: every work item is then a segment pack, queries of one kind with
  * bitwise equal parameters and dt, step counts in the same 1/16 octave and
- * the same cells per lane E (2, 4 or 8, chosen per query by the least
+ * the same cells per lane E (2, 4, 8 or 16, chosen per query by the least
  * estimated issue cost, at most option "batch.E" or else the (kind, size)
  * bucket's autotuned cap) sharing a wavefront, query m on ceil(n_m / E)
  * lanes, at most 64 lanes and 64 queries.  An unpacked batch runs every
@@ -380,22 +382,24 @@ reach_status reach_plan_batch(reach_ctx* ctx, const reach_query* q, int64_t nq,
 reach_status reach_embed_rk4_batch(reach_ctx* ctx, const reach_query* q, int64_t nq,
                                    void* workspace, size_t workspace_bytes, void* stream);
 
-/* Autotuner of the batch (its tile shapes per size bucket), on the caller's
-   whole batch: times it (one warm-up and four timed calls, HIP events on
-   `stream`, fastest kept, host planning included) at the current settings,
-   then, for every (kind, log2 n bucket) with at least 256 queries, most
-   queries first, tries the narrower largest pack widths 4 and 2 cells per
-   lane for that bucket and keeps one only if the whole batch gets more than
-   1% faster; then, unless option "batch.waves" is set, times 12 and 8
-   resident waves per compute unit and keeps the faster for packed batches.
-   A batch that does not pack is only timed.  The widths are recorded in the
-   context (used while option "batch.E" is 0).  Arguments as
-   reach_embed_rk4_batch, whose results the queries' r_lo / r_hi hold
-   afterwards; every setting gives the same boxes bit for bit.  best[0] =
-   resident waves (0: the default), best[1] = nanoseconds of the whole batch at
-   the chosen settings.  `best` is a host array of 2.  With
-   REACH_AUTOTUNE_CACHE set, the bucket widths are appended there and read
-   back by reach_ctx_create on the same device architecture. */
+/* Autotuner of the batch (its pack widths and resident waves), on the
+   caller's whole batch.  After a few untimed calls, every comparison times
+   the batch (one warm-up and four timed calls, HIP events on `stream`,
+   fastest kept, host planning included) with the candidate setting and again
+   with the current one, and keeps the candidate only if it is more than 1%
+   faster.  In order: the width of the whole batch (largest pack width 16,
+   the wide kernel at one wavefront per SIMD, against 8, the narrow kernel at
+   two); then, for every (kind, log2 n bucket) with at least 256 queries, most
+   queries first, the narrower widths 8, 4 and 2 for that bucket; then,
+   unless option "batch.waves" is set, 4, 8 and (without 16-cell packs) 12
+   resident waves per compute unit.  A batch that does not pack is only
+   timed.  The widths are recorded in the context (used while option
+   "batch.E" is 0).  Arguments as reach_embed_rk4_batch, whose results the
+   queries' r_lo / r_hi hold afterwards; every setting gives the same boxes
+   bit for bit.  best[0] = resident waves (0: the default), best[1] =
+   nanoseconds of the whole batch at the chosen settings.  `best` is a host
+   array of 2.  With REACH_AUTOTUNE_CACHE set, the widths are appended there
+   and read back by reach_ctx_create on the same device architecture. */
 reach_status reach_autotune_batch(reach_ctx* ctx, const reach_query* q, int64_t nq,
                                   void* workspace, size_t workspace_bytes, void* stream,
                                   int64_t* best);

@@ -259,7 +259,7 @@ __device__ __forceinline__ unsigned run_query_kind(const QDesc& d, int side) {
 }
 
 // Segment packs: several queries of one kind with bitwise equal constants and
-// dt share a wave, E cells per lane (E = 2, 4 or 8, one E per pack).  Member m
+// dt share a wave, E cells per lane (E = 2, 4, 8 or 16, one E per pack).  Member m
 // runs on the L_m = ceil(n_m / E) lanes after the previous members', in the
 // balanced layout of those lanes: the first F_m = n_m - L_m (E - 1) lanes hold
 // E cells and the others E - 1 (the planner packs a query at this E only when
@@ -425,16 +425,16 @@ __global__ __launch_bounds__(64) void batch_kernel(const QDesc* __restrict__ des
 }
 
 // Persistent worker of a packed batch: every item is a segment pack.  The
-// packs' bodies are inlined into this one kernel (no calls), whose registers
-// are capped for three waves per SIMD: packs carry at most 8 cells per lane,
-// and the extra resident wave hides the FP64 dependency latency of the stage
-// chains.
-__global__ __launch_bounds__(64, 3) void pack_kernel(const QDesc* __restrict__ desc,
-                                                      const BatchItem* __restrict__ items,
-                                                      const uint32_t* __restrict__ members,
-                                                      const uint64_t* n_items,
-                                                      unsigned long long* counter,
-                                                      unsigned int* qflags, unsigned int* status) {
+// packs' bodies are inlined into this one kernel (no calls).  EMAX is the
+// widest pack it runs: with EMAX = 8 its registers are capped for three waves
+// per SIMD (the extra resident wave hides the FP64 dependency latency of the
+// stage chains); the 16-cell bodies need ~240 registers, so EMAX = 16 runs
+// two waves per SIMD.
+template <int EMAX>
+__global__ __launch_bounds__(64, EMAX > 8 ? 2 : 3) void pack_kernel(
+        const QDesc* __restrict__ desc, const BatchItem* __restrict__ items,
+        const uint32_t* __restrict__ members, const uint64_t* n_items,
+        unsigned long long* counter, unsigned int* qflags, unsigned int* status) {
     const int lane = threadIdx.x;
     const uint64_t ni = wave_bcast(*n_items);
     for (;;) {
@@ -446,17 +446,25 @@ __global__ __launch_bounds__(64, 3) void pack_kernel(const QDesc* __restrict__ d
         const int kind = desc[members[it.start]].kind;
         const uint32_t* mi = members + it.start;
         const int cnt = it.count;
-        const int sel = (kind == K_CTM ? 0 : kind == K_RD ? 3 : 6) + (it.E == 2 ? 0 : it.E == 4 ? 1 : 2);
-        switch (sel) {
+        const int ki = kind == K_CTM ? 0 : kind == K_RD ? 1 : 2;
+        const int ei = it.E == 2 ? 0 : it.E == 4 ? 1 : it.E == 8 ? 2 : 3;
+        switch (4 * ki + ei) {
             case 0: run_seg<K_CTM, 2>(desc, mi, cnt, qflags, status); break;
             case 1: run_seg<K_CTM, 4>(desc, mi, cnt, qflags, status); break;
             case 2: run_seg<K_CTM, 8>(desc, mi, cnt, qflags, status); break;
-            case 3: run_seg<K_RD, 2>(desc, mi, cnt, qflags, status); break;
-            case 4: run_seg<K_RD, 4>(desc, mi, cnt, qflags, status); break;
-            case 5: run_seg<K_RD, 8>(desc, mi, cnt, qflags, status); break;
-            case 6: run_seg<K_LIN3, 2>(desc, mi, cnt, qflags, status); break;
-            case 7: run_seg<K_LIN3, 4>(desc, mi, cnt, qflags, status); break;
-            default: run_seg<K_LIN3, 8>(desc, mi, cnt, qflags, status); break;
+            case 4: run_seg<K_RD, 2>(desc, mi, cnt, qflags, status); break;
+            case 5: run_seg<K_RD, 4>(desc, mi, cnt, qflags, status); break;
+            case 6: run_seg<K_RD, 8>(desc, mi, cnt, qflags, status); break;
+            case 8: run_seg<K_LIN3, 2>(desc, mi, cnt, qflags, status); break;
+            case 9: run_seg<K_LIN3, 4>(desc, mi, cnt, qflags, status); break;
+            case 10: run_seg<K_LIN3, 8>(desc, mi, cnt, qflags, status); break;
+            default:   // E = 16 (the host gives such packs to EMAX = 16 only)
+                if constexpr (EMAX > 8) {
+                    if (ki == 0) run_seg<K_CTM, 16>(desc, mi, cnt, qflags, status);
+                    else if (ki == 1) run_seg<K_RD, 16>(desc, mi, cnt, qflags, status);
+                    else run_seg<K_LIN3, 16>(desc, mi, cnt, qflags, status);
+                }
+                break;
         }
     }
 }
@@ -580,10 +588,13 @@ __global__ __launch_bounds__(64) void serve_kernel(ServeSlot* ring, int32_t slot
 hipError_t launch_batch(const QDesc* d, const BatchItem* items, const uint32_t* members,
                         const uint64_t* n_items, unsigned long long* counter,
                         unsigned int* qflags, unsigned int* pair, unsigned int* status,
-                        int split, bool packed, int64_t grid, hipStream_t s) {
-    if (packed)
-        hipLaunchKernelGGL(pack_kernel, dim3((unsigned)grid), dim3(WAVE), 0, s, d, items, members,
-                           n_items, counter, qflags, status);
+                        int split, int packed, int64_t grid, hipStream_t s) {
+    if (packed == 2)
+        hipLaunchKernelGGL(pack_kernel<16>, dim3((unsigned)grid), dim3(WAVE), 0, s, d, items,
+                           members, n_items, counter, qflags, status);
+    else if (packed)
+        hipLaunchKernelGGL(pack_kernel<8>, dim3((unsigned)grid), dim3(WAVE), 0, s, d, items,
+                           members, n_items, counter, qflags, status);
     else
         hipLaunchKernelGGL(batch_kernel, dim3((unsigned)grid), dim3(WAVE), 0, s, d, items,
                            members, n_items, counter, qflags, pair, status, split);

@@ -169,7 +169,7 @@ inline int batch_cells_per_lane(int64_t n) { return (int)((n + 63) / 64); }
 // Segment packs: queries of one kind, constants and dt sharing a wave at
 // E cells per lane (kSegE), member m on ceil(n_m / E) lanes, at most 64 lanes
 // and so at most 64 members.
-constexpr int kSegE[] = {2, 4, 8};
+constexpr int kSegE[] = {2, 4, 8, 16};
 constexpr int kPackMax = 64;
 
 // One work item of a batch: the queries members[start .. start + count) --
@@ -183,17 +183,23 @@ struct BatchItem {
 
 // Persistent batch worker: `grid` waves pull work items through *counter:
 // items[0 .. *n_items) (d[] in the caller's order, members[] the query
-// indices of the items in launch order).  packed: every item is a segment
-// pack (E > 0), run by the packing kernel (three waves per SIMD); otherwise
+// indices of the items in launch order).  packed 1: every item is a segment
+// pack of at most 8 cells per lane (E > 0), run by the packing kernel at
+// three waves per SIMD; packed 2: some pack has 16 cells per lane, all run by
+// the wide packing kernel at two waves per SIMD; packed 0:
 // every item is one query (E = 0), or with `split` two per item (one per side
 // of a cooperative chain), pair[i] counting the finished sides of item i.
 hipError_t launch_batch(const QDesc* d, const BatchItem* items, const uint32_t* members,
                         const uint64_t* n_items, unsigned long long* counter,
                         unsigned int* qflags, unsigned int* pair, unsigned int* status,
-                        int split, bool packed, int64_t grid, hipStream_t stream);
-// Resident waves per compute unit of the batch kernels at full occupancy.
+                        int split, int packed, int64_t grid, hipStream_t stream);
+// Default waves per compute unit of the batch kernels: the one-query kernel
+// and the narrow packing kernel two per SIMD (the narrow one fits three, which
+// measures slower), the wide packing kernel one per SIMD (16 cells give one
+// wave enough independent work to keep its SIMD issuing; two measure slower).
 constexpr int kBatchWavesPerCU = 8;
-constexpr int kPackWavesPerCU = 12;
+constexpr int kPackWavesPerCU = 8;
+constexpr int kWideWavesPerCU = 4;
 // Zero `count` 32-bit words (a kernel, so it can sit in a captured graph).
 hipError_t launch_zero(void* p, int64_t count, hipStream_t stream);
 // One query with a plain launch (the one-launch-per-query baseline).  With

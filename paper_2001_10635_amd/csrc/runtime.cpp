@@ -140,6 +140,8 @@ struct reach_ctx {
     std::map<std::tuple<int, int, int, int>, TuneEntry> tune;
     std::map<std::pair<int, int>, int> batch_tune;        // (kind, log2 n bucket) -> pack E cap
     int64_t batch_waves = 0;                             // autotuned resident waves (0 = none)
+    int batch_cap = 0;                                   // autotuned pack E cap of all buckets (0 = none)
+    int last_packed = 0;                                 // kernel of the last batch (launch_batch)
     // batch staging (pinned host) and graph cache
     QDesc* staging = nullptr;            // [nq] descriptors, [nq] items, item count
     int64_t staging_cap = 0;
@@ -603,7 +605,10 @@ void load_tune_cache(reach_ctx* c) {
                 c->tune[{kind, dtype, bucket, cell}] = TuneEntry{E, K, S};
         } else if (std::sscanf(line, "reach2 batch %63s %d %d %d %lf", arch, &kind, &bucket, &cap,
                                &ps) == 5) {
-            if (c->arch == arch && (cap == 2 || cap == 4 || cap == 8))
+            const bool cap_ok = cap == 2 || cap == 4 || cap == 8 || cap == 16;
+            if (c->arch == arch && cap_ok && kind == -1 && bucket == -1)
+                c->batch_cap = cap;   // the whole batch's width
+            else if (c->arch == arch && cap_ok)
                 c->batch_tune[{kind, bucket}] = cap;
         }
     }
@@ -704,8 +709,9 @@ reach_status reach_set_option(reach_ctx* c, const char* key, int64_t value) {
         return fail(c, REACH_E_INVAL, "embed.S must be 0, 1 or 2");
     if (!std::strcmp(key, "batch.pack") && value > 2)
         return fail(c, REACH_E_INVAL, "batch.pack must be 0 (auto), 1 (always) or 2 (never)");
-    if (!std::strcmp(key, "batch.E") && value && value != 2 && value != 4 && value != 8)
-        return fail(c, REACH_E_INVAL, "batch.E must be 0, 2, 4 or 8");
+    if (!std::strcmp(key, "batch.E") && value && value != 2 && value != 4 && value != 8 &&
+        value != 16)
+        return fail(c, REACH_E_INVAL, "batch.E must be 0, 2, 4, 8 or 16");
     if (!std::strcmp(key, "heat.P") && value && !heat_waves((int)value))
         return fail(c, REACH_E_INVAL, "heat.P must be 0, 2, 3, 4, 5 or 8");
     c->opt[key] = value;
@@ -1263,6 +1269,8 @@ int wave_time_bucket(uint64_t cost) {
 // seg_E picks the cheapest E of kSegE up to cap (ties to the wider), or the
 // narrowest valid E above cap when none up to it is valid.
 constexpr double kCellOps = 6.0, kSegLaneOps = 12.0;
+// Default cap on E before the batch autotuner has run.
+constexpr int kSegECap = 16;
 
 int seg_E(int64_t n, int cap) {
     double best = 1e300;
@@ -1293,15 +1301,17 @@ bool batch_packs(const reach_ctx* c, int64_t nq) {
 }
 
 // Largest cells per lane of a pack for (kind, size bucket): option batch.E,
-// else the autotuned value (reach_autotune_batch), else 8.
+// else the bucket's autotuned cap, else the autotuned cap of the whole batch
+// (reach_autotune_batch), else kSegECap.
 int batch_ecap(const reach_ctx* c, int kind, int bucket) {
     if (c) {
         const int64_t e = opt_get(c, "batch.E");
         if (e > 0) return (int)e;
         auto it = c->batch_tune.find({kind, bucket});
         if (it != c->batch_tune.end()) return it->second;
+        if (c->batch_cap) return c->batch_cap;
     }
-    return 8;
+    return kSegECap;
 }
 
 // The schedule of a batch: the descriptors descs[nq] in the caller's order
@@ -1330,7 +1340,7 @@ struct PlanTimes {
 
 reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int64_t nq,
                         int split, int nth, QDesc* descs, std::vector<uint32_t>* members_out,
-                        std::vector<BatchItem>* items_out, bool* packed,
+                        std::vector<BatchItem>* items_out, int* packed,
                         PlanTimes* times = nullptr) {
     using clk = std::chrono::steady_clock;
     auto since = [](clk::time_point t0) {
@@ -1370,7 +1380,7 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
         uint32_t mem[kPackMax];
     };
     const bool packs = !split && batch_packs(c, nq);
-    *packed = packs;
+    *packed = packs ? 1 : 0;
     int ecap[4][kNB];
     for (int k = 0; k < 4; ++k)
         for (int b = 0; b < kNB; ++b) ecap[k][b] = batch_ecap(c, k, b);
@@ -1394,9 +1404,9 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
     std::vector<std::vector<Item>> titems((size_t)nth);
     std::vector<std::vector<uint32_t>> tmembers((size_t)nth);
     std::vector<int64_t> bad((size_t)nth, nq);
-    // cells per lane of a packed query by cap (2, 4, 8) and size
-    int8_t etab[3][513];
-    for (int ci = 0; ci < 3; ++ci)
+    // cells per lane of a packed query by cap (2, 4, 8, 16) and size
+    int8_t etab[4][513];
+    for (int ci = 0; ci < 4; ++ci)
         for (int64_t n = 1; n <= 512; ++n) etab[ci][n] = (int8_t)seg_E(n, 2 << ci);
     // pass 1: descriptors, validation, pack keys (class ids local to the
     // thread); each packed query goes to the list of the thread that owns its
@@ -1431,7 +1441,7 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
                 continue;
             }
             const int cap = ecap[d.kind & 3][std::min(n_bucket(d.n), kNB - 1)];
-            const int E = etab[cap >= 8 ? 2 : cap >= 4 ? 1 : 0][d.n];
+            const int E = etab[cap >= 16 ? 3 : cap >= 8 ? 2 : cap >= 4 ? 1 : 0][d.n];
             int cls = -1;
             Consts cs;
             std::memset(&cs, 0, sizeof cs);
@@ -1635,6 +1645,7 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
         const Item& it = titems[sorted[(size_t)k].t][sorted[(size_t)k].k];
         io[(size_t)k] = BatchItem{p, it.count, it.E};
         p += it.count;
+        if (it.E > 8) *packed = 2;
     }
     if (times) times->order_ms = since(t0);
     t0 = clk::now();
@@ -1685,7 +1696,7 @@ reach_status reach_plan_batch(reach_ctx* c, const reach_query* q, int64_t nq,
         pool = local.get();
     }
     const int nth = pool ? std::min(batch_host_threads(nq), pool->size()) : 1;
-    bool packed = false;
+    int packed = 0;
     const reach_status st = plan_batch(c, pool, q, nq, split, nth, descs.data(), &members, &items,
                                        &packed);
     if (st != REACH_OK) return st;
@@ -1731,7 +1742,7 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     std::vector<uint32_t> members;
     std::vector<BatchItem> items;
     PlanTimes pt;
-    bool packed = false;
+    int packed = 0;
     reach_status pst = plan_batch(c, pool, q, nq, split, nth, hb.desc, &members, &items, &packed,
                                   &pt);
     if (pst != REACH_OK) return pst;
@@ -1747,8 +1758,15 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     auto* pair = (unsigned int*)(base + align256(8) + align256(4 * (size_t)nq));
     const BatchBlock db = batch_block(base + align256(8) + 2 * align256(4 * (size_t)nq), nq);
     int64_t grid = opt_get(c, "batch.waves");
-    if (grid <= 0 && packed) grid = c->batch_waves;
-    if (grid <= 0) grid = (int64_t)c->cus * (packed ? kPackWavesPerCU : kBatchWavesPerCU);
+    if (grid <= 0) {
+        if (packed) grid = c->batch_waves;
+        if (grid <= 0)
+            grid = (int64_t)c->cus * (packed == 2 ? kWideWavesPerCU
+                                      : packed == 1 ? kPackWavesPerCU : kBatchWavesPerCU);
+        // the wide packing kernel holds at most two waves per SIMD
+        if (packed == 2) grid = std::min<int64_t>(grid, (int64_t)c->cus * 8);
+    }
+    c->last_packed = packed;
     grid = std::min<int64_t>(grid, split ? 2 * ni : ni);
 
     if (c->log) {
@@ -1774,7 +1792,7 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
         hipError_t e = enqueue(hs);
         if (e != hipSuccess) return hip_fail(c, e, "batch launch");
     } else {
-        GraphKey key{nq, ws, c->staging, (grid * 2 + split) * 2 + (packed ? 1 : 0), hs};
+        GraphKey key{nq, ws, c->staging, (grid * 2 + split) * 3 + packed, hs};
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             hipGraph_t g = nullptr;
@@ -1798,11 +1816,14 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
 
 // Batch autotuner, on the caller's whole batch (a bucket's queries alone
 // would be too few to fill the device, and their timing would favour short
-// items over dense ones).  The batch is timed (one warm-up and four timed
-// calls, fastest kept) at the current settings; then, bucket by bucket, most
-// queries first, for every (kind, size bucket) with at least kTuneMinQueries
-// queries each narrower pack cap (4, 2) is tried and kept only if the whole
-// batch gets faster by more than kTuneGain; then 12 and 8 resident waves per
+// items over dense ones).  After kTuneWarm untimed calls, every comparison
+// times the batch (one warm-up and four timed calls, fastest kept) with the
+// candidate setting and then again with the current one, and takes the
+// candidate only when it is faster by more than kTuneGain.  In order: the
+// width of the whole batch (every bucket's cap 16, the wide kernel, against
+// 8, the narrow one); then, bucket by bucket, most queries first, for every
+// (kind, size bucket) with at least kTuneMinQueries queries, the narrower
+// caps 8, 4 and 2; then 4, 8 and (narrow kernel only) 12 resident waves per
 // compute unit.  Results are those of the batch at any setting (bitwise).
 reach_status reach_autotune_batch(reach_ctx* c, const reach_query* q, int64_t nq, void* ws,
                                   size_t ws_bytes, void* stream, int64_t* best) {
@@ -1810,6 +1831,7 @@ reach_status reach_autotune_batch(reach_ctx* c, const reach_query* q, int64_t nq
     if (!best || nq < 1 || !q) return fail(c, REACH_E_INVAL, "bad arguments");
     constexpr int64_t kTuneMinQueries = 256;
     constexpr double kTuneGain = 0.01;
+    constexpr int kTuneWarm = 8;
     constexpr int kNB = 10;
     hipStream_t hs = (hipStream_t)stream;
     HIPCHK(c, hipSetDevice(c->device));
@@ -1838,8 +1860,37 @@ reach_status reach_autotune_batch(reach_ctx* c, const reach_query* q, int64_t nq
     };
     const int64_t save_E = opt_get(c, "batch.E"), save_waves = opt_get(c, "batch.waves");
     c->opt["batch.E"] = 0;
+    // widths are timed at each packing kernel's default wave count
+    c->batch_waves = 0;
+    // a few untimed calls first, so that the device clock has left its idle
+    // level before anything is compared
+    reach_status st = REACH_OK;
+    for (int w = 0; w < kTuneWarm && st == REACH_OK; ++w)
+        st = reach_embed_rk4_batch(c, q, nq, ws, ws_bytes, stream);
+    if (st == REACH_OK && hipStreamSynchronize(hs) != hipSuccess)
+        st = fail(c, REACH_E_DEVICE, "batch warm-up");
     double cur = 0;
-    reach_status st = time_batch(&cur);
+    if (st == REACH_OK) st = time_batch(&cur);
+    // a setting replaces the current one only when the batch timed with it is
+    // faster by kTuneGain than the batch timed again with the current one
+    // right after (drift of the device clock hits both alike)
+    auto trial = [&](const std::function<void()>& cand, const std::function<void()>& keep,
+                     bool* won) -> reach_status {
+        double tc = 0, tk = 0;
+        cand();
+        reach_status r = time_batch(&tc);
+        keep();
+        if (r == REACH_OK) r = time_batch(&tk);
+        if (r != REACH_OK) return r;
+        *won = tc < tk * (1.0 - kTuneGain);
+        if (*won) {
+            cand();
+            cur = tc;
+        } else {
+            cur = tk;
+        }
+        return REACH_OK;
+    };
     const bool packs = !opt_get(c, "batch.split") && batch_packs(c, nq);
     if (st == REACH_OK && packs) {
         // (kind, bucket) groups, most queries first
@@ -1852,38 +1903,47 @@ reach_status reach_autotune_batch(reach_ctx* c, const reach_query* q, int64_t nq
         for (const auto& kv : count)
             if (kv.second >= kTuneMinQueries) order.push_back({-kv.second, kv.first});
         std::sort(order.begin(), order.end());
-        for (const auto& o : order) {
-            const auto key = o.second;
+        // the whole batch's width first: every bucket at 8 cells per lane (the
+        // narrow kernel, two waves per SIMD) against 16 (the wide kernel, one)
+        for (const auto& kv : count) c->batch_tune.erase(kv.first);
+        const int first = c->batch_cap ? c->batch_cap : kSegECap;
+        const int other = first == 16 ? 8 : 16;
+        bool won = false;
+        st = trial([&] { c->batch_cap = other; }, [&] { c->batch_cap = first; }, &won);
+        if (st == REACH_OK) save_batch_tune_entry(c, -1, -1, c->batch_cap, cur);
+        // then narrower caps bucket by bucket
+        for (size_t k = 0; k < order.size() && st == REACH_OK; ++k) {
+            const auto key = order[k].second;
             const int keep = batch_ecap(c, key.first, key.second);
-            int best_cap = keep;
-            for (int cap : {4, 2}) {
-                if (cap >= keep) continue;
-                c->batch_tune[key] = cap;
-                double ns = 0;
-                st = time_batch(&ns);
+            for (int cap : {8, 4, 2}) {
+                if (cap >= batch_ecap(c, key.first, key.second)) continue;
+                const int now = batch_ecap(c, key.first, key.second);
+                st = trial([&] { c->batch_tune[key] = cap; }, [&] { c->batch_tune[key] = now; },
+                           &won);
                 if (st != REACH_OK) break;
-                if (ns < cur * (1.0 - kTuneGain)) { cur = ns; best_cap = cap; }
             }
-            c->batch_tune[key] = best_cap;
-            if (st != REACH_OK) break;
-            save_batch_tune_entry(c, key.first, key.second, best_cap, cur);
+            if (st == REACH_OK && batch_ecap(c, key.first, key.second) != keep)
+                save_batch_tune_entry(c, key.first, key.second,
+                                      batch_ecap(c, key.first, key.second), cur);
         }
     }
     int64_t best_waves = save_waves;
     if (st == REACH_OK && packs && save_waves == 0) {
-        double best_ns = 1e300;
-        for (int64_t per_cu : {(int64_t)kPackWavesPerCU, (int64_t)kBatchWavesPerCU}) {
-            c->opt["batch.waves"] = per_cu * c->cus;
-            double ns = 0;
-            st = time_batch(&ns);
+        // from the kernel's default (one wave per SIMD for the wide kernel,
+        // two for the narrow one), which the last timed call used
+        const bool wide = c->last_packed == 2;
+        int64_t now = (int64_t)c->cus * (wide ? kWideWavesPerCU : kPackWavesPerCU);
+        for (int64_t per_cu : {4, 8, 12}) {
+            const int64_t w = per_cu * c->cus;
+            // the wide packing kernel holds at most two waves per SIMD
+            if (w == now || (wide && per_cu > 8)) continue;
+            bool won = false;
+            const int64_t was = now;
+            st = trial([&] { c->batch_waves = w; }, [&] { c->batch_waves = was; }, &won);
             if (st != REACH_OK) break;
-            if (ns < best_ns) { best_ns = ns; best_waves = per_cu * c->cus; }
+            if (won) now = w;
         }
-        c->opt["batch.waves"] = 0;
-        if (st == REACH_OK) {
-            c->batch_waves = best_waves;
-            cur = best_ns;
-        }
+        best_waves = now;
     }
     c->opt["batch.E"] = save_E;
     hipEventDestroy(e0);

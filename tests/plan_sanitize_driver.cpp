@@ -48,7 +48,7 @@ static int check(int64_t nq, uint64_t seed, bool plant_bad) {
     for (int64_t k = 0; k < ni; ++k) {
         const int32_t E = width[(size_t)k];
         if (count[(size_t)k] < 1 || count[(size_t)k] > 64 || (E == 0 && count[(size_t)k] != 1) ||
-            (E != 0 && E != 2 && E != 4 && E != 8)) { std::printf("FAIL: count/width\n"); return 1; }
+            (E != 0 && E != 2 && E != 4 && E != 8 && E != 16)) { std::printf("FAIL: count/width\n"); return 1; }
         int64_t lanes = 0;
         for (int32_t j = 0; j < count[(size_t)k]; ++j) {
             const int64_t p = start[(size_t)k] + j;
