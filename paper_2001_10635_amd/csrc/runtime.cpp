@@ -64,7 +64,14 @@ struct TuneEntry { int E; int K; int S; };
 // Host worker threads kept for the life of a context (starting threads per
 // call costs more than the work they share on a batch of 10^5 queries).
 // run(nth, fn) calls fn(0) on the caller and fn(1 .. nth-1) on workers and
-// returns when all have finished.
+// returns when all have finished.  A batch plan runs five such phases back to
+// back, so a worker that finishes one watches the job counter for up to
+// kSpinUs before it sleeps on the condition variable (a wake-up from sleep
+// costs tens of microseconds per phase), and the caller likewise watches for
+// the last worker before it sleeps.  A worker that sees the new job while
+// watching takes it without the mutex (the job is published before the
+// counter, release / acquire), so that the workers of a phase do not queue on
+// one lock.
 class HostPool {
   public:
     explicit HostPool(int n) : n_(n) {
@@ -73,8 +80,9 @@ class HostPool {
     ~HostPool() {
         {
             std::lock_guard<std::mutex> g(m_);
-            stop_ = true;
+            stop_.store(true, std::memory_order_relaxed);
             ++gen_;
+            agen_.store(gen_, std::memory_order_release);
         }
         start_.notify_all();
         for (auto& t : th_) t.join();
@@ -87,46 +95,60 @@ class HostPool {
         }
         {
             std::lock_guard<std::mutex> g(m_);
-            job_ = &fn;
-            job_n_ = std::min(nth, n_);
-            pending_ = n_ - 1;
+            job_.store(&fn, std::memory_order_relaxed);
+            job_n_.store(std::min(nth, n_), std::memory_order_relaxed);
+            pending_.store(n_ - 1, std::memory_order_relaxed);
             ++gen_;
+            agen_.store(gen_, std::memory_order_release);
         }
         start_.notify_all();
         fn(0);
+        spin([&] { return pending_.load(std::memory_order_acquire) == 0; });
         std::unique_lock<std::mutex> lk(m_);
-        done_.wait(lk, [&] { return pending_ == 0; });
-        job_ = nullptr;
+        done_.wait(lk, [&] { return pending_.load(std::memory_order_acquire) == 0; });
     }
 
   private:
+    static constexpr int kSpinUs = 200;
+    template <class P>
+    static void spin(P&& ready) {
+        const auto until = std::chrono::steady_clock::now() + std::chrono::microseconds(kSpinUs);
+        while (!ready()) {
+            for (int k = 0; k < 64 && !ready(); ++k) __builtin_ia32_pause();
+            if (ready() || std::chrono::steady_clock::now() > until) return;
+        }
+    }
     void loop(int id) {
         uint64_t seen = 0;
         for (;;) {
-            const std::function<void(int)>* job = nullptr;
-            int jn = 0;
-            {
+            spin([&] { return agen_.load(std::memory_order_acquire) != seen; });
+            uint64_t g = agen_.load(std::memory_order_acquire);
+            if (g == seen) {
                 std::unique_lock<std::mutex> lk(m_);
                 start_.wait(lk, [&] { return gen_ != seen; });
-                seen = gen_;
-                if (stop_) return;
-                job = job_;
-                jn = job_n_;
+                g = gen_;
             }
+            seen = g;
+            if (stop_.load(std::memory_order_acquire)) return;
+            const std::function<void(int)>* job = job_.load(std::memory_order_relaxed);
+            const int jn = job_n_.load(std::memory_order_relaxed);
             if (id < jn) (*job)(id);
-            std::lock_guard<std::mutex> g(m_);
-            if (--pending_ == 0) done_.notify_one();
+            if (pending_.fetch_sub(1, std::memory_order_acq_rel) == 1) {
+                std::lock_guard<std::mutex> g(m_);
+                done_.notify_one();
+            }
         }
     }
     int n_;
     std::vector<std::thread> th_;
     std::mutex m_;
     std::condition_variable start_, done_;
-    const std::function<void(int)>* job_ = nullptr;
-    int job_n_ = 0;
-    int pending_ = 0;
-    uint64_t gen_ = 0;
-    bool stop_ = false;
+    std::atomic<const std::function<void(int)>*> job_{nullptr};
+    std::atomic<int> job_n_{0};
+    std::atomic<int> pending_{0};
+    uint64_t gen_ = 0;               // under m_; agen_ mirrors it for watchers
+    std::atomic<uint64_t> agen_{0};
+    std::atomic<bool> stop_{false};
 };
 
 struct reach_ctx {
@@ -1202,12 +1224,15 @@ reach_status make_desc(reach_ctx* c, const reach_query& q, int64_t tag, QDesc* d
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Host threads for preparing a batch of nq queries (1 below 16384 queries).
+// Host threads for preparing a batch of nq queries (1 below 16384 queries,
+// at most kMaxHostThreads).
+constexpr int64_t kMaxHostThreads = 16;
 int batch_host_threads(int64_t nq) {
     if (nq < 16384) return 1;
     const unsigned hw = std::thread::hardware_concurrency();
-    const int64_t by_size = nq / 8192;
-    return (int)std::max<int64_t>(1, std::min<int64_t>({by_size, 8, hw ? (int64_t)hw : 1}));
+    const int64_t by_size = nq / 4096;
+    return (int)std::max<int64_t>(
+        1, std::min<int64_t>({by_size, kMaxHostThreads, hw ? (int64_t)hw : 1}));
 }
 
 // fn(t) for t in [0, nth): t = 0 on the calling thread, the rest on the pool's
@@ -1221,12 +1246,24 @@ void run_threads(HostPool* pool, int nth, F&& fn) {
     pool->run(nth, std::function<void(int)>(fn));
 }
 
+// fn(u) for every u in [0, nu) on nth threads, each thread taking the next
+// unclaimed u: a thread the system holds back delays only the unit it holds,
+// and the outputs, kept per unit, do not depend on which thread ran which.
+template <class F>
+void run_units(HostPool* pool, int nth, int nu, F&& fn) {
+    std::atomic<int> next{0};
+    run_threads(pool, std::min(nth, nu), [&](int) {
+        for (int u = next.fetch_add(1); u < nu; u = next.fetch_add(1)) fn(u);
+    });
+}
+
 // The context's pool, started on first use with batch_host_threads' maximum.
 HostPool* host_pool(reach_ctx* c) {
     if (!c) return nullptr;
     if (!c->pool) {
         const unsigned hw = std::thread::hardware_concurrency();
-        c->pool.reset(new HostPool((int)std::max<int64_t>(1, std::min<int64_t>(8, hw ? hw : 1))));
+        c->pool.reset(new HostPool(
+            (int)std::max<int64_t>(1, std::min<int64_t>(kMaxHostThreads, hw ? hw : 1))));
     }
     return c->pool.get();
 }
@@ -1318,7 +1355,9 @@ int batch_ecap(const reach_ctx* c, int kind, int bucket) {
 // and the work items in launch order (items[k] covers members[start .. start
 // + count), indices into q, contiguous in launch order).
 //
-// Two parallel passes.  First each of nth threads reads a contiguous chunk of
+// Two parallel passes over nu work units (up to two per thread, claimed
+// dynamically; every output is kept per unit, so the plan does not depend on
+// which thread ran which unit).  First each unit reads a contiguous chunk of
 // the caller's array once: it validates every query (without touching the
 // context; the first bad query, lowest index, is re-checked with the context
 // afterwards to set the error message).  When the batch does not pack
@@ -1326,14 +1365,14 @@ int batch_ecap(const reach_ctx* c, int kind, int bucket) {
 // wave.  When it packs, every item is a segment pack, and each query gets a
 // pack key: its constants class (bitwise equal kind, dt and parameters),
 // cells per lane E (seg_E under the bucket's cap) and 1/16-octave step
-// bucket.  Then each thread owns the keys of the (E, bucket) pairs r with r
-// mod nth = its index and scans the queries of its keys in caller order,
-// placing each in the first of up to kOpen open packs of its key with room
-// (at most 64 lanes and kPackMax queries; when none has room the fullest is
-// closed); the packs still open at the end are packed again per key, widest
-// query first into the first pack with room.  Items are then ordered longest first by the wave time (E * steps
-// of the longest member; ceil(n / 64) * steps alone) at 1/16 octave, ties in
-// thread order.
+// bucket.  Then unit u owns the keys of the (E, bucket) pairs r with r mod
+// nu = u and scans the queries of its keys in caller order, placing each in
+// the first of up to kOpen open packs of its key with room (at most 64 lanes
+// and kPackMax queries; when none has room the fullest is closed); the packs
+// still open at the end are packed again per key, widest query first into
+// the first pack with room.  Items are then ordered longest first by the wave
+// time (E * steps of the longest member; ceil(n / 64) * steps alone) at 1/16
+// octave, ties in unit order.
 struct PlanTimes {
     double pass_ms = 0, order_ms = 0, members_ms = 0;
 };
@@ -1347,9 +1386,10 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
         return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
     };
     auto t0 = clk::now();
+    int nu = 1;   // work units (set below)
     auto chunk = [&](int t, int64_t total, int64_t* lo, int64_t* hi) {
-        *lo = total * t / nth;
-        *hi = total * (t + 1) / nth;
+        *lo = total * t / nu;
+        *hi = total * (t + 1) / nu;
     };
     constexpr int kBuckets = 64 * 16;
     constexpr int kLanes = 64;
@@ -1401,35 +1441,39 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
         o.lanes = 0;
         o.max_steps = 0;
     };
-    std::vector<std::vector<Item>> titems((size_t)nth);
-    std::vector<std::vector<uint32_t>> tmembers((size_t)nth);
-    std::vector<int64_t> bad((size_t)nth, nq);
+    // work units: contiguous chunks of the queries in pass 1, (E, step bucket)
+    // partitions in pass 2, item ranges after; several per thread, claimed
+    // dynamically (run_units)
+    nu = nth > 1 ? (int)std::min<int64_t>(2 * (int64_t)nth, std::max<int64_t>(nth, nq / 2048)) : 1;
+    std::vector<std::vector<Item>> titems((size_t)nu);
+    std::vector<std::vector<uint32_t>> tmembers((size_t)nu);
+    std::vector<int64_t> bad((size_t)nu, nq);
     // cells per lane of a packed query by cap (2, 4, 8, 16) and size
     int8_t etab[4][513];
     for (int ci = 0; ci < 4; ++ci)
         for (int64_t n = 1; n <= 512; ++n) etab[ci][n] = (int8_t)seg_E(n, 2 << ci);
     // pass 1: descriptors, validation, pack keys (class ids local to the
-    // thread); each packed query goes to the list of the thread that owns its
-    // (E, step bucket) pair, r mod nth
+    // chunk); a chunk's packed queries are listed by the partition owning
+    // their (E, step bucket) pair, r mod nu
     // what pass 2 needs of a query, carried in the lists so that it never
-    // reads the descriptors other threads wrote
+    // reads the descriptors other chunks wrote
     struct QRef {
         uint32_t i;
-        int32_t key;       // (E index, step bucket) << 4 | thread-local class
+        int32_t key;       // (E index, step bucket) << 4 | chunk-local class
         int64_t nsteps;
         int32_t L;         // lanes at the key's E
     };
-    std::vector<std::vector<Consts>> tclasses((size_t)nth);
-    std::vector<std::vector<std::vector<QRef>>> lists(
-        (size_t)nth, std::vector<std::vector<QRef>>((size_t)nth));
-    run_threads(pool, nth, [&](int t) {
+    std::vector<std::vector<Consts>> tclasses((size_t)nu);
+    std::vector<std::vector<QRef>> lists((size_t)nu);          // by partition, caller order within
+    std::vector<std::vector<uint32_t>> list_at((size_t)nu);    // partition p: [at[p], at[p + 1])
+    run_units(pool, nth, nu, [&](int t) {
         int64_t lo, hi;
         chunk(t, nq, &lo, &hi);
         std::vector<Item> items;
         std::vector<uint32_t> members;
         int64_t my_bad = nq;
         std::vector<Consts> classes;
-        std::vector<std::vector<QRef>>& mine = lists[(size_t)t];
+        std::vector<QRef> mine;
         for (int64_t i = lo; i < hi; ++i) {
             QDesc& d = descs[i];
             if (make_desc(nullptr, q[i], i, &d) != REACH_OK) {
@@ -1468,8 +1512,18 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
             while (kSegE[ei] != E) ++ei;
             const int b = wave_time_bucket((uint64_t)std::min<int64_t>(d.nsteps, (int64_t)1 << 40));
             const int r = ei * kBuckets + b;
-            mine[(size_t)(r % nth)].push_back(
-                QRef{(uint32_t)i, (r << 4) | cls, d.nsteps, (int32_t)((d.n + E - 1) / E)});
+            mine.push_back(QRef{(uint32_t)i, (r << 4) | cls, d.nsteps, (int32_t)((d.n + E - 1) / E)});
+        }
+        // by partition (counting sort, caller order kept within a partition)
+        std::vector<uint32_t>& at = list_at[(size_t)t];
+        at.assign((size_t)nu + 1, 0);
+        for (const QRef& qr : mine) ++at[(size_t)((qr.key >> 4) % nu) + 1];
+        for (int u = 0; u < nu; ++u) at[(size_t)u + 1] += at[(size_t)u];
+        std::vector<QRef>& sorted_refs = lists[(size_t)t];
+        sorted_refs.resize(mine.size());
+        {
+            std::vector<uint32_t> put(at.begin(), at.end() - 1);
+            for (const QRef& qr : mine) sorted_refs[put[(size_t)((qr.key >> 4) % nu)]++] = qr;
         }
         titems[(size_t)t] = std::move(items);
         tmembers[(size_t)t] = std::move(members);
@@ -1482,10 +1536,10 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
         return make_desc(c, q[first_bad], first_bad, &tmp);
     }
     if (packs) {
-        // global class ids (the threads' tables merged in thread order)
+        // global class ids (the chunks' tables merged in chunk order)
         std::vector<Consts> global;
-        std::vector<std::vector<int32_t>> remap((size_t)nth);
-        for (int t = 0; t < nth; ++t)
+        std::vector<std::vector<int32_t>> remap((size_t)nu);
+        for (int t = 0; t < nu; ++t)
             for (const Consts& cs : tclasses[(size_t)t]) {
                 int g = -1;
                 for (size_t u = 0; u < global.size(); ++u)
@@ -1497,20 +1551,16 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
                 remap[(size_t)t].push_back(g);
             }
         const size_t G = global.size();
-        // key = (E index, step bucket) * G + global class; thread t owns the
-        // (E index, step bucket) pairs r with r mod nth == t
-        std::vector<uint8_t> owner((size_t)kNE * kBuckets);
+        // key = (E index, step bucket) * G + global class; partition t owns
+        // the (E index, step bucket) pairs r with r mod nu == t
         std::vector<uint32_t> local((size_t)kNE * kBuckets);
-        std::vector<uint32_t> owned((size_t)nth, 0);
-        for (size_t r = 0; r < owner.size(); ++r) {
-            owner[r] = (uint8_t)(r % (size_t)nth);
-            local[r] = owned[owner[r]]++;
-        }
-        // pass 2: thread t packs the keys it owns, scanning the queries in
+        std::vector<uint32_t> owned((size_t)nu, 0);
+        for (size_t r = 0; r < local.size(); ++r) local[r] = owned[r % (size_t)nu]++;
+        // pass 2: partition t packs the keys it owns, scanning the queries in
         // caller order.  The scan only assigns each query a pack (fill levels
         // in a small table, a key's kOpen current packs side by side); the
         // packs' member lists are then formed by a counting sort on the pack.
-        run_threads(pool, nth, [&](int t) {
+        run_units(pool, nth, nu, [&](int t) {
             std::vector<Item>& items = titems[(size_t)t];
             std::vector<uint32_t>& members = tmembers[(size_t)t];
             struct Pack {
@@ -1521,9 +1571,11 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
             std::vector<int32_t> slot((size_t)owned[(size_t)t] * G * kOpen, -1);
             std::vector<const QRef*> refs;
             std::vector<int32_t> assign;
-            for (int u = 0; u < nth; ++u) {
+            for (int u = 0; u < nu; ++u) {
                 const std::vector<int32_t>& rm = remap[(size_t)u];
-                for (const QRef& qr : lists[(size_t)u][(size_t)t]) {
+                const std::vector<uint32_t>& at = list_at[(size_t)u];
+                for (uint32_t k = at[(size_t)t]; k < at[(size_t)t + 1]; ++k) {
+                    const QRef& qr = lists[(size_t)u][k];
                     const size_t r = (size_t)(qr.key >> 4);
                     const int E = kSegE[r / kBuckets];
                     const int L = qr.L;
@@ -1615,15 +1667,22 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
     }
     if (times) times->pass_ms = since(t0);
     t0 = clk::now();
-    // launch order: bucket-major, then thread, then the thread's item order
-    std::vector<int64_t> hist((size_t)nth * kBuckets, 0);
-    run_threads(pool, nth, [&](int t) {
+    // launch order: bucket-major, then unit, then the unit's item order
+    std::vector<int64_t> hist((size_t)nu * kBuckets, 0);
+    std::vector<int> blo((size_t)nu, kBuckets), bhi((size_t)nu, -1);   // buckets in use
+    run_units(pool, nth, nu, [&](int t) {
         int64_t* h = &hist[(size_t)t * kBuckets];
-        for (const Item& it : titems[(size_t)t]) ++h[it.bucket];
+        for (const Item& it : titems[(size_t)t]) {
+            ++h[it.bucket];
+            blo[(size_t)t] = std::min<int>(blo[(size_t)t], it.bucket);
+            bhi[(size_t)t] = std::max<int>(bhi[(size_t)t], it.bucket);
+        }
     });
+    const int b0 = *std::min_element(blo.begin(), blo.end());
+    const int b1 = *std::max_element(bhi.begin(), bhi.end());
     int64_t ni = 0;
-    for (int b = 0; b < kBuckets; ++b)
-        for (int t = 0; t < nth; ++t) {
+    for (int b = b0; b <= b1; ++b)
+        for (int t = 0; t < nu; ++t) {
             const int64_t v = hist[(size_t)t * kBuckets + b];
             hist[(size_t)t * kBuckets + b] = ni;
             ni += v;
@@ -1632,7 +1691,7 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
         uint32_t t, k;
     };
     std::vector<Ref> sorted((size_t)ni);
-    run_threads(pool, nth, [&](int t) {
+    run_units(pool, nth, nu, [&](int t) {
         int64_t* h = &hist[(size_t)t * kBuckets];
         const auto& items = titems[(size_t)t];
         for (size_t k = 0; k < items.size(); ++k)
@@ -1651,7 +1710,7 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
     t0 = clk::now();
     std::vector<uint32_t>& mo = *members_out;
     mo.resize((size_t)nq);
-    run_threads(pool, nth, [&](int t) {
+    run_units(pool, nth, nu, [&](int t) {
         int64_t lo, hi;
         chunk(t, ni, &lo, &hi);
         for (int64_t k = lo; k < hi; ++k) {
