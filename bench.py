@@ -316,7 +316,17 @@ def query_mix(rc, R, torch, workloads, nq, cpu=True):
                     "profiled_kernel_us": k_us,
                     "valu_issue_frac_of_profiled_kernel": (
                         round(valu * 64 / (k_us * 1e-6) / VALU_LANE_PEAK, 4)
-                        if valu and k_us else None)}
+                        if valu and k_us else None),
+                    # the same launch in GPU cycles (GRBM_COUNT of the PMC
+                    # summary): wave-instructions per CU-cycle, the launch at
+                    # the 2.4 GHz peak clock, and the clock the GPU ran at
+                    "valu_issue_per_cu_cycle": profile_value(
+                        "pack_kernel_mix1e5_f64_pmc.txt", "valu_issue_per_cu_cycle", BATCH_SOURCES),
+                    "profiled_kernel_us_at_2p4_ghz": profile_value(
+                        "pack_kernel_mix1e5_f64_pmc.txt", "launch_us_at_2.4_ghz", BATCH_SOURCES),
+                    "profiled_gpu_clock_ghz": profile_value(
+                        "pack_kernel_mix1e5_f64_pmc.txt", "gpu_clock_ghz_in_this_run",
+                        BATCH_SOURCES)}
     out["one_launch_per_query"] = {"queries_per_s": nq / te, "seconds": round(te, 4)}
     out["batch_speedup"] = round(te / tb, 2)
     out["batch_equals_per_query"] = same
