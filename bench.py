@@ -59,6 +59,7 @@ HEAT_SOURCES = ("dev.hpp", "heat3d.hip")
 # the packed batch's kernel sources (its instruction count also follows the
 # planner's packing, whose changes call for a new summary)
 BATCH_SOURCES = ("dev.hpp", "batch.hip")
+MC_SOURCES = ("dev.hpp", "mc.hip")
 # FP64 VALU instructions of one state-step's arithmetic in the batch kernels
 # (per cell and stage: RD 4, CTM 5 for the right-hand side; the RK4 updates
 # 1 + 2 + 2 + 2 over the four stages)
@@ -738,6 +739,15 @@ def extra_mc_ctm4096(rc, R, torch, workloads, cpu_samples):
                         "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s",
                         "frac": round(ops / sec / FP32_PEAK, 4),
                         "frac_of_nonpacked_peak": round(ops / sec / (FP32_PEAK / 2), 4)}}
+    # VALU issue of this launch from the committed PMC summary (taken on the
+    # current Monte Carlo sources), and per CU-cycle at the clock of that run
+    valu = profile_value("mc_kernel_ctm4096_f32_pmc.txt", "valu_wave_instructions_per_launch",
+                         MC_SOURCES)
+    if valu:
+        out["roofline"]["valu_lane_instructions_per_cell_step"] = round(valu * 64 / cell_steps, 2)
+        out["roofline"]["valu_issue_frac"] = round(valu * 64 / sec / VALU_LANE_PEAK, 4)
+        out["roofline"]["valu_issue_per_cu_cycle"] = profile_value(
+            "mc_kernel_ctm4096_f32_pmc.txt", "valu_issue_per_cu_cycle", MC_SOURCES)
     # containment in the FP64 embedding box of the same problem (the FP32 box
     # values are exact in FP64), with the FP32-vs-FP64 slack of the tests
     e_lo, e_hi = rc.embed(p.kind, p.prm, x_lo.double(), x_hi.double(), p.dt, p.nsteps)
