@@ -92,25 +92,61 @@ __device__ __forceinline__ void rk_update(T k, T& y, T& acc, T& t, const Steps<T
 // Where a window sits relative to the chain's right end.
 //   PAD : the window runs past cell n-1; cells at or beyond n hold the
 //         boundary's ghost value at every stage (nvalid cells of this lane are
-//         inside the chain).
+//         inside the chain): a select per cell.
+//   ONE : (with PAD; the Monte Carlo kernel, whose every wave may pad) only
+//         cell n, the right neighbour of cell n-1, is set to the ghost after
+//         each stage: slot `en` of the lane holding it, en the same in every
+//         lane, so one indexed register move per stage replaces the per-cell
+//         selects.  Cells beyond n then hold values that reach no cell of the
+//         chain and that no caller reads or checks.  Only for lane arrays of
+//         up to 128 bytes: an index into longer ones (or into both sides of a
+//         window) made the compiler move them to scratch memory.
 //   END : the window contains cell n-1, so lane 63's right neighbour is the
 //         ghost.  Zero-filled lane shifts already give the Dirichlet ghost 0;
 //         only the CTM's free outflow (ghost -inf) needs an explicit value.
 // A window's left end at cell 0 needs nothing: lane 0 receives 0 from the
 // left, which is both the Dirichlet ghost and the CTM's zero inflow flux.
-template <int E, bool PAD, bool END> struct Mask {
-    int nvalid;
+template <int E, bool PAD, bool END, bool ONE = false> struct Mask {
+    int nvalid;  // cells of this lane inside the chain
+    int en;      // slot of cell n in its lane (wave-uniform; ONE only)
+    bool mine;   // this lane holds cell n (ONE only)
+    template <class T> static constexpr bool indexed() { return PAD && ONE && E * sizeof(T) <= 128; }
+    template <class T> static constexpr bool per_cell() { return PAD && !indexed<T>(); }
     __device__ __forceinline__ bool ok(int e) const { return !PAD || e < nvalid; }
+    template <class T>
+    __device__ __forceinline__ void fix(T (&v)[E], T ghost) const {
+        if constexpr (indexed<T>()) {
+            const T cur = v[en];
+            v[en] = mine ? ghost : cur;
+        }
+    }
 };
+
+// The mask of a window whose first n_rel cells (1 <= n_rel <= 64 E) are the
+// chain's (cell n is the window's cell n_rel).
+template <int E, bool END, bool ONE = false>
+__device__ __forceinline__ Mask<E, true, END, ONE> chain_end_mask(int64_t n_rel) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t left = n_rel - (int64_t)lane * E;
+    Mask<E, true, END, ONE> M;
+    M.nvalid = (int)(left < 0 ? 0 : (left > E ? E : left));
+    M.en = 0;
+    M.mine = false;
+    if constexpr (ONE) {
+        M.en = __builtin_amdgcn_readfirstlane((int)(n_rel % E));
+        M.mine = lane == (int)(n_rel / E);
+    }
+    return M;
+}
 
 // One RK4 stage for all cells of the lane, for every side s < S.
 //   in  : the stage input (y for stage 1, t otherwise)
 // For S == 2 the sides are (lower, upper) of the embedding; for S == 1 the
 // kernel integrates f itself (Monte Carlo).
-template <int KIND, int STAGE, class T, int E, int S, int MODE, bool MASKED, bool END>
+template <int KIND, int STAGE, class T, int E, int S, int MODE, bool MASKED, bool END, bool ONE>
 __device__ __forceinline__ void rk_stage(T (&y)[S][E], T (&acc)[S][E], T (&t)[S][E],
                                          const SysPrm<T>& P, const Inputs<T, E, S, MODE>& U,
-                                         const Steps<T>& st, const Mask<E, MASKED, END>& M)
+                                         const Steps<T>& st, const Mask<E, MASKED, END, ONE>& M)
 {
     T (&in)[S][E] = (STAGE == 1) ? y : t;
     if constexpr (KIND == K_CTM) {
@@ -134,12 +170,13 @@ __device__ __forceinline__ void rk_stage(T (&y)[S][E], T (&acc)[S][E], T (&t)[S]
                 Fprev = F;
                 if (STAGE == 4) {
                     rk_update<4>(k, y[s][e], acc[s][e], t[s][e], st);
-                    if (MASKED && !M.ok(e)) y[s][e] = neg_inf<T>();
+                    if (M.template per_cell<T>() && !M.ok(e)) y[s][e] = neg_inf<T>();
                 } else {
                     rk_update<STAGE>(k, y[s][e], acc[s][e], t[s][e], st);
-                    if (MASKED && !M.ok(e)) t[s][e] = neg_inf<T>();
+                    if (M.template per_cell<T>() && !M.ok(e)) t[s][e] = neg_inf<T>();
                 }
             }
+            if constexpr (MASKED) M.fix(STAGE == 4 ? y[s] : t[s], neg_inf<T>());
         }
     } else if constexpr (KIND == K_RD) {
         // k = (y_{e-1} - 2 y_e + y_{e+1}) / h^2 - y_e^3 + u, Dirichlet ghosts 0,
@@ -160,12 +197,13 @@ __device__ __forceinline__ void rk_stage(T (&y)[S][E], T (&acc)[S][E], T (&t)[S]
                 left = mid;
                 if (STAGE == 4) {
                     rk_update<4>(k, y[s][e], acc[s][e], t[s][e], st);
-                    if (MASKED && !M.ok(e)) y[s][e] = T(0);
+                    if (M.template per_cell<T>() && !M.ok(e)) y[s][e] = T(0);
                 } else {
                     rk_update<STAGE>(k, y[s][e], acc[s][e], t[s][e], st);
-                    if (MASKED && !M.ok(e)) t[s][e] = T(0);
+                    if (M.template per_cell<T>() && !M.ok(e)) t[s][e] = T(0);
                 }
             }
+            if constexpr (MASKED) M.fix(STAGE == 4 ? y[s] : t[s], T(0));
         }
     } else {
         // LIN3.  S == 1: f = aL y_{e-1} + aD y_e + aR y_{e+1} + b u.
@@ -210,21 +248,25 @@ __device__ __forceinline__ void rk_stage(T (&y)[S][E], T (&acc)[S][E], T (&t)[S]
                 left[s] = mid[s];
                 if (STAGE == 4) {
                     rk_update<4>(k[s], y[s][e], acc[s][e], t[s][e], st);
-                    if (MASKED && !M.ok(e)) y[s][e] = T(0);
+                    if (M.template per_cell<T>() && !M.ok(e)) y[s][e] = T(0);
                 } else {
                     rk_update<STAGE>(k[s], y[s][e], acc[s][e], t[s][e], st);
-                    if (MASKED && !M.ok(e)) t[s][e] = T(0);
+                    if (M.template per_cell<T>() && !M.ok(e)) t[s][e] = T(0);
                 }
             }
+        }
+        if constexpr (MASKED) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) M.fix(STAGE == 4 ? y[s] : t[s], T(0));
         }
     }
 }
 
 // `nsteps` classical RK4 steps on the lane's registers.
-template <int KIND, class T, int E, int S, int MODE, bool MASKED, bool END>
+template <int KIND, class T, int E, int S, int MODE, bool MASKED, bool END, bool ONE>
 __device__ __forceinline__ void rk4_steps(T (&y)[S][E], int64_t nsteps, const SysPrm<T>& P,
                                           const Inputs<T, E, S, MODE>& U, const Steps<T>& st,
-                                          const Mask<E, MASKED, END>& M)
+                                          const Mask<E, MASKED, END, ONE>& M)
 {
     T acc[S][E], t[S][E];
     for (int64_t k = 0; k < nsteps; ++k) {

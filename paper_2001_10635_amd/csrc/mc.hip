@@ -42,8 +42,6 @@ __global__ __launch_bounds__(WAVE * MC_WPB) void mc_kernel(McArgs a) {
     const int64_t w = wb + wv;
     const int64_t n = a.n;
     const bool masked = (int64_t)WAVE * E > n;
-    const int64_t left = n - (int64_t)lane * E;
-    const int nvalid = (int)(left < 0 ? 0 : (left > E ? E : left));
 
     const T* __restrict__ xlo = (const T*)a.x_lo;
     const T* __restrict__ xhi = (const T*)a.x_hi;
@@ -136,7 +134,7 @@ __global__ __launch_bounds__(WAVE * MC_WPB) void mc_kernel(McArgs a) {
 
         // the wave holds the whole chain: its window always contains cell n-1
         if (masked) {
-            Mask<E, true, true> M{nvalid};
+            const auto M = chain_end_mask<E, true, true>(n);
             rk4_steps<KIND, T, E, 1, MODE>(y, a.nsteps, P, U, st, M);
         } else {
             Mask<E, false, true> M{E};
