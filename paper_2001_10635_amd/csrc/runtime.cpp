@@ -1380,7 +1380,8 @@ struct PlanTimes {
 reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int64_t nq,
                         int split, int nth, QDesc* descs, std::vector<uint32_t>* members_out,
                         std::vector<BatchItem>* items_out, int* packed,
-                        PlanTimes* times = nullptr) {
+                        PlanTimes* times = nullptr,
+                        const std::function<void()>& descs_done = nullptr) {
     using clk = std::chrono::steady_clock;
     auto since = [](clk::time_point t0) {
         return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
@@ -1535,6 +1536,9 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
         QDesc tmp;
         return make_desc(c, q[first_bad], first_bad, &tmp);
     }
+    // every descriptor is written: the caller may start moving them while
+    // the items are formed
+    if (descs_done) descs_done();
     if (packs) {
         // global class ids (the chunks' tables merged in chunk order)
         std::vector<Consts> global;
@@ -1797,25 +1801,32 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
         HIPCHK(c, hipEventSynchronize(c->staging_ev));
     }
     const BatchBlock hb = batch_block(c->staging, nq);
+    char* base = (char*)ws;
+    auto* counter = (unsigned long long*)base;
+    auto* qflags = (unsigned int*)(base + align256(8));
+    auto* pair = (unsigned int*)(base + align256(8) + align256(4 * (size_t)nq));
+    const BatchBlock db = batch_block(base + align256(8) + 2 * align256(4 * (size_t)nq), nq);
     const auto t_start = std::chrono::steady_clock::now();
     std::vector<uint32_t> members;
     std::vector<BatchItem> items;
     PlanTimes pt;
     int packed = 0;
+    // the descriptors go up as soon as they are written, while the host forms
+    // the work items (outside any captured graph: the graph copies the rest)
+    hipError_t desc_err = hipSuccess;
+    const size_t desc_bytes = sizeof(QDesc) * (size_t)nq;
     reach_status pst = plan_batch(c, pool, q, nq, split, nth, hb.desc, &members, &items, &packed,
-                                  &pt);
+                                  &pt, [&] {
+        desc_err = hipMemcpyAsync(db.desc, hb.desc, desc_bytes, hipMemcpyHostToDevice, hs);
+    });
     if (pst != REACH_OK) return pst;
+    if (desc_err != hipSuccess) return hip_fail(c, desc_err, "descriptor upload");
     const int64_t ni = (int64_t)items.size();
     std::memcpy(hb.items, items.data(), sizeof(BatchItem) * (size_t)ni);
     std::memcpy(hb.members, members.data(), sizeof(uint32_t) * (size_t)nq);
     *hb.count = (uint64_t)ni;
     const auto t_plan = std::chrono::steady_clock::now();
 
-    char* base = (char*)ws;
-    auto* counter = (unsigned long long*)base;
-    auto* qflags = (unsigned int*)(base + align256(8));
-    auto* pair = (unsigned int*)(base + align256(8) + align256(4 * (size_t)nq));
-    const BatchBlock db = batch_block(base + align256(8) + 2 * align256(4 * (size_t)nq), nq);
     int64_t grid = opt_get(c, "batch.waves");
     if (grid <= 0) {
         if (packed) grid = c->batch_waves;
@@ -1841,7 +1852,8 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     auto enqueue = [&](hipStream_t s) -> hipError_t {
         hipError_t e = launch_zero(base, (int64_t)(align256(8) + 2 * align256(4 * (size_t)nq)) / 4, s);
         if (e != hipSuccess) return e;
-        e = hipMemcpyAsync(db.desc, c->staging, batch_block_bytes(nq), hipMemcpyHostToDevice, s);
+        e = hipMemcpyAsync(db.items, hb.items, batch_block_bytes(nq) - desc_bytes,
+                           hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
         return launch_batch(db.desc, db.items, db.members, db.count, counter, qflags, pair,
                             c->status, split, packed, grid, s);
