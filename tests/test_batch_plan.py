@@ -113,6 +113,23 @@ def test_only_identical_constants_share_a_wave():
         "49 and 50 steps share packs"
 
 
+def test_more_constant_classes_than_a_chunk_keeps():
+    """40 step sizes in one packed batch: a work unit keeps 16 constant classes
+    in its table and runs queries of further classes in packs of their own, so
+    the plan still covers every query once, never mixes constants in a pack,
+    and packs the tabled classes densely."""
+    p = workloads.small_problem(workloads.KIND_RD, 12, 3, 40)
+    qs = [R.make_query(p.kind, 12, p.prm, R.REACH_F64, FAKE, FAKE, FAKE, FAKE,
+                       0.01 * (1 + k % 40), 40, FAKE, FAKE, n_in=1) for k in range(20000)]
+    plan = R.reach_plan_batch(None, qs, with_E=True)
+    check_plan(qs, plan)
+    for _, it in plan:
+        assert len({qs[i].dt for i in it}) == 1
+    sizes = [len(it) for _, it in plan]
+    assert max(sizes) > 1 and min(sizes) == 1, "shared packs and packs of their own"
+    assert len(plan) < len(qs), "the tabled classes pack"
+
+
 def test_cells_per_lane_follow_the_cost_rule():
     """At the default cap of 16 cells per lane: n = 10 packs at E = 4 (3
     lanes), n = 5 at E = 2 (no balanced 4-cell layout), n = 100 at E = 8 (13

@@ -119,11 +119,12 @@ def test_batch_equals_alone_and_oracle(rc, mix, mode):
         assert_rel(got[k][1], o_hi, 1e-12, f"query {k} upper")
 
 
-@pytest.mark.parametrize("mode", ["alone", "packed"])
+@pytest.mark.parametrize("mode", ["alone", "packed", "packed_E4"])
 def test_batch_graph_replays_match_eager(rc, mix, mode):
-    """The captured graph (counter reset kernel, descriptor upload, worker) is
-    replayed with eager work and synchronisation in between; every replay
-    equals the eager result."""
+    """The captured graph (counter reset kernel, upload of the work items,
+    worker; the descriptors are copied on the stream before it) is replayed
+    with eager work and synchronisation in between; every replay equals the
+    eager result, with the wide, the narrow and the one-query kernel."""
     qs = mix.queries()
     nb = R.reach_batch_workspace_bytes(len(qs))
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
@@ -362,6 +363,44 @@ def test_packs_with_unequal_steps_and_sizes_equal_alone(rc):
             assert rc.sync() == R.REACH_OK
             assert np.array_equal(got_lo[a:e], to_host(a_lo)), f"query {k} n={ns[k]} cap {cap}"
             assert np.array_equal(got_hi[a:e], to_host(a_hi)), f"query {k} n={ns[k]} cap {cap}"
+
+
+def test_many_constant_classes_equal_alone(rc):
+    """3000 reaction-diffusion queries with 40 step sizes in one packed batch:
+    classes past a work unit's table of 16 run in packs of their own, and
+    every box equals its single run bit for bit."""
+    rng = np.random.default_rng(5)
+    nq = 3000
+    ns = [int(v) for v in rng.integers(8, 80, nq)]
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    lo = rng.uniform(-0.5, 0.5, offs[-1])
+    hi = lo + rng.uniform(0.0, 0.05, offs[-1])
+    x_lo, x_hi = to_dev(lo), to_dev(hi)
+    p_lo, p_hi = to_dev(np.array([-0.1])), to_dev(np.array([0.1]))
+    r_lo = torch.full((int(offs[-1]),), np.nan, dtype=torch.float64, device="cuda")
+    r_hi = torch.full_like(r_lo, np.nan)
+    dts = [0.01 * (1 + k % 40) for k in range(nq)]
+    qs = [R.make_query(R.REACH_RD, ns[k], (1.0,), R.REACH_F64, x_lo.data_ptr() + 8 * int(offs[k]),
+                       x_hi.data_ptr() + 8 * int(offs[k]), r_lo.data_ptr() + 8 * int(offs[k]),
+                       r_hi.data_ptr() + 8 * int(offs[k]), dts[k], 30, p_lo, p_hi, n_in=1)
+          for k in range(nq)]
+    nb = R.reach_batch_workspace_bytes(nq)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    with options(rc, {"batch.pack": 1}):
+        plan = R.reach_plan_batch(rc.ctx, qs, with_E=True)
+        assert all(len({dts[i] for i in it}) == 1 for _, it in plan)
+        assert any(len(it) > 1 for _, it in plan)
+        say("packed batch of 40 constant classes")
+        R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
+        assert rc.sync() == R.REACH_OK
+    got_lo, got_hi = to_host(r_lo), to_host(r_hi)
+    for k in range(0, nq, 7):
+        a, e = int(offs[k]), int(offs[k + 1])
+        a_lo, a_hi = rc.embed(R.REACH_RD, (1.0,), x_lo[a:e].contiguous(), x_hi[a:e].contiguous(),
+                              dts[k], 30, p_lo=p_lo, p_hi=p_hi)
+        assert rc.sync() == R.REACH_OK
+        assert np.array_equal(got_lo[a:e], to_host(a_lo)), f"query {k}"
+        assert np.array_equal(got_hi[a:e], to_host(a_hi)), f"query {k}"
 
 
 def test_plan_follows_the_split_option(rc, mix):
