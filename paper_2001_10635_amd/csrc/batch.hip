@@ -427,9 +427,9 @@ __global__ __launch_bounds__(64) void batch_kernel(const QDesc* __restrict__ des
 // Persistent worker of a packed batch: every item is a segment pack.  The
 // packs' bodies are inlined into this one kernel (no calls).  EMAX is the
 // widest pack it runs: with EMAX = 8 its registers are capped for three waves
-// per SIMD (the extra resident wave hides the FP64 dependency latency of the
-// stage chains); the 16-cell bodies need ~240 registers, so EMAX = 16 runs
-// two waves per SIMD.
+// per SIMD (it runs fastest at two); the 16-cell bodies need ~240 registers,
+// so EMAX = 16 fits two waves per SIMD and runs fastest at one, whose 32
+// independent cell-sides per stage keep the SIMD issuing.
 template <int EMAX>
 __global__ __launch_bounds__(64, EMAX > 8 ? 2 : 3) void pack_kernel(
         const QDesc* __restrict__ desc, const BatchItem* __restrict__ items,

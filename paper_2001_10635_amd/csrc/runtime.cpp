@@ -1374,7 +1374,7 @@ int batch_ecap(const reach_ctx* c, int kind, int bucket) {
 // time (E * steps of the longest member; ceil(n / 64) * steps alone) at 1/16
 // octave, ties in unit order.
 struct PlanTimes {
-    double pass_ms = 0, order_ms = 0, members_ms = 0;
+    double pass1_ms = 0, pass_ms = 0, order_ms = 0, members_ms = 0;
 };
 
 reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int64_t nq,
@@ -1539,6 +1539,7 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
     // every descriptor is written: the caller may start moving them while
     // the items are formed
     if (descs_done) descs_done();
+    if (times) times->pass1_ms = since(t0);
     if (packs) {
         // global class ids (the chunks' tables merged in chunk order)
         std::vector<Consts> global;
@@ -1671,59 +1672,63 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
     }
     if (times) times->pass_ms = since(t0);
     t0 = clk::now();
-    // launch order: bucket-major, then unit, then the unit's item order
-    std::vector<int64_t> hist((size_t)nu * kBuckets, 0);
+    // launch order: bucket-major, then unit, then the unit's item order.  A
+    // count of items and of their members per (unit, bucket), one prefix over
+    // (bucket, unit), then every unit places its own items and members.
+    // (the counts live in buffers kept by the calling thread: fresh ones of this
+    // size would cost page faults on every call)
+    thread_local std::vector<int64_t> hist_buf, mhist_buf;
+    if (hist_buf.size() < (size_t)nu * kBuckets) {
+        hist_buf.resize((size_t)nu * kBuckets);
+        mhist_buf.resize((size_t)nu * kBuckets);
+    }
+    int64_t* hist = hist_buf.data();
+    int64_t* mhist = mhist_buf.data();
     std::vector<int> blo((size_t)nu, kBuckets), bhi((size_t)nu, -1);   // buckets in use
     run_units(pool, nth, nu, [&](int t) {
         int64_t* h = &hist[(size_t)t * kBuckets];
+        int64_t* mh = &mhist[(size_t)t * kBuckets];
+        std::fill(h, h + kBuckets, 0);
+        std::fill(mh, mh + kBuckets, 0);
         for (const Item& it : titems[(size_t)t]) {
             ++h[it.bucket];
+            mh[it.bucket] += it.count;
             blo[(size_t)t] = std::min<int>(blo[(size_t)t], it.bucket);
             bhi[(size_t)t] = std::max<int>(bhi[(size_t)t], it.bucket);
         }
     });
     const int b0 = *std::min_element(blo.begin(), blo.end());
     const int b1 = *std::max_element(bhi.begin(), bhi.end());
-    int64_t ni = 0;
+    int64_t ni = 0, nm = 0;
     for (int b = b0; b <= b1; ++b)
         for (int t = 0; t < nu; ++t) {
-            const int64_t v = hist[(size_t)t * kBuckets + b];
-            hist[(size_t)t * kBuckets + b] = ni;
+            const size_t x = (size_t)t * kBuckets + b;
+            const int64_t v = hist[x], mv = mhist[x];
+            hist[x] = ni;
+            mhist[x] = nm;
             ni += v;
+            nm += mv;
         }
-    struct Ref {
-        uint32_t t, k;
-    };
-    std::vector<Ref> sorted((size_t)ni);
-    run_units(pool, nth, nu, [&](int t) {
-        int64_t* h = &hist[(size_t)t * kBuckets];
-        const auto& items = titems[(size_t)t];
-        for (size_t k = 0; k < items.size(); ++k)
-            sorted[(size_t)h[items[k].bucket]++] = Ref{(uint32_t)t, (uint32_t)k};
-    });
-    std::vector<BatchItem>& io = *items_out;
-    io.resize((size_t)ni);
-    uint32_t p = 0;
-    for (int64_t k = 0; k < ni; ++k) {
-        const Item& it = titems[sorted[(size_t)k].t][sorted[(size_t)k].k];
-        io[(size_t)k] = BatchItem{p, it.count, it.E};
-        p += it.count;
-        if (it.E > 8) *packed = 2;
-    }
     if (times) times->order_ms = since(t0);
     t0 = clk::now();
+    std::vector<BatchItem>& io = *items_out;
     std::vector<uint32_t>& mo = *members_out;
+    io.resize((size_t)ni);
     mo.resize((size_t)nq);
+    std::vector<uint8_t> wide((size_t)nu, 0);
     run_units(pool, nth, nu, [&](int t) {
-        int64_t lo, hi;
-        chunk(t, ni, &lo, &hi);
-        for (int64_t k = lo; k < hi; ++k) {
-            const Ref r = sorted[(size_t)k];
-            const Item& it = titems[r.t][r.k];
-            const uint32_t* src = &tmembers[r.t][it.first];
-            std::memcpy(&mo[io[(size_t)k].start], src, sizeof(uint32_t) * it.count);
+        int64_t* h = &hist[(size_t)t * kBuckets];
+        int64_t* mh = &mhist[(size_t)t * kBuckets];
+        for (const Item& it : titems[(size_t)t]) {
+            const int64_t k = h[it.bucket]++;
+            const int64_t m = mh[it.bucket];
+            mh[it.bucket] += it.count;
+            io[(size_t)k] = BatchItem{(uint32_t)m, it.count, it.E};
+            std::memcpy(&mo[(size_t)m], &tmembers[(size_t)t][it.first], sizeof(uint32_t) * it.count);
+            if (it.E > 8) wide[(size_t)t] = 1;
         }
     });
+    if (std::find(wide.begin(), wide.end(), 1) != wide.end()) *packed = 2;
     if (times) times->members_ms = since(t0);
     return REACH_OK;
 }
@@ -1843,11 +1848,12 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
         using ms = std::chrono::duration<double, std::milli>;
         log_call(c, "\"call\": \"batch\", \"queries\": %lld, \"items\": %lld, \"packed\": %lld, "
                     "\"waves\": %lld, \"split\": %d, \"host_threads\": %d, \"plan_ms\": %.3f, "
-                    "\"plan_pass_ms\": %.3f, \"plan_order_ms\": %.3f, \"plan_members_ms\": %.3f",
+                    "\"plan_pass1_ms\": %.3f, \"plan_pass_ms\": %.3f, \"plan_order_ms\": %.3f, "
+                    "\"plan_members_ms\": %.3f",
                  (long long)nq, (long long)ni, (long long)(nq - (int64_t)std::count_if(
                      items.begin(), items.end(), [](const BatchItem& x) { return x.count == 1; })),
-                 (long long)grid, split, nth, ms(t_plan - t_start).count(), pt.pass_ms,
-                 pt.order_ms, pt.members_ms);
+                 (long long)grid, split, nth, ms(t_plan - t_start).count(), pt.pass1_ms,
+                 pt.pass_ms, pt.order_ms, pt.members_ms);
     }
     auto enqueue = [&](hipStream_t s) -> hipError_t {
         hipError_t e = launch_zero(base, (int64_t)(align256(8) + 2 * align256(4 * (size_t)nq)) / 4, s);
