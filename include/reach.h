@@ -347,9 +347,11 @@ int64_t reach_mc_samples(int64_t n, double eps, double delta);
  * `q` is a HOST array of nq queries whose pointers are device pointers; it is
  * read during the call only.  workspace: reach_batch_workspace_bytes(nq)
  * bytes of device memory.  Results are identical to nq separate
- * reach_embed_rk4 calls.  The launch sequence (counter reset, descriptor
- * upload, worker kernel) is replayed from a captured hipGraph when the same
- * nq capacity and stream repeat.
+ * reach_embed_rk4 calls.  The query descriptors are copied to the
+ * workspace on `stream` as soon as the host has written them, while it forms
+ * the work items; the rest of the sequence (counter reset, upload of the work
+ * items, worker kernel) is replayed from a captured hipGraph when the same nq
+ * capacity and stream repeat.
  * Errors: as reach_embed_rk4 for each query, REACH_E_UNSUPPORTED for n > 512,
  * REACH_F32 or per-cell inputs, REACH_E_NOMEM for a short workspace.
  */
