@@ -184,9 +184,9 @@ struct BatchItem {
 // Persistent batch worker: `grid` waves pull work items through *counter:
 // items[0 .. *n_items) (d[] in the caller's order, members[] the query
 // indices of the items in launch order).  packed 1: every item is a segment
-// pack of at most 8 cells per lane (E > 0), run by the packing kernel at
-// three waves per SIMD; packed 2: some pack has 16 cells per lane, all run by
-// the wide packing kernel at two waves per SIMD; packed 0:
+// pack of at most 8 cells per lane (E > 0), run by the packing kernel (room
+// for three waves per SIMD); packed 2: some pack has 16 cells per lane, all
+// run by the wide packing kernel (room for two); packed 0:
 // every item is one query (E = 0), or with `split` two per item (one per side
 // of a cooperative chain), pair[i] counting the finished sides of item i.
 hipError_t launch_batch(const QDesc* d, const BatchItem* items, const uint32_t* members,
