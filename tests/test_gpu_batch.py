@@ -403,6 +403,48 @@ def test_many_constant_classes_equal_alone(rc):
         assert np.array_equal(got_hi[a:e], to_host(a_hi)), f"query {k}"
 
 
+@pytest.mark.parametrize("cap", [16, 2])
+def test_packs_with_zero_and_few_steps_equal_alone(rc, cap):
+    """Packed queries of 1-512 cells with 0, 1, 2 or 5 steps: a zero-step
+    query returns its box, every box equals its single run bit for bit."""
+    rng = np.random.default_rng(17 + cap)
+    nq = 600
+    ns = [int(v) for v in rng.integers(1, 513, nq)]
+    steps = [int(v) for v in rng.choice([0, 1, 2, 5], nq)]
+    offs = np.concatenate([[0], np.cumsum(ns)])
+    lo = rng.uniform(-0.5, 0.5, offs[-1])
+    hi = lo + rng.uniform(0.0, 0.05, offs[-1])
+    x_lo, x_hi = to_dev(lo), to_dev(hi)
+    p_lo, p_hi = to_dev(np.array([-0.1])), to_dev(np.array([0.1]))
+    r_lo = torch.full((int(offs[-1]),), np.nan, dtype=torch.float64, device="cuda")
+    r_hi = torch.full_like(r_lo, np.nan)
+    qs = [R.make_query(R.REACH_RD, ns[k], (1.0,), R.REACH_F64, x_lo.data_ptr() + 8 * int(offs[k]),
+                       x_hi.data_ptr() + 8 * int(offs[k]), r_lo.data_ptr() + 8 * int(offs[k]),
+                       r_hi.data_ptr() + 8 * int(offs[k]), 0.1, steps[k], p_lo, p_hi, n_in=1)
+          for k in range(nq)]
+    nb = R.reach_batch_workspace_bytes(nq)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    with options(rc, {"batch.pack": 1, "batch.E": cap}):
+        plan = R.reach_plan_batch(rc.ctx, qs, with_E=True)
+        assert all(E for E, _ in plan)
+        say(f"packs with 0-5 steps, cap {cap}")
+        R.reach_embed_rk4_batch(rc.ctx, qs, ws, nb, 0)
+        assert rc.sync() == R.REACH_OK
+    got_lo, got_hi = to_host(r_lo), to_host(r_hi)
+    for k in range(nq):
+        a, e = int(offs[k]), int(offs[k + 1])
+        if steps[k] == 0:
+            assert np.array_equal(got_lo[a:e], lo[a:e]) and np.array_equal(got_hi[a:e], hi[a:e])
+            continue
+        if k % 5:
+            continue
+        a_lo, a_hi = rc.embed(R.REACH_RD, (1.0,), x_lo[a:e].contiguous(), x_hi[a:e].contiguous(),
+                              0.1, steps[k], p_lo=p_lo, p_hi=p_hi)
+        assert rc.sync() == R.REACH_OK
+        assert np.array_equal(got_lo[a:e], to_host(a_lo)), f"query {k} n={ns[k]}"
+        assert np.array_equal(got_hi[a:e], to_host(a_hi)), f"query {k} n={ns[k]}"
+
+
 def test_plan_follows_the_split_option(rc, mix):
     """With batch.split = 1 the batch runs one side per wave: no packs."""
     qs = mix.queries()
