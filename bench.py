@@ -965,6 +965,12 @@ def main():
                   "valu_lane_instructions_per_state_step": lanes_per_ss,
                   "valu_issue_frac": (round(lanes_per_ss * ss_per_launch_s / VALU_LANE_PEAK, 4)
                                       if lanes_per_ss else None),
+                  # the same issue in GPU cycles (GRBM_COUNT of the PMC summary's
+                  # run): wave-instructions per CU-cycle at the clock the GPU ran
+                  "valu_issue_per_cu_cycle": profile_value(
+                      "embed_tile_kernel_rd2p26_f64_pmc.txt", "valu_issue_per_cu_cycle"),
+                  "profiled_gpu_clock_ghz": profile_value(
+                      "embed_tile_kernel_rd2p26_f64_pmc.txt", "gpu_clock_ghz_in_this_run"),
                   # rocprof DRAM bytes (read + write) per launch over this launch time
                   "hbm_frac_measured": (round(traffic / launch_s / HBM_PEAK, 4)
                                         if traffic else None)}
