@@ -173,8 +173,8 @@ const char* reach_last_error(const reach_ctx* ctx);
                   the autotuned cap of the query's bucket, else that of the
                   whole batch, else 16)
      "batch.waves" resident waves of the batch kernels (0 = default: the
-                  autotuned count for a packed batch, else 8 per compute unit,
-                  4 when a pack has 16 cells per lane)
+                  count the autotuner chose for that packing kernel, else 8
+                  per compute unit, 4 when a pack has 16 cells per lane)
      "serve.mode" 0 (default): persistent serving kernel; 1: one launch per
                   served query (read by reach_server_start)
      "serve.waves" resident waves of the serving kernel (0 = default)

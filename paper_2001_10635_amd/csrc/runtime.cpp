@@ -161,7 +161,8 @@ struct reach_ctx {
     // (kind, dtype, log2 n bucket, per-cell inputs)
     std::map<std::tuple<int, int, int, int>, TuneEntry> tune;
     std::map<std::pair<int, int>, int> batch_tune;        // (kind, log2 n bucket) -> pack E cap
-    int64_t batch_waves = 0;                             // autotuned resident waves (0 = none)
+    int64_t batch_waves[2] = {0, 0};                     // autotuned resident waves of the
+                                                         // narrow / wide packing kernel (0 = none)
     int batch_cap = 0;                                   // autotuned pack E cap of all buckets (0 = none)
     int last_packed = 0;                                 // kernel of the last batch (launch_batch)
     // batch staging (pinned host) and graph cache
@@ -1834,7 +1835,7 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
 
     int64_t grid = opt_get(c, "batch.waves");
     if (grid <= 0) {
-        if (packed) grid = c->batch_waves;
+        if (packed) grid = c->batch_waves[packed - 1];
         if (grid <= 0)
             grid = (int64_t)c->cus * (packed == 2 ? kWideWavesPerCU
                                       : packed == 1 ? kPackWavesPerCU : kBatchWavesPerCU);
@@ -1938,7 +1939,7 @@ reach_status reach_autotune_batch(reach_ctx* c, const reach_query* q, int64_t nq
     const int64_t save_E = opt_get(c, "batch.E"), save_waves = opt_get(c, "batch.waves");
     c->opt["batch.E"] = 0;
     // widths are timed at each packing kernel's default wave count
-    c->batch_waves = 0;
+    c->batch_waves[0] = c->batch_waves[1] = 0;
     // a few untimed calls first, so that the device clock has left its idle
     // level before anything is compared
     reach_status st = REACH_OK;
@@ -2009,6 +2010,7 @@ reach_status reach_autotune_batch(reach_ctx* c, const reach_query* q, int64_t nq
         // from the kernel's default (one wave per SIMD for the wide kernel,
         // two for the narrow one), which the last timed call used
         const bool wide = c->last_packed == 2;
+        int64_t& tuned = c->batch_waves[wide ? 1 : 0];
         int64_t now = (int64_t)c->cus * (wide ? kWideWavesPerCU : kPackWavesPerCU);
         for (int64_t per_cu : {4, 8, 12}) {
             const int64_t w = per_cu * c->cus;
@@ -2016,7 +2018,7 @@ reach_status reach_autotune_batch(reach_ctx* c, const reach_query* q, int64_t nq
             if (w == now || (wide && per_cu > 8)) continue;
             bool won = false;
             const int64_t was = now;
-            st = trial([&] { c->batch_waves = w; }, [&] { c->batch_waves = was; }, &won);
+            st = trial([&] { tuned = w; }, [&] { tuned = was; }, &won);
             if (st != REACH_OK) break;
             if (won) now = w;
         }
