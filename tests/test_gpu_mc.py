@@ -37,7 +37,7 @@ def oracle_mc(kind, prm, lo, hi, pl, ph, dt, nsteps, m, seed, dtype, s0=0):
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
 @pytest.mark.parametrize("variant", ["ctm", "rd", "rd_cell", "lin3", "lin3_cell"])
-@pytest.mark.parametrize("n", [1, 3, 64, 100, 257, 1000, 2048])
+@pytest.mark.parametrize("n", [1, 3, 64, 100, 257, 1000, 1500, 2048])
 def test_mc_matches_oracle(rc, variant, n, dtype):
     case = make_case(variant, n, dtype, seed=2000 + n)
     m, nsteps, seed = 48, 23, 31 + n
@@ -48,6 +48,21 @@ def test_mc_matches_oracle(rc, variant, n, dtype):
     rt = RTOL[np.dtype(dtype)]
     assert_rel(g_min, o_min, rt, "min")
     assert_rel(g_max, o_max, rt, "max")
+
+
+@pytest.mark.parametrize("variant", ["ctm", "rd", "rd_cell", "lin3", "lin3_cell"])
+@pytest.mark.parametrize("n", [2100, 3000, 4000])
+def test_mc_f32_wide_padded_matches_oracle(rc, variant, n):
+    """FP32 chains of 2049-4095 cells: 64 cells per lane with the chain ending
+    inside the wave (the per-cell boundary select of the widest lanes)."""
+    case = make_case(variant, n, np.float32, seed=2000 + n)
+    m, nsteps, seed = 32, 17, 31 + n
+    say(f"mc {variant} n={n} float32")
+    g_min, g_max, st = run_mc(rc, *case, nsteps, m, seed)
+    assert st == R.REACH_OK
+    o_min, o_max = oracle_mc(*case, nsteps, m, seed, np.float32)
+    assert_rel(g_min, o_min, 1e-5, "min")
+    assert_rel(g_max, o_max, 1e-5, "max")
 
 
 def test_mc_f32_full_width_n4096(rc):
