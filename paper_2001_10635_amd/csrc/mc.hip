@@ -34,7 +34,96 @@ __device__ __forceinline__ T nan_max(T m, T x) {
 // instead of stacking single-wave groups on the same SIMDs.
 constexpr int MC_WPB = 4;
 
+// Balanced layout of a chain that ends inside the wave, for lane arrays too
+// long for the indexed ghost fix-up of the other padded waves: the chain
+// fills lanes 0 .. L-1 (L = ceil(n / E)), the first F = n - L (E - 1) of them
+// with E cells and the others ("short" lanes) with E - 1, so that cell n-1 is
+// the last cell of lane L-1 and no cell of the chain has a padded neighbour
+// inside its lane.  Per stage a short lane takes its last cell's right
+// neighbour, and the value it hands to the lane on its left, by a select, and
+// lane L-1 takes the ghost as its right neighbour: a few selects per stage
+// instead of one per cell.  Lanes past L-1 and a short lane's unused slot
+// compute values that reach no cell of the chain.  Per cell the arithmetic is
+// the general stage's (rk_stage).
+template <int E, class T>
+__device__ __forceinline__ T mc_right_of(const T (&in)[E], int e, T rn, bool shortl) {
+    if (e == E - 1) return rn;
+    if (e == E - 2) return shortl ? rn : in[E - 1];
+    return in[e + 1];
+}
+template <int E, class T>
+__device__ __forceinline__ T mc_last_of(const T (&in)[E], bool shortl) {
+    return shortl ? in[E - 2] : in[E - 1];
+}
+
+template <int KIND, int STAGE, class T, int E, int MODE>
+__device__ __forceinline__ void mc_bal_stage(T (&y)[E], T (&acc)[E], T (&t)[E],
+                                             const SysPrm<T>& P, const Inputs<T, E, 1, MODE>& U,
+                                             const Steps<T>& st, bool shortl, bool endl) {
+    T (&in)[E] = (STAGE == 1) ? y : t;
+    if constexpr (KIND == K_CTM) {
+        // free outflow past cell n-1 (ghost -inf), zero inflow into cell 0
+        // (lane 0 receives 0 from the shift)
+        const T v = P.a0, w = P.a1, wc = P.a2, q = P.a3;
+        T rn = from_right(in[0]);
+        rn = endl ? neg_inf<T>() : rn;
+        T F[E];
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+            F[e] = minT(minT(v * in[e], fmaT(-w, mc_right_of<E>(in, e, rn, shortl), wc)), q);
+        T Fprev = from_left(mc_last_of<E>(F, shortl));
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const T k = Fprev - F[e];
+            Fprev = F[e];
+            rk_update<STAGE>(k, y[e], acc[e], t[e], st);
+        }
+    } else if constexpr (KIND == K_RD) {
+        // Dirichlet ghosts 0
+        const T ih2 = P.a0, two_ih2 = P.a1;
+        T left = from_left(mc_last_of<E>(in, shortl));
+        T rn = from_right(in[0]);
+        rn = endl ? T(0) : rn;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const T mid = in[e];
+            const T right = mc_right_of<E>(in, e, rn, shortl);
+            const T loc = fmaT(-mid, fmaT(mid, mid, two_ih2), U.at(0, e));
+            const T k = fmaT(left + right, ih2, loc);
+            left = mid;
+            rk_update<STAGE>(k, y[e], acc[e], t[e], st);
+        }
+    } else {
+        // LIN3 integrating f itself: aL y_{e-1} + aD y_e + aR y_{e+1} + b u, ghosts 0
+        const T aL = P.a0, aD = P.a1, aR = P.a2, b = P.a3;
+        T left = from_left(mc_last_of<E>(in, shortl));
+        T rn = from_right(in[0]);
+        rn = endl ? T(0) : rn;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+            const T mid = in[e];
+            const T right = mc_right_of<E>(in, e, rn, shortl);
+            const T k = fmaT(b, U.at(0, e), fmaT(aR, right, fmaT(aD, mid, aL * left)));
+            left = mid;
+            rk_update<STAGE>(k, y[e], acc[e], t[e], st);
+        }
+    }
+}
+
 template <int KIND, class T, int E, int MODE>
+__device__ __forceinline__ void mc_bal_steps(T (&y)[E], int64_t nsteps, const SysPrm<T>& P,
+                                             const Inputs<T, E, 1, MODE>& U, const Steps<T>& st,
+                                             bool shortl, bool endl) {
+    T acc[E], t[E];
+    for (int64_t k = 0; k < nsteps; ++k) {
+        mc_bal_stage<KIND, 1>(y, acc, t, P, U, st, shortl, endl);
+        mc_bal_stage<KIND, 2>(y, acc, t, P, U, st, shortl, endl);
+        mc_bal_stage<KIND, 3>(y, acc, t, P, U, st, shortl, endl);
+        mc_bal_stage<KIND, 4>(y, acc, t, P, U, st, shortl, endl);
+    }
+}
+
+template <int KIND, class T, int E, int MODE, bool BAL = false>
 __global__ __launch_bounds__(WAVE * MC_WPB) void mc_kernel(McArgs a) {
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
@@ -42,6 +131,14 @@ __global__ __launch_bounds__(WAVE * MC_WPB) void mc_kernel(McArgs a) {
     const int64_t w = wb + wv;
     const int64_t n = a.n;
     const bool masked = (int64_t)WAVE * E > n;
+    // BAL (chosen by the host): a padded wave whose lane arrays are too long
+    // for the indexed ghost fix-up, in the balanced layout (n >= (E - 1) L)
+    const int64_t Lb = (n + E - 1) / E;
+    const int64_t Fb = n - Lb * (E - 1);               // lanes holding E cells
+    const bool shortl = lane >= Fb;
+    const int cnt = lane >= Lb ? 0 : (shortl ? E - 1 : E);
+    const int64_t first_j = (int64_t)lane * E - (shortl ? (int64_t)lane - Fb : 0);
+    const bool endl = lane == Lb - 1;
 
     const T* __restrict__ xlo = (const T*)a.x_lo;
     const T* __restrict__ xhi = (const T*)a.x_hi;
@@ -56,6 +153,61 @@ __global__ __launch_bounds__(WAVE * MC_WPB) void mc_kernel(McArgs a) {
     for (int64_t s = w < a.nw ? a.s0 + w : a.s0 + a.m; s < a.s0 + a.m; s += a.nw) {
         T y[1][E];
         Inputs<T, E, 1, MODE> U;
+        if constexpr (BAL) {
+            {
+                // balanced layout: slot e of this lane is cell first_j + e
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int64_t j = first_j + e;
+                    const U4 r = philox4x64_10((uint64_t)(j >> 2), (uint64_t)s, MC_STREAM, 0, k0, k1);
+                    const T u = unif(philox_word(r, (int)(j & 3)), T(0));
+                    y[0][e] = ghost<KIND, T>();
+                    if (e < cnt) y[0][e] = fmaT(u, xhi[j] - xlo[j], xlo[j]);
+                }
+                if constexpr (MODE == IN_SCALAR) {
+                    if (a.n_in == 0) {
+                        U.u[0] = T(0);
+                    } else {
+                        const U4 r = philox4x64_10((uint64_t)(n >> 2), (uint64_t)s, MC_STREAM, 0, k0, k1);
+                        const T u = unif(philox_word(r, (int)(n & 3)), T(0));
+                        const T pl = ((const T*)a.p_lo)[0], ph = ((const T*)a.p_hi)[0];
+                        U.u[0] = fmaT(u, ph - pl, pl);
+                    }
+                } else {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const int64_t c = first_j + e;
+                        const int64_t j = n + c;
+                        const U4 r = philox4x64_10((uint64_t)(j >> 2), (uint64_t)s, MC_STREAM, 0, k0, k1);
+                        const T u = unif(philox_word(r, (int)(j & 3)), T(0));
+                        U.u[0][e] = T(0);
+                        if (e < cnt) {
+                            const T pl = ((const T*)a.p_lo)[c], ph = ((const T*)a.p_hi)[c];
+                            U.u[0][e] = fmaT(u, ph - pl, pl);
+                        }
+                    }
+                }
+                mc_bal_steps<KIND, T, E, MODE>(y[0], a.nsteps, P, U, st, shortl, endl);
+                // each cell's running min / max in the slot of the plain
+                // layout (slot j mod E of lane j / E), which the reduction reads
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    if (e < cnt) {
+                        const int64_t j = first_j + e;
+                        const size_t idx = (size_t)(j % E) * WAVE + (size_t)(j / E);
+                        if (first) {
+                            pmin[idx] = y[0][e];
+                            pmax[idx] = y[0][e];
+                        } else {
+                            pmin[idx] = nan_min(pmin[idx], y[0][e]);
+                            pmax[idx] = nan_max(pmax[idx], y[0][e]);
+                        }
+                    }
+                }
+                first = false;
+                continue;
+            }
+        }
         // initial state: one Philox block per 4 consecutive cells
         if constexpr (E % 4 == 0) {
 #pragma unroll
@@ -252,6 +404,16 @@ __global__ __launch_bounds__(WAVE * RED_WAVES) void mc_reduce_kernel(
 template <int KIND, class T, int E, int MODE>
 static hipError_t go(const McArgs& a, hipStream_t s) {
     const unsigned grid = (unsigned)((a.nw + MC_WPB - 1) / MC_WPB);
+    // the balanced layout for padded waves with lane arrays over 128 bytes
+    const int64_t L = (a.n + E - 1) / E;
+    const bool bal = E * sizeof(T) > 128 && (int64_t)WAVE * E > a.n && a.n >= (int64_t)(E - 1) * L;
+    if constexpr (E * sizeof(T) > 128) {
+        if (bal) {
+            hipLaunchKernelGGL((mc_kernel<KIND, T, E, MODE, true>), dim3(grid), dim3(WAVE * MC_WPB),
+                               0, s, a);
+            return hipGetLastError();
+        }
+    }
     hipLaunchKernelGGL((mc_kernel<KIND, T, E, MODE>), dim3(grid), dim3(WAVE * MC_WPB), 0, s, a);
     return hipGetLastError();
 }
