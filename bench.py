@@ -396,6 +396,30 @@ def query_mix(rc, R, torch, workloads, nq, cpu=True):
     for mode, name in ((0, "served_persistent"), (1, "served_launch_per_query")):
         out[name] = serve(mode, nq, 1.0)
         log(f"{name}: {out[name]}")
+    # what a query costs with the server otherwise idle: the query at the 99th
+    # percentile of the wave time ceil(n / 64) x steps, and the longest one,
+    # each submitted alone and polled to its result (median of 20 after one
+    # that may start the grid), beside the served p99, which adds queueing
+    # behind other queries to such times
+    cost = np.array([-(-int(q.problem.n) // 64) * int(q.problem.nsteps) for q in qs])
+    order = np.argsort(cost, kind="stable")
+    rc.set_option("serve.mode", 0)
+    R.reach_server_start(rc.ctx, pool, pool.numel(), 1024)
+    alone = {}
+    for name, i in (("p99_cost_query", int(order[int(0.99 * (nq - 1))])),
+                    ("max_cost_query", int(order[-1]))):
+        reps = []
+        for _ in range(21):
+            t = time.perf_counter()
+            tk = R.reach_submit(rc.ctx, hq[i])
+            while R.reach_poll(rc.ctx, tk)[0] == R.REACH_PENDING:
+                pass
+            reps.append(time.perf_counter() - t)
+        alone[name] = {"n": int(qs[i].problem.n), "nsteps": int(qs[i].problem.nsteps),
+                       "submit_to_result_us": round(float(np.median(reps[1:])) * 1e6, 1)}
+    R.reach_server_stop(rc.ctx)
+    out["served_persistent"]["alone_on_idle_server"] = alone
+    log(f"alone: {alone}")
     # launch per query cannot keep up with 5e4/s: its latency then grows with
     # the backlog.  Its rate under that overload is the most it sustains; the
     # same stream slowed to 80% of that rate (the first 2 s of it) gives its
