@@ -347,11 +347,17 @@ int64_t reach_mc_samples(int64_t n, double eps, double delta);
  * `q` is a HOST array of nq queries whose pointers are device pointers; it is
  * read during the call only.  workspace: reach_batch_workspace_bytes(nq)
  * bytes of device memory.  Results are identical to nq separate
- * reach_embed_rk4 calls.  The query descriptors are copied to the
- * workspace on `stream` as soon as the host has written them, while it forms
- * the work items; the rest of the sequence (counter reset, upload of the work
- * items, worker kernel) is replayed from a captured hipGraph when the same nq
- * capacity and stream repeat.
+ * reach_embed_rk4 calls.  The workspace holds two blocks of descriptors
+ * and work items, used by turns.  The query descriptors are copied into this
+ * call's block on the context's own copy stream as soon as the host has
+ * written them, while it forms the work items, which follow; the upload waits
+ * only for the kernel that read the block two batches before.  The counter
+ * reset and the worker kernel (replayed from a captured hipGraph when the
+ * same nq capacity, block and stream repeat) run on `stream` after the upload
+ * and after the context's previous batch kernel, on whichever stream that ran.
+ * The call returns once the uploads are issued, so batches issued back to
+ * back overlap the host's planning and the upload of one batch with the
+ * previous batch's kernel.
  * Errors: as reach_embed_rk4 for each query, REACH_E_UNSUPPORTED for n > 512,
  * REACH_F32 or per-cell inputs, REACH_E_NOMEM for a short workspace.
  */

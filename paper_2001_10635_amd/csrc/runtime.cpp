@@ -168,7 +168,13 @@ struct reach_ctx {
     // batch staging (pinned host) and graph cache
     QDesc* staging = nullptr;            // [nq] descriptors, [nq] items, item count
     int64_t staging_cap = 0;
-    hipEvent_t staging_ev = nullptr;
+    hipEvent_t staging_ev = nullptr;     // the last batch's uploads from the staging are done
+    hipEvent_t batch_ev = nullptr;       // the last batch's kernel is done
+    hipEvent_t block_ev[2] = {nullptr, nullptr};   // the last kernel that read workspace block b
+    bool batch_ev_recorded = false;
+    bool block_ev_recorded[2] = {false, false};
+    int next_block = 0;                  // workspace block of the next batch
+    hipStream_t copy_stream = nullptr;   // batch uploads, beside the previous batch's kernel
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::vector<hipStream_t> each_streams;
     bool log = false;                    // REACH_LOG: one JSON line per call on stderr
@@ -692,6 +698,17 @@ reach_status reach_ctx_create(int device, reach_ctx** out) {
     if (hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming) != hipSuccess) {
         hipFree(c->status); delete c; return REACH_E_DEVICE;
     }
+    bool ok = hipEventCreateWithFlags(&c->batch_ev, hipEventDisableTiming) == hipSuccess;
+    for (int k = 0; k < 2 && ok; ++k)
+        ok = hipEventCreateWithFlags(&c->block_ev[k], hipEventDisableTiming) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&c->copy_stream, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        for (hipEvent_t e : {c->staging_ev, c->batch_ev, c->block_ev[0], c->block_ev[1]})
+            if (e) hipEventDestroy(e);
+        hipFree(c->status);
+        delete c;
+        return REACH_E_DEVICE;
+    }
     *out = c;
     return REACH_OK;
 }
@@ -707,6 +724,10 @@ void reach_ctx_destroy(reach_ctx* c) {
     for (auto s : c->each_streams) hipStreamDestroy(s);
     if (c->staging) hipHostFree(c->staging);
     if (c->staging_ev) hipEventDestroy(c->staging_ev);
+    if (c->batch_ev) hipEventDestroy(c->batch_ev);
+    for (hipEvent_t e : c->block_ev)
+        if (e) hipEventDestroy(e);
+    if (c->copy_stream) hipStreamDestroy(c->copy_stream);
     if (c->status) hipFree(c->status);
     c->pool.reset();
     delete c;
@@ -1739,10 +1760,10 @@ reach_status plan_batch(reach_ctx* c, HostPool* pool, const reach_query* q, int6
 extern "C" {
 
 // batch workspace: [work counter][per-query flags][per-query side counters]
-// [descriptors, items, item count]
+// and two blocks of [descriptors, items, item count, members], used by turns
 size_t reach_batch_workspace_bytes(int64_t nq) {
     if (nq < 0) return (size_t)-1;
-    return align256(8) + 2 * align256(4 * (size_t)nq) + align256(batch_block_bytes(nq));
+    return align256(8) + 2 * align256(4 * (size_t)nq) + 2 * align256(batch_block_bytes(nq));
 }
 
 reach_status reach_plan_batch(reach_ctx* c, const reach_query* q, int64_t nq,
@@ -1793,9 +1814,11 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     const int split = opt_get(c, "batch.split") ? 1 : 0;
     HostPool* pool = batch_host_threads(nq) > 1 ? host_pool(c) : nullptr;
     const int nth = pool ? std::min(batch_host_threads(nq), pool->size()) : 1;
-    // pinned staging (reused; wait for the previous upload from it)
+    // pinned staging (reused; wait for the previous upload from it, which
+    // ends before that batch's kernel starts).  Growing it drops the cached
+    // graphs, after every launched one has finished.
     if (c->staging_cap < nq) {
-        HIPCHK(c, hipEventSynchronize(c->staging_ev));
+        HIPCHK(c, hipDeviceSynchronize());
         if (c->staging) HIPCHK(c, hipHostFree(c->staging));
         c->staging = nullptr;
         for (auto& kv : c->graphs) hipGraphExecDestroy(kv.second);
@@ -1811,19 +1834,28 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     auto* counter = (unsigned long long*)base;
     auto* qflags = (unsigned int*)(base + align256(8));
     auto* pair = (unsigned int*)(base + align256(8) + align256(4 * (size_t)nq));
-    const BatchBlock db = batch_block(base + align256(8) + 2 * align256(4 * (size_t)nq), nq);
+    // two blocks of descriptors and work items, used by turns: this batch's
+    // upload (on the context's copy stream) waits only for the kernel that
+    // read its block two batches ago, so it runs beside the previous batch's
+    // kernel; the counter reset and the kernel wait for that kernel, on any
+    // stream, and for the upload
+    const int blk = c->next_block;
+    const BatchBlock db = batch_block(base + align256(8) + 2 * align256(4 * (size_t)nq) +
+                                      (size_t)blk * align256(batch_block_bytes(nq)), nq);
+    hipStream_t cs = c->copy_stream;
+    if (c->block_ev_recorded[blk]) HIPCHK(c, hipStreamWaitEvent(cs, c->block_ev[blk], 0));
     const auto t_start = std::chrono::steady_clock::now();
     std::vector<uint32_t> members;
     std::vector<BatchItem> items;
     PlanTimes pt;
     int packed = 0;
     // the descriptors go up as soon as they are written, while the host forms
-    // the work items (outside any captured graph: the graph copies the rest)
+    // the work items
     hipError_t desc_err = hipSuccess;
     const size_t desc_bytes = sizeof(QDesc) * (size_t)nq;
     reach_status pst = plan_batch(c, pool, q, nq, split, nth, hb.desc, &members, &items, &packed,
                                   &pt, [&] {
-        desc_err = hipMemcpyAsync(db.desc, hb.desc, desc_bytes, hipMemcpyHostToDevice, hs);
+        desc_err = hipMemcpyAsync(db.desc, hb.desc, desc_bytes, hipMemcpyHostToDevice, cs);
     });
     if (pst != REACH_OK) return pst;
     if (desc_err != hipSuccess) return hip_fail(c, desc_err, "descriptor upload");
@@ -1856,11 +1888,16 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
                  (long long)grid, split, nth, ms(t_plan - t_start).count(), pt.pass1_ms,
                  pt.pass_ms, pt.order_ms, pt.members_ms);
     }
+    // the rest of the block (items, their count, the members) follows; the
+    // staging is free for the next call once both copies are done, so the
+    // next call plans while this batch's kernel runs
+    HIPCHK(c, hipMemcpyAsync(db.items, hb.items, batch_block_bytes(nq) - desc_bytes,
+                             hipMemcpyHostToDevice, cs));
+    HIPCHK(c, hipEventRecord(c->staging_ev, cs));
+    HIPCHK(c, hipStreamWaitEvent(hs, c->staging_ev, 0));
+    if (c->batch_ev_recorded) HIPCHK(c, hipStreamWaitEvent(hs, c->batch_ev, 0));
     auto enqueue = [&](hipStream_t s) -> hipError_t {
         hipError_t e = launch_zero(base, (int64_t)(align256(8) + 2 * align256(4 * (size_t)nq)) / 4, s);
-        if (e != hipSuccess) return e;
-        e = hipMemcpyAsync(db.items, hb.items, batch_block_bytes(nq) - desc_bytes,
-                           hipMemcpyHostToDevice, s);
         if (e != hipSuccess) return e;
         return launch_batch(db.desc, db.items, db.members, db.count, counter, qflags, pair,
                             c->status, split, packed, grid, s);
@@ -1870,7 +1907,7 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
         hipError_t e = enqueue(hs);
         if (e != hipSuccess) return hip_fail(c, e, "batch launch");
     } else {
-        GraphKey key{nq, ws, c->staging, (grid * 2 + split) * 3 + packed, hs};
+        GraphKey key{nq, ws, c->staging, (((grid * 2 + split) * 3 + packed) * 2 + blk), hs};
         auto it = c->graphs.find(key);
         if (it == c->graphs.end()) {
             hipGraph_t g = nullptr;
@@ -1887,7 +1924,11 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
         }
         HIPCHK(c, hipGraphLaunch(it->second, hs));
     }
-    HIPCHK(c, hipEventRecord(c->staging_ev, hs));
+    HIPCHK(c, hipEventRecord(c->batch_ev, hs));
+    HIPCHK(c, hipEventRecord(c->block_ev[blk], hs));
+    c->batch_ev_recorded = true;
+    c->block_ev_recorded[blk] = true;
+    c->next_block = 1 - blk;
     (void)counter;
     return REACH_OK;
 }

@@ -121,8 +121,8 @@ def test_batch_equals_alone_and_oracle(rc, mix, mode):
 
 @pytest.mark.parametrize("mode", ["alone", "packed", "packed_E4"])
 def test_batch_graph_replays_match_eager(rc, mix, mode):
-    """The captured graph (counter reset kernel, upload of the work items,
-    worker; the descriptors are copied on the stream before it) is replayed
+    """The captured graph (counter reset kernel and worker; the descriptors
+    and the work items are copied on the stream before it) is replayed
     with eager work and synchronisation in between; every replay equals the
     eager result, with the wide, the narrow and the one-query kernel."""
     qs = mix.queries()
@@ -263,6 +263,36 @@ def test_batch_of_20000_queries_equals_one_launch_per_query(rc):
                                       dt=0.01, nsteps=int(b["ks"][i]))
         assert_rel(got_lo[a:e], o_lo, 1e-12, f"query {i} lower")
         assert_rel(got_hi[a:e], o_hi, 1e-12, f"query {i} upper")
+
+
+def test_back_to_back_batches_on_two_streams_share_a_workspace(rc):
+    """Batches issued without waiting, alternately on two streams with one
+    workspace: a call plans while the previous batch's kernel runs, and its
+    uploads wait on the device for that kernel, so every box equals the
+    query's own launch bit for bit."""
+    A = packed_ctm_batch(20000, 11)
+    B = packed_ctm_batch(20000, 12)
+    qa = R.query_array([A["q"](i) for i in range(20000)])
+    qb = R.query_array([B["q"](i) for i in range(20000)])
+    nb = R.reach_batch_workspace_bytes(20000)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    say("back-to-back batches on two streams")
+    for rep in range(3):
+        R.reach_embed_rk4_batch(rc.ctx, qa, ws, nb, s1)
+        R.reach_embed_rk4_batch(rc.ctx, qb, ws, nb, s2)
+    torch.cuda.synchronize()
+    assert rc.sync() == R.REACH_OK
+    got = [(to_host(X["r_lo"]), to_host(X["r_hi"])) for X in (A, B)]
+    for X, q in ((A, qa), (B, qb)):
+        X["r_lo"].fill_(np.nan)
+        X["r_hi"].fill_(np.nan)
+        R.reach_embed_rk4_each(rc.ctx, q, 8)
+    assert rc.sync() == R.REACH_OK
+    for (g_lo, g_hi), X in zip(got, (A, B)):
+        assert not np.isnan(g_lo).any()
+        assert np.array_equal(to_host(X["r_lo"]), g_lo)
+        assert np.array_equal(to_host(X["r_hi"]), g_hi)
 
 
 def test_batch_of_20000_reports_the_first_bad_query(rc):
