@@ -453,10 +453,11 @@ def query_mix(rc, R, torch, workloads, nq, cpu=True):
     return out
 
 
-def batch_only(rc, R, torch, workloads, nq, tune_first=False):
+def batch_only(rc, R, torch, workloads, nq, tune_first=False, back_to_back=0):
     """One offline batch of the query mix (the batch kernel alone, profiling;
     the last batch launch is the timed one), after the batch autotuner if
-    tune_first."""
+    tune_first; then, if back_to_back, 3 untimed and that many timed batches
+    issued without waiting in between (those launches come last)."""
     p4 = workloads.serve_mix_f64()
     qs = workloads.query_stream(nq, p4.extra["rate"], seed=p4.seed)
     ns = np.array([q.problem.n for q in qs])
@@ -489,8 +490,23 @@ def batch_only(rc, R, torch, workloads, nq, tune_first=False):
     torch.cuda.synchronize()
     tb = time.perf_counter() - t
     assert rc.sync() == R.REACH_OK
-    return {"workload": f"{nq} queries of the mix, one batch", "seconds": round(tb, 4),
-            "queries_per_s": nq / tb, "autotune": tune}
+    out = {"workload": f"{nq} queries of the mix, one batch", "seconds": round(tb, 4),
+           "queries_per_s": nq / tb, "autotune": tune}
+    if back_to_back:
+        ref = r_lo.cpu().numpy()
+        for _ in range(3):
+            R.reach_embed_rk4_batch(rc.ctx, dq, wsb, nbw, None)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(back_to_back):
+            R.reach_embed_rk4_batch(rc.ctx, dq, wsb, nbw, None)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t) / back_to_back
+        assert rc.sync() == R.REACH_OK
+        assert np.array_equal(r_lo.cpu().numpy(), ref)
+        out["back_to_back"] = {"batches": back_to_back, "seconds_per_batch": round(el, 5),
+                               "queries_per_s": nq / el}
+    return out
 
 
 def oracle_queries(qs, h_lo, h_hi, offs, u_lo, u_hi, k):
@@ -864,6 +880,8 @@ def main():
                     help="option batch.E for --only batch (largest cells per lane of a pack)")
     ap.add_argument("--batch-waves", type=int, default=0,
                     help="option batch.waves for --only batch (resident waves)")
+    ap.add_argument("--batch-back-to-back", type=int, default=0, metavar="K",
+                    help="--only batch: then 3 untimed and K timed batches issued back to back")
     ap.add_argument("--stream-probe", action="store_true",
                     help="time the HBM stream probe over its shapes and print it (only)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -904,7 +922,8 @@ def main():
             rc.set_option("batch.waves", args.batch_waves)
             out = batch_only(rc, R, torch, workloads, args.queries,
                              tune_first=not (args.batch_pack or args.batch_E or args.batch_waves
-                                             or args.no_tune))
+                                             or args.no_tune),
+                             back_to_back=args.batch_back_to_back)
         print(json.dumps(out), flush=True)
         rc.close()
         return
