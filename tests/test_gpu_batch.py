@@ -267,9 +267,10 @@ def test_batch_of_20000_queries_equals_one_launch_per_query(rc):
 
 def test_back_to_back_batches_on_two_streams_share_a_workspace(rc):
     """Batches issued without waiting, alternately on two streams with one
-    workspace: a call plans while the previous batch's kernel runs, and its
-    uploads wait on the device for that kernel, so every box equals the
-    query's own launch bit for bit."""
+    workspace, then on one stream: a call plans while the previous batch's
+    kernel runs, its uploads wait on the device for the kernel that used their
+    workspace block, and its kernel for the previous kernel, so every box
+    equals the query's own launch bit for bit."""
     A = packed_ctm_batch(20000, 11)
     B = packed_ctm_batch(20000, 12)
     qa = R.query_array([A["q"](i) for i in range(20000)])
@@ -277,10 +278,13 @@ def test_back_to_back_batches_on_two_streams_share_a_workspace(rc):
     nb = R.reach_batch_workspace_bytes(20000)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
-    say("back-to-back batches on two streams")
+    say("back-to-back batches on two streams, then on one")
     for rep in range(3):
         R.reach_embed_rk4_batch(rc.ctx, qa, ws, nb, s1)
         R.reach_embed_rk4_batch(rc.ctx, qb, ws, nb, s2)
+    for rep in range(3):
+        R.reach_embed_rk4_batch(rc.ctx, qb, ws, nb, s1)
+        R.reach_embed_rk4_batch(rc.ctx, qa, ws, nb, s1)
     torch.cuda.synchronize()
     assert rc.sync() == R.REACH_OK
     got = [(to_host(X["r_lo"]), to_host(X["r_hi"])) for X in (A, B)]
