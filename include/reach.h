@@ -198,8 +198,10 @@ reach_status reach_plan_embed(reach_ctx* ctx, const reach_system* sys, reach_dty
 /* Autotuner for reach_embed_rk4: times every built tile shape (E cells per
    lane) and steps-per-pass K on the caller's own buffers (trial_steps RK4
    steps per trial, one warm-up and two timed calls, HIP events on `stream`),
-   and records the fastest for this system kind, dtype and power-of-two size
-   bucket of n in the context; later calls of that bucket use it.  Arguments
+   re-times the four fastest and the built-in default over ten times the
+   steps, and records the fastest (the default unless a shape beats it by
+   more than 1%) for this system kind, dtype and power-of-two size bucket of
+   n in the context; later calls of that bucket use it.  Arguments
    are those of reach_embed_rk4 (r_lo / r_hi receive scratch results).
    best[0] = E, best[1] = K, best[2] = femtoseconds per state-step (2n per
    step), best[3] = S (sides per wavefront).  `best` is a host array of 4.
