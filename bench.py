@@ -348,8 +348,17 @@ def query_mix(rc, R, torch, workloads, nq, cpu=True):
                     "profiled_gpu_clock_ghz": profile_value(
                         "pack_kernel_mix1e5_f64_pmc.txt", "gpu_clock_ghz_in_this_run",
                         BATCH_SOURCES),
-                    "back_to_back": {"batches": 10, "seconds_per_batch": round(t_b2b, 5),
-                                     "queries_per_s": nq / t_b2b}}
+                    "back_to_back": {
+                        "batches": 10, "seconds_per_batch": round(t_b2b, 5),
+                        "queries_per_s": nq / t_b2b,
+                        # the kernel when batches follow each other (committed
+                        # summary on the current batch sources)
+                        "profiled_kernel_us": profile_value(
+                            "pack_kernel_mix1e5_f64_back_to_back.txt",
+                            "back_to_back_launch_us_mean", BATCH_SOURCES),
+                        "profiled_gpu_clock_ghz": profile_value(
+                            "pack_kernel_mix1e5_f64_back_to_back.txt", "pmc_gpu_clock_ghz_mean",
+                            BATCH_SOURCES)}}
     out["one_launch_per_query"] = {"queries_per_s": nq / te, "seconds": round(te, 4)}
     out["batch_speedup"] = round(te / tb, 2)
     out["batch_equals_per_query"] = same
