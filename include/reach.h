@@ -199,8 +199,8 @@ reach_status reach_plan_embed(reach_ctx* ctx, const reach_system* sys, reach_dty
    lane) and steps-per-pass K on the caller's own buffers (trial_steps RK4
    steps per trial, one warm-up and two timed calls, HIP events on `stream`),
    re-times the four fastest and the built-in default over ten times the
-   steps, and records the fastest (the default unless a shape beats it by
-   more than 1%) for this system kind, dtype and power-of-two size bucket of
+   steps (three rounds, each shape once per round), and records the fastest
+   (the default unless a shape beats it by more than 2%) for this system kind, dtype and power-of-two size bucket of
    n in the context; later calls of that bucket use it.  Arguments
    are those of reach_embed_rk4 (r_lo / r_hi receive scratch results).
    best[0] = E, best[1] = K, best[2] = femtoseconds per state-step (2n per
