@@ -353,7 +353,8 @@ int64_t reach_mc_samples(int64_t n, double eps, double delta);
  * and work items, used by turns.  The query descriptors are copied into this
  * call's block on the context's own copy stream as soon as the host has
  * written them, while it forms the work items, which follow; the upload waits
- * only for the kernel that read the block two batches before.  The counter
+ * for the kernel that read the block two batches before (and for the previous
+ * batch's kernel when the workspace or nq differs from the previous call's).  The counter
  * reset and the worker kernel (replayed from a captured hipGraph when the
  * same nq capacity, block and stream repeat) run on `stream` after the upload
  * and after the context's previous batch kernel, on whichever stream that ran.

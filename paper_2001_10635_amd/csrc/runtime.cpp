@@ -174,6 +174,8 @@ struct reach_ctx {
     bool batch_ev_recorded = false;
     bool block_ev_recorded[2] = {false, false};
     int next_block = 0;                  // workspace block of the next batch
+    void* last_ws = nullptr;             // workspace and query count of the last batch
+    int64_t last_nq = 0;
     hipStream_t copy_stream = nullptr;   // batch uploads, beside the previous batch's kernel
     std::map<GraphKey, hipGraphExec_t> graphs;
     std::vector<hipStream_t> each_streams;
@@ -1861,6 +1863,10 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
                                       (size_t)blk * align256(batch_block_bytes(nq)), nq);
     hipStream_t cs = c->copy_stream;
     if (c->block_ev_recorded[blk]) HIPCHK(c, hipStreamWaitEvent(cs, c->block_ev[blk], 0));
+    // another workspace or query count moves the blocks, which may then
+    // overlap what the previous batch's kernel still uses: wait for it too
+    if (c->batch_ev_recorded && (ws != c->last_ws || nq != c->last_nq))
+        HIPCHK(c, hipStreamWaitEvent(cs, c->batch_ev, 0));
     const auto t_start = std::chrono::steady_clock::now();
     std::vector<uint32_t> members;
     std::vector<BatchItem> items;
@@ -1946,6 +1952,8 @@ reach_status reach_embed_rk4_batch(reach_ctx* c, const reach_query* q, int64_t n
     c->batch_ev_recorded = true;
     c->block_ev_recorded[blk] = true;
     c->next_block = 1 - blk;
+    c->last_ws = ws;
+    c->last_nq = nq;
     (void)counter;
     return REACH_OK;
 }

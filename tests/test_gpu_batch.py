@@ -267,10 +267,11 @@ def test_batch_of_20000_queries_equals_one_launch_per_query(rc):
 
 def test_back_to_back_batches_on_two_streams_share_a_workspace(rc):
     """Batches issued without waiting, alternately on two streams with one
-    workspace, then on one stream: a call plans while the previous batch's
-    kernel runs, its uploads wait on the device for the kernel that used their
-    workspace block, and its kernel for the previous kernel, so every box
-    equals the query's own launch bit for bit."""
+    workspace, then on one stream, then with a smaller batch between: a call
+    plans while the previous batch's kernel runs, its uploads wait on the
+    device for the kernel that used their workspace block (and for the
+    previous kernel when the block layout moves), and its kernel for the
+    previous kernel, so every box equals the query's own launch bit for bit."""
     A = packed_ctm_batch(20000, 11)
     B = packed_ctm_batch(20000, 12)
     qa = R.query_array([A["q"](i) for i in range(20000)])
@@ -285,6 +286,12 @@ def test_back_to_back_batches_on_two_streams_share_a_workspace(rc):
     for rep in range(3):
         R.reach_embed_rk4_batch(rc.ctx, qb, ws, nb, s1)
         R.reach_embed_rk4_batch(rc.ctx, qa, ws, nb, s1)
+    # a smaller batch (B's first 7000 queries) in the same workspace moves the
+    # blocks: its uploads also wait for the batch before it
+    qc = R.query_array([B["q"](i) for i in range(7000)])
+    for rep in range(3):
+        R.reach_embed_rk4_batch(rc.ctx, qc, ws, nb, s1)
+        R.reach_embed_rk4_batch(rc.ctx, qa, ws, nb, s2)
     torch.cuda.synchronize()
     assert rc.sync() == R.REACH_OK
     got = [(to_host(X["r_lo"]), to_host(X["r_hi"])) for X in (A, B)]
